@@ -1,0 +1,175 @@
+/*
+ * ozc - complex matrix multiplication emulated on INT8 matrix cores by the
+ * Ozaki-II scheme (Chinese-remainder reconstruction), for AMD MI355X (gfx950).
+ *
+ * Method: Uchino, Ma, Imamura, Ozaki, Gutsche, "Emulation of Complex Matrix
+ * Multiplication based on the Chinese Remainder Theorem" (arXiv 2512.08321).
+ * The operation is the BLAS zgemm / cgemm one,
+ *
+ *     C := alpha * op(A) * op(B) + beta * C,
+ *
+ * with op(A) m x k, op(B) k x n, C m x n, all column-major with interleaved
+ * (re, im) complex elements.  The paper states the product C = AB for
+ * A in C^{m x k}, B in C^{k x n} (Section III); alpha, beta and op() are the
+ * BLAS calling convention of the routines the paper's library replaces
+ * (Section III-D).
+ *
+ * Pipeline (Algorithm 1, Section III):
+ *   1. per-row / per-column power-of-two scaling exponents mu_i, nu_j, shared
+ *      by the real and imaginary parts (Section III-B), fast mode (Cauchy-
+ *      Schwarz bound) or accurate mode (bound from an extra INT8 product);
+ *   2. truncation a' = trunc(a 2^mu) and symmetric INT8 residues modulo N
+ *      pairwise-coprime moduli p_l <= 256 (Algorithm 1 Steps I, IV, V-i/ii);
+ *   3. per modulus, the complex INT8 product with INT32 accumulation, either
+ *      Karatsuba with 3 products (equation (10)) or the expanded form with 4
+ *      products (equation (7)), reduced to INT8 residues E'_l (Step V-iii/iv);
+ *   4. C' = mod(sum_l (P/p_l) q_l E'_l, P) (Step V-v/vi), reconstructed
+ *      exactly in integer arithmetic, rounded to nearest-even, then
+ *      C = ldexp(C', -(mu_i + nu_j)) (Step VI) and alpha/beta.
+ * The uniqueness condition 2 sum_h |a'_ih| |b'_hj| < P (equation (4)) holds by
+ * construction of the exponents, so C' equals the exact integer product of
+ * the truncated inputs.
+ *
+ * Every call is asynchronous on the handle's stream: it enqueues HIP kernels
+ * and returns; no host synchronisation happens inside ozc_zgemm/ozc_cgemm.
+ * A handle is not thread safe: use one handle per host thread.
+ * All matrix pointers are device pointers; alpha/beta are host pointers.
+ * No function aborts: every error is reported through the returned status.
+ */
+#ifndef OZC_H
+#define OZC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ozc_context *ozc_handle_t;
+
+typedef enum {
+    OZC_STATUS_SUCCESS = 0,
+    OZC_STATUS_INVALID_VALUE = 1,   /* an argument is out of range (BLAS-style checks)   */
+    OZC_STATUS_NOT_SUPPORTED = 2,   /* e.g. k above OZC_MAX_K                              */
+    OZC_STATUS_ALLOC_FAILED = 3,    /* device allocation of the workspace failed          */
+    OZC_STATUS_HIP_ERROR = 4,       /* a HIP runtime call or kernel launch failed          */
+    OZC_STATUS_NONFINITE = 5,       /* reported by ozc_last_info: an input was inf or NaN  */
+    OZC_STATUS_INVALID_HANDLE = 6
+} ozc_status_t;
+
+typedef enum { OZC_OP_N = 0, OZC_OP_T = 1, OZC_OP_C = 2 } ozc_op_t;
+
+/* Scaling-vector rule (Section III-B). */
+typedef enum { OZC_MODE_FAST = 0, OZC_MODE_ACCURATE = 1 } ozc_mode_t;
+
+/* Complex INT8 product per modulus (Section III-A): Karatsuba (eq. (10), 3
+ * products, 6mnk INT8 operations) or the expanded real form (eq. (7), 4
+ * products, 8mnk operations).  Both give bit-identical results. */
+typedef enum { OZC_ALGO_KARATSUBA = 0, OZC_ALGO_4M = 1 } ozc_algo_t;
+
+#define OZC_MIN_MODULI 2
+#define OZC_MAX_MODULI 24
+/* INT8 products accumulate exactly in INT32 while k <= 2^17 (Section II). */
+#define OZC_MAX_K 131072
+
+/* Exponent sentinels reported by ozc_inspect for rows/columns without scaling. */
+#define OZC_EXP_ZERO ((int16_t)-32768)    /* all-zero row (or vanishing accurate bound) */
+#define OZC_EXP_NONFINITE ((int16_t)32767) /* the row/column holds an inf or NaN        */
+
+/* Create a handle bound to HIP device `device` (made current for the call).
+ * The handle owns its moduli tables and, unless ozc_set_workspace is used, a
+ * device workspace that grows on demand.  Stream: the null stream until
+ * ozc_set_stream.  Errors: INVALID_VALUE (handle NULL / bad device),
+ * HIP_ERROR, ALLOC_FAILED. */
+ozc_status_t ozc_create(ozc_handle_t *handle, int device);
+
+/* Free the handle and the workspace it owns (synchronises its stream first). */
+ozc_status_t ozc_destroy(ozc_handle_t handle);
+
+/* Stream (a hipStream_t, passed as void*) on which later calls enqueue work. */
+ozc_status_t ozc_set_stream(ozc_handle_t handle, void *stream);
+
+/* Number of moduli N in [OZC_MIN_MODULI, OZC_MAX_MODULI] (Algorithm 1 input
+ * N; moduli are the first N of 256, 255, 253, 251, 247, 241, ... , the
+ * greedy descending pairwise-coprime integers <= 256), scaling mode and
+ * product algorithm for the following calls.  Default: N = 14, fast,
+ * Karatsuba.  Errors: INVALID_VALUE. */
+ozc_status_t ozc_set_config(ozc_handle_t handle, int num_moduli, ozc_mode_t mode,
+                            ozc_algo_t algo);
+
+/* Device workspace in bytes that ozc_zgemm/ozc_cgemm need for this shape
+ * under the current configuration (element size does not matter). */
+ozc_status_t ozc_workspace_size(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb,
+                                int64_t m, int64_t n, int64_t k, size_t *bytes);
+
+/* Use caller-owned device memory as workspace (ptr == NULL returns to the
+ * handle's own growing workspace).  The caller keeps ownership and must keep
+ * it alive while calls using it are in flight.  A later call whose shape
+ * needs more than `bytes` fails with ALLOC_FAILED. */
+ozc_status_t ozc_set_workspace(ozc_handle_t handle, void *ptr, size_t bytes);
+
+/* C := alpha op(A) op(B) + beta C, complex128 (double2) elements.
+ * A: lda >= max(1, m) if transa == N, else >= max(1, k); B: ldb >= max(1, k)
+ * if transb == N, else >= max(1, n); ldc >= max(1, m).  m, n, k >= 0,
+ * k <= OZC_MAX_K (else NOT_SUPPORTED).  m == 0 or n == 0: no work.
+ * alpha == 0 or k == 0: C := beta C without reading A or B.  beta == 0: C
+ * is not read.  Rows of op(A) / columns of op(B) holding inf or NaN give NaN
+ * output entries and set the status that ozc_last_info reports.
+ * Result (alpha = 1, beta = 0): out_ij = ldexp(RNE(C'_ij), -(mu_i + nu_j)),
+ * with C' the exact integer reconstruction.  General alpha/beta, in this
+ * order: x_r = fma(a_r, c_r, -(a_i c_i)); x_i = fma(a_r, c_i, a_i c_r);
+ * beta == 0: out = x; else out_r = fma(b_r, C_r, fma(-b_i, C_i, x_r)),
+ * out_i = fma(b_r, C_i, fma(b_i, C_r, x_i)). */
+ozc_status_t ozc_zgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, int64_t m,
+                       int64_t n, int64_t k, const double alpha[2], const void *A,
+                       int64_t lda, const void *B, int64_t ldb, const double beta[2],
+                       void *C, int64_t ldc);
+
+/* As ozc_zgemm for complex64 (float2) elements: inputs are promoted exactly
+ * to double, the result above is computed in double with alpha/beta
+ * promoted, and rounded once more to float (round to nearest even). */
+ozc_status_t ozc_cgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, int64_t m,
+                       int64_t n, int64_t k, const float alpha[2], const void *A,
+                       int64_t lda, const void *B, int64_t ldb, const float beta[2],
+                       void *C, int64_t ldc);
+
+/* Intermediates of the pipeline for alpha = 1, beta = 0, for verification.
+ * `single` = 0: complex128 inputs, 1: complex64.  Output buffers are device
+ * memory owned by the caller; any of them may be NULL.  Layouts (dense):
+ *   mu     int16[m]   nu int16[n]   (exponents or the OZC_EXP_* sentinels)
+ *   resA   int8[N][planes][m][k]    residues of the rows of op(A)
+ *   resB   int8[N][planes][n][k]    residues of the columns of op(B)
+ *          planes: Karatsuba 3 (re, im, re+im reduced), 4M 2 (re, im)
+ *   prods  int32[N][nprod][n][m]    raw INT32 products per modulus, each
+ *          plane column-major: Karatsuba (D, E, F) = (RR, II, SS); 4M (RR, II, RI, IR)
+ *   eprime int8[N][2][n][m]         E'_R, E'_I per modulus, column-major
+ *   C      m x n output (ldc) as ozc_zgemm/ozc_cgemm would write it.
+ * Same validity rules and errors as ozc_zgemm. */
+ozc_status_t ozc_inspect(ozc_handle_t handle, int single, ozc_op_t transa, ozc_op_t transb,
+                         int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                         const void *B, int64_t ldb, int16_t *mu, int16_t *nu, int8_t *resA,
+                         int8_t *resB, int32_t *prods, int8_t *eprime, void *C, int64_t ldc);
+
+typedef struct {
+    int num_moduli;      /* N used by the last call                                  */
+    int mode;            /* ozc_mode_t                                               */
+    int algo;            /* ozc_algo_t                                               */
+    int nonfinite;       /* 1 if the last call met an inf/NaN input                  */
+    int64_t m, n, k;     /* shape of the last call                                   */
+    size_t workspace;    /* bytes of workspace the last call used                    */
+    double int8_ops;     /* INT8 MFMA operations of the residue products (2 per MAC)  */
+} ozc_info_t;
+
+/* Synchronises the handle's stream and reports on the last call.  Returns
+ * NONFINITE when the last call met inf/NaN input (info still filled). */
+ozc_status_t ozc_last_info(ozc_handle_t handle, ozc_info_t *info);
+
+/* Static text for a status code. */
+const char *ozc_status_string(ozc_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZC_H */

@@ -1,0 +1,207 @@
+"""Ozaki-II emulation of complex GEMM on MI355X INT8 matrix cores.
+
+Thin ctypes binding of ``libozc.so`` (C-ABI declared in ``include/ozc.h``):
+argument marshalling only; every step of the computation runs in the HIP
+kernels of the library.  PyTorch is used for device memory and streams.
+
+Low level: ``Handle`` mirrors the C functions (``ozc_zgemm``, ``ozc_cgemm``,
+``ozc_inspect``, ...) on raw device pointers.  High level: ``gemm(A, B, ...)``
+takes torch tensors.
+
+The library must have been built (``python -m paper_2512_08321_amd.build``
+or ``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Handle", "OzcError", "gemm", "lib", "OP", "MODE", "ALGO", "MAX_K", "MIN_MODULI",
+           "MAX_MODULI", "EXP_ZERO", "EXP_NONFINITE", "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libozc.so")
+
+OP = {"N": 0, "T": 1, "C": 2}
+MODE = {"fast": 0, "accurate": 1}
+ALGO = {"karatsuba": 0, "4m": 1}
+MAX_K = 131072
+MIN_MODULI, MAX_MODULI = 2, 24
+EXP_ZERO, EXP_NONFINITE = -32768, 32767
+
+STATUS = {0: "success", 1: "invalid value", 2: "not supported", 3: "device allocation failed",
+          4: "HIP runtime error", 5: "non-finite input", 6: "invalid handle"}
+
+
+class OzcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("num_moduli", ctypes.c_int), ("mode", ctypes.c_int), ("algo", ctypes.c_int),
+                ("nonfinite", ctypes.c_int), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("workspace", ctypes.c_size_t), ("int8_ops", ctypes.c_double)]
+
+
+_lib = None
+_VP, _I64, _INT = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+_D2 = ctypes.c_double * 2
+_F2 = ctypes.c_float * 2
+
+EXPORTS = {
+    "ozc_create": [ctypes.POINTER(_VP), _INT],
+    "ozc_destroy": [_VP],
+    "ozc_set_stream": [_VP, _VP],
+    "ozc_set_config": [_VP, _INT, _INT, _INT],
+    "ozc_workspace_size": [_VP, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
+    "ozc_set_workspace": [_VP, _VP, ctypes.c_size_t],
+    "ozc_zgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _D2, _VP, _I64, _VP, _I64, _D2, _VP, _I64],
+    "ozc_cgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _F2, _VP, _I64, _VP, _I64, _F2, _VP, _I64],
+    "ozc_inspect": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _VP,
+                    _VP, _VP, _VP, _VP, _I64],
+    "ozc_last_info": [_VP, ctypes.POINTER(Info)],
+    "ozc_status_string": [_INT],
+}
+
+
+def lib():
+    """The loaded libozc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise ImportError(f"{library_path} is missing: build it with "
+                              "`python -m paper_2512_08321_amd.build`")
+        L = ctypes.CDLL(library_path)
+        for name, args in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "ozc_status_string" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise OzcError(status, where)
+
+
+def _ptr(x) -> int | None:
+    """Device pointer of a torch tensor (or an int / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+class Handle:
+    """One ozc handle bound to a device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0, num_moduli: int = 14, mode: str = "fast",
+                 algo: str = "karatsuba"):
+        self._h = _VP()
+        _check(lib().ozc_create(ctypes.byref(self._h), device), "ozc_create")
+        self.device = device
+        self.set_config(num_moduli, mode, algo)
+
+    def close(self):
+        if self._h:
+            lib().ozc_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_config(self, num_moduli: int, mode: str = "fast", algo: str = "karatsuba"):
+        _check(lib().ozc_set_config(self._h, int(num_moduli), MODE[mode], ALGO[algo]), "ozc_set_config")
+        self.num_moduli, self.mode, self.algo = int(num_moduli), mode, algo
+
+    def set_stream(self, stream: int | None = None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().ozc_set_stream(self._h, stream or None), "ozc_set_stream")
+
+    def workspace_size(self, transa, transb, m, n, k) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ozc_workspace_size(self._h, OP[transa], OP[transb], m, n, k, ctypes.byref(b)),
+               "ozc_workspace_size")
+        return b.value
+
+    def set_workspace(self, ptr, nbytes: int):
+        _check(lib().ozc_set_workspace(self._h, _ptr(ptr), int(nbytes)), "ozc_set_workspace")
+
+    def zgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+        self.set_stream(stream)
+        a, b = complex(alpha), complex(beta)
+        _check(lib().ozc_zgemm(self._h, OP[transa], OP[transb], m, n, k, _D2(a.real, a.imag),
+                               _ptr(A), lda, _ptr(B), ldb, _D2(b.real, b.imag), _ptr(C), ldc),
+               "ozc_zgemm")
+
+    def cgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+        self.set_stream(stream)
+        a, b = complex(alpha), complex(beta)
+        _check(lib().ozc_cgemm(self._h, OP[transa], OP[transb], m, n, k, _F2(a.real, a.imag),
+                               _ptr(A), lda, _ptr(B), ldb, _F2(b.real, b.imag), _ptr(C), ldc),
+               "ozc_cgemm")
+
+    def inspect(self, single, transa, transb, m, n, k, A, lda, B, ldb, mu=None, nu=None,
+                resA=None, resB=None, prods=None, eprime=None, C=None, ldc=1, stream=None):
+        self.set_stream(stream)
+        _check(lib().ozc_inspect(self._h, int(bool(single)), OP[transa], OP[transb], m, n, k,
+                                 _ptr(A), lda, _ptr(B), ldb, _ptr(mu), _ptr(nu), _ptr(resA),
+                                 _ptr(resB), _ptr(prods), _ptr(eprime), _ptr(C), ldc),
+               "ozc_inspect")
+
+    def last_info(self, raise_nonfinite: bool = False) -> dict:
+        info = Info()
+        st = lib().ozc_last_info(self._h, ctypes.byref(info))
+        if st not in (0, 5) or (st == 5 and raise_nonfinite):
+            _check(st, "ozc_last_info")
+        return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+_handles: dict = {}
+
+
+def default_handle(device: int = 0) -> Handle:
+    if device not in _handles:
+        _handles[device] = Handle(device)
+    return _handles[device]
+
+
+def gemm(A, B, C=None, alpha=1.0, beta=0.0, num_moduli: int = 14, mode: str = "fast",
+         algo: str = "karatsuba", handle: Handle | None = None):
+    """alpha * A @ B + beta * C for row-major complex torch tensors on the GPU.
+
+    complex128 -> ozc_zgemm, complex64 -> ozc_cgemm.  Row-major C = A B is
+    computed as the column-major product C^T = B^T A^T (no copies); the
+    scheme treats rows of A and columns of B symmetrically, so the result is
+    the same bit for bit.
+    """
+    import torch
+
+    if A.dtype != B.dtype or A.dtype not in (torch.complex128, torch.complex64):
+        raise TypeError("A and B must both be complex128 or complex64")
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("shape mismatch")
+    m, k = A.shape
+    n = B.shape[1]
+    A = A.contiguous()
+    B = B.contiguous()
+    if C is None:
+        C = torch.empty((m, n), dtype=A.dtype, device=A.device)
+        beta = 0.0
+    elif not C.is_contiguous() or C.shape != (m, n) or C.dtype != A.dtype:
+        raise ValueError("C must be a contiguous (m, n) tensor of the same dtype")
+    h = handle or default_handle(A.device.index or 0)
+    if (h.num_moduli, h.mode, h.algo) != (num_moduli, mode, algo):
+        h.set_config(num_moduli, mode, algo)
+    call = h.zgemm if A.dtype == torch.complex128 else h.cgemm
+    call("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C, max(1, n))
+    return C

@@ -1,0 +1,431 @@
+// C-ABI of the emulated complex GEMM (include/ozc.h): argument checks,
+// workspace layout and the order of kernel launches on the caller's stream.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/ozc.h"
+#include "internal.h"
+
+using namespace ozc;
+
+struct ozc_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int nmod = 14;
+    ozc_mode_t mode = OZC_MODE_FAST;
+    ozc_algo_t algo = OZC_ALGO_KARATSUBA;
+    void *ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    void *ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    NTable *tab_dev = nullptr;          // kMaxModuli tables, index N - 1
+    std::vector<NTable> tab_host;
+    uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
+    ozc_info_t last{};
+};
+
+namespace {
+
+constexpr int64_t kTileM = 128, kTileN = 128, kTileK = 64;
+constexpr size_t kAlign = 256;
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int64_t m_pad, n_pad, k_pad;
+    int planes, nprod;
+    size_t maxA, maxB, sigA, sigB, XA, YB, muA, nuB, barA, barB, resA, resB, ep, prods, total;
+};
+
+Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool with_prods) {
+    Layout L{};
+    L.m_pad = round_up(m > 0 ? m : 1, kTileM);
+    L.n_pad = round_up(n > 0 ? n : 1, kTileN);
+    L.k_pad = round_up(k > 0 ? k : 1, kTileK);
+    L.planes = h->algo == OZC_ALGO_KARATSUBA ? 3 : 2;
+    L.nprod = h->algo == OZC_ALGO_KARATSUBA ? 3 : 4;
+    const size_t N = (size_t)h->nmod;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.maxA = take(8 * (size_t)L.m_pad);
+    L.maxB = take(8 * (size_t)L.n_pad);
+    L.sigA = take(8 * (size_t)L.m_pad);
+    L.sigB = take(8 * (size_t)L.n_pad);
+    L.XA = take(4 * (size_t)L.m_pad);
+    L.YB = take(4 * (size_t)L.n_pad);
+    L.muA = take(2 * (size_t)L.m_pad);
+    L.nuB = take(2 * (size_t)L.n_pad);
+    const bool accu = h->mode == OZC_MODE_ACCURATE;
+    L.barA = take(accu ? 3 * (size_t)L.m_pad * L.k_pad : 0);
+    L.barB = take(accu ? 3 * (size_t)L.n_pad * L.k_pad : 0);
+    L.resA = take(N * L.planes * (size_t)L.m_pad * L.k_pad);
+    L.resB = take(N * L.planes * (size_t)L.n_pad * L.k_pad);
+    L.ep = take(N * 2 * (size_t)L.m_pad * L.n_pad);
+    L.prods = take(with_prods ? N * L.nprod * 4 * (size_t)L.m_pad * L.n_pad : 0);
+    L.total = off;
+    return L;
+}
+
+#define OZC_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return OZC_STATUS_HIP_ERROR; \
+    } while (0)
+
+ozc_status_t ensure_workspace(ozc_context *h, size_t bytes, char **ws) {
+    if (h->ws_user) {
+        if (bytes > h->ws_user_bytes) return OZC_STATUS_ALLOC_FAILED;
+        *ws = (char *)h->ws_user;
+        return OZC_STATUS_SUCCESS;
+    }
+    if (bytes > h->ws_own_bytes) {
+        if (h->ws_own) {
+            OZC_TRY(hipStreamSynchronize(h->stream));
+            OZC_TRY(hipFree(h->ws_own));
+            h->ws_own = nullptr;
+            h->ws_own_bytes = 0;
+        }
+        if (hipMalloc(&h->ws_own, bytes) != hipSuccess) {
+            h->ws_own = nullptr;
+            (void)hipGetLastError();
+            return OZC_STATUS_ALLOC_FAILED;
+        }
+        h->ws_own_bytes = bytes;
+    }
+    *ws = (char *)h->ws_own;
+    return OZC_STATUS_SUCCESS;
+}
+
+OperandView view_A(const void *A, ozc_op_t ta, int64_t m, int64_t k, int64_t lda) {
+    OperandView v{};
+    v.base = A;
+    v.rows = m;
+    v.k = k;
+    if (ta == OZC_OP_N) {  // op(A)[i][h] = A[i + h lda]
+        v.stride_r = 1;
+        v.stride_h = lda;
+        v.contig_h = 0;
+    } else {               // op(A)[i][h] = A[h + i lda] (conjugated for C)
+        v.stride_r = lda;
+        v.stride_h = 1;
+        v.contig_h = 1;
+    }
+    v.conj = ta == OZC_OP_C;
+    return v;
+}
+
+OperandView view_B(const void *B, ozc_op_t tb, int64_t n, int64_t k, int64_t ldb) {
+    OperandView v{};
+    v.base = B;
+    v.rows = n;  // rows of the view = columns of op(B)
+    v.k = k;
+    if (tb == OZC_OP_N) {  // op(B)[h][j] = B[h + j ldb]
+        v.stride_r = ldb;
+        v.stride_h = 1;
+        v.contig_h = 1;
+    } else {               // op(B)[h][j] = B[j + h ldb]
+        v.stride_r = 1;
+        v.stride_h = ldb;
+        v.contig_h = 0;
+    }
+    v.conj = tb == OZC_OP_C;
+    return v;
+}
+
+bool valid_op(ozc_op_t t) { return t == OZC_OP_N || t == OZC_OP_T || t == OZC_OP_C; }
+
+ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k, const void *A,
+                        int64_t lda, const void *B, int64_t ldb, const void *C, int64_t ldc,
+                        bool c_optional) {
+    if (!valid_op(ta) || !valid_op(tb)) return OZC_STATUS_INVALID_VALUE;
+    if (m < 0 || n < 0 || k < 0) return OZC_STATUS_INVALID_VALUE;
+    const int64_t rowsA = ta == OZC_OP_N ? m : k;
+    const int64_t rowsB = tb == OZC_OP_N ? k : n;
+    if (lda < (rowsA > 1 ? rowsA : 1)) return OZC_STATUS_INVALID_VALUE;
+    if (ldb < (rowsB > 1 ? rowsB : 1)) return OZC_STATUS_INVALID_VALUE;
+    if (ldc < (m > 1 ? m : 1)) return OZC_STATUS_INVALID_VALUE;
+    if (m > 0 && n > 0 && C == nullptr && !c_optional) return OZC_STATUS_INVALID_VALUE;
+    if (m > 0 && n > 0 && k > 0 && (A == nullptr || B == nullptr)) return OZC_STATUS_INVALID_VALUE;
+    if (k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
+    if (m > ((int64_t)1 << 31) || n > ((int64_t)1 << 31)) return OZC_STATUS_NOT_SUPPORTED;
+    return OZC_STATUS_SUCCESS;
+}
+
+struct InspectOut {
+    int16_t *mu, *nu;
+    int8_t *resA, *resB;
+    int32_t *prods;
+    int8_t *eprime;
+};
+
+ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
+                 int64_t k, const double alpha[2], const void *A, int64_t lda, const void *B,
+                 int64_t ldb, const double beta[2], void *C, int64_t ldc, const InspectOut *ins) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, ins != nullptr);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    hipStream_t s = h->stream;
+    OZC_TRY(hipSetDevice(h->device));
+    h->last = ozc_info_t{};
+    h->last.num_moduli = h->nmod;
+    h->last.mode = h->mode;
+    h->last.algo = h->algo;
+    h->last.m = m;
+    h->last.n = n;
+    h->last.k = k;
+    OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
+    if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
+    const bool alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0;
+    if ((alpha_zero || k == 0) && ins == nullptr) {
+        OZC_TRY(launch_scale_c(C, m, n, ldc, single, alpha[0], alpha[1], beta[0], beta[1], s));
+        return OZC_STATUS_SUCCESS;
+    }
+    if (k == 0) return OZC_STATUS_INVALID_VALUE;  // nothing to inspect
+
+    const Layout L = make_layout(h, m, n, k, ins && ins->prods);
+    char *ws = nullptr;
+    st = ensure_workspace(h, L.total, &ws);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    h->last.workspace = L.total;
+    h->last.int8_ops = 2.0 * (double)L.nprod * (double)h->nmod * (double)m * (double)n * (double)k;
+
+    const NTable *tab = h->tab_dev + (h->nmod - 1);
+    const NTable &th = h->tab_host[(size_t)h->nmod - 1];
+    uint64_t *maxA = (uint64_t *)(ws + L.maxA), *maxB = (uint64_t *)(ws + L.maxB);
+    uint64_t *sigA = (uint64_t *)(ws + L.sigA), *sigB = (uint64_t *)(ws + L.sigB);
+    int32_t *XA = (int32_t *)(ws + L.XA), *YB = (int32_t *)(ws + L.YB);
+    int16_t *muA = (int16_t *)(ws + L.muA), *nuB = (int16_t *)(ws + L.nuB);
+    int8_t *resA = (int8_t *)(ws + L.resA), *resB = (int8_t *)(ws + L.resB);
+    int8_t *ep = (int8_t *)(ws + L.ep);
+    int32_t *prods = ins && ins->prods ? (int32_t *)(ws + L.prods) : nullptr;
+    uint32_t *status = (uint32_t *)h->status_dev;
+
+    const OperandView vA = view_A(A, ta, m, k, lda);
+    const OperandView vB = view_B(B, tb, n, k, ldb);
+
+    // Step III: scaling exponents
+    OZC_TRY(launch_fill_u64(maxA, L.m_pad, 0, s));
+    OZC_TRY(launch_fill_u64(maxB, L.n_pad, 0, s));
+    OZC_TRY(launch_row_maxabs(vA, single, maxA, s));
+    OZC_TRY(launch_row_maxabs(vB, single, maxB, s));
+    int abits;
+    if (h->mode == OZC_MODE_FAST) {
+        OZC_TRY(launch_fill_u64(sigA, L.m_pad, 0, s));
+        OZC_TRY(launch_fill_u64(sigB, L.n_pad, 0, s));
+        OZC_TRY(launch_row_sigma(vA, single, maxA, sigA, s));
+        OZC_TRY(launch_row_sigma(vB, single, maxB, sigB, s));
+        OZC_TRY(launch_fast_exponents(maxA, sigA, m, L.m_pad, tab, muA, status, s));
+        OZC_TRY(launch_fast_exponents(maxB, sigB, n, L.n_pad, tab, nuB, status, s));
+        abits = th.max_abits_fast;
+    } else {
+        int8_t *barA = (int8_t *)(ws + L.barA), *barB = (int8_t *)(ws + L.barB);
+        OZC_TRY(launch_fill_u64((uint64_t *)XA, L.m_pad / 2, 0, s));
+        OZC_TRY(launch_fill_u64((uint64_t *)YB, L.n_pad / 2, 0, s));
+        OZC_TRY(launch_ceil7(vA, single, maxA, barA, L.m_pad, L.k_pad, s));
+        OZC_TRY(launch_ceil7(vB, single, maxB, barB, L.n_pad, L.k_pad, s));
+        BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB};
+        OZC_TRY(launch_bound_gemm(ba, s));
+        OZC_TRY(launch_accu_exponents(maxA, XA, m, L.m_pad, tab, muA, status, s));
+        OZC_TRY(launch_accu_exponents(maxB, YB, n, L.n_pad, tab, nuB, status, s));
+        abits = th.max_abits_accu;
+    }
+    int nchunks = (abits + kChunkBits - 1) / kChunkBits;
+    if (nchunks < 1) nchunks = 1;
+    if (nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
+
+    // Steps IV, V-i/ii: truncation and residues
+    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, nchunks, resA, L.m_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, nchunks, resB, L.n_pad, L.k_pad, s));
+
+    // Step V-iii/iv: INT8 products and their residues
+    GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, h->algo == OZC_ALGO_KARATSUBA ? 0 : 1,
+                tab, ep, prods};
+    OZC_TRY(launch_residue_gemm(ga, s));
+
+    // Steps V-v, V-vi, VI
+    if (C) {
+        CrtArgs ca{};
+        ca.eprime = ep;
+        ca.m = m;
+        ca.n = n;
+        ca.m_pad = L.m_pad;
+        ca.n_pad = L.n_pad;
+        ca.nmod = h->nmod;
+        ca.nlimbs = th.nlimbs;
+        ca.tab = tab;
+        ca.mu = muA;
+        ca.nu = nuB;
+        ca.alpha_r = alpha[0];
+        ca.alpha_i = alpha[1];
+        ca.beta_r = beta[0];
+        ca.beta_i = beta[1];
+        ca.C = C;
+        ca.ldc = ldc;
+        ca.single = single;
+        OZC_TRY(launch_crt_output(ca, s));
+    }
+
+    if (ins) {
+        if (ins->mu) OZC_TRY(hipMemcpyAsync(ins->mu, muA, 2 * (size_t)m, hipMemcpyDeviceToDevice, s));
+        if (ins->nu) OZC_TRY(hipMemcpyAsync(ins->nu, nuB, 2 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        const int64_t N = h->nmod;
+        // dense copies of padded planes: plane q of `count` planes, `rows` x `width` bytes
+        auto planes = [&](void *dst, const void *src, size_t width, size_t src_pitch, int64_t rows,
+                          int64_t src_rows, int64_t count) -> hipError_t {
+            for (int64_t q = 0; q < count; ++q) {
+                hipError_t e = hipMemcpy2DAsync((char *)dst + (size_t)q * rows * width, width,
+                                                (const char *)src + (size_t)q * src_rows * src_pitch,
+                                                src_pitch, width, (size_t)rows,
+                                                hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        if (ins->resA) OZC_TRY(planes(ins->resA, resA, (size_t)k, (size_t)L.k_pad, m, L.m_pad, N * L.planes));
+        if (ins->resB) OZC_TRY(planes(ins->resB, resB, (size_t)k, (size_t)L.k_pad, n, L.n_pad, N * L.planes));
+        if (ins->eprime) OZC_TRY(planes(ins->eprime, ep, (size_t)m, (size_t)L.m_pad, n, L.n_pad, N * 2));
+        if (ins->prods)
+            OZC_TRY(planes(ins->prods, prods, 4 * (size_t)m, 4 * (size_t)L.m_pad, n, L.n_pad, N * L.nprod));
+    }
+    return OZC_STATUS_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ozc_status_string(ozc_status_t s) {
+    switch (s) {
+        case OZC_STATUS_SUCCESS: return "success";
+        case OZC_STATUS_INVALID_VALUE: return "invalid value";
+        case OZC_STATUS_NOT_SUPPORTED: return "not supported";
+        case OZC_STATUS_ALLOC_FAILED: return "device allocation failed";
+        case OZC_STATUS_HIP_ERROR: return "HIP runtime error";
+        case OZC_STATUS_NONFINITE: return "non-finite input";
+        case OZC_STATUS_INVALID_HANDLE: return "invalid handle";
+    }
+    return "unknown status";
+}
+
+ozc_status_t ozc_create(ozc_handle_t *handle, int device) {
+    if (!handle) return OZC_STATUS_INVALID_VALUE;
+    *handle = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return OZC_STATUS_INVALID_VALUE;
+    if (hipSetDevice(device) != hipSuccess) return OZC_STATUS_HIP_ERROR;
+    ozc_context *h = new (std::nothrow) ozc_context();
+    if (!h) return OZC_STATUS_ALLOC_FAILED;
+    h->device = device;
+    h->tab_host.resize(kMaxModuli);
+    build_tables(h->tab_host.data());
+    if (hipMalloc(&h->tab_dev, sizeof(NTable) * kMaxModuli) != hipSuccess ||
+        hipMalloc(&h->status_dev, 256) != hipSuccess) {
+        if (h->tab_dev) (void)hipFree(h->tab_dev);
+        delete h;
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    if (hipMemcpy(h->tab_dev, h->tab_host.data(), sizeof(NTable) * kMaxModuli,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->status_dev, 0, 256) != hipSuccess) {
+        (void)hipFree(h->tab_dev);
+        (void)hipFree(h->status_dev);
+        delete h;
+        return OZC_STATUS_HIP_ERROR;
+    }
+    *handle = h;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_destroy(ozc_handle_t h) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws_own) (void)hipFree(h->ws_own);
+    (void)hipFree(h->tab_dev);
+    (void)hipFree(h->status_dev);
+    delete h;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_set_stream(ozc_handle_t h, void *stream) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    h->stream = (hipStream_t)stream;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_set_config(ozc_handle_t h, int num_moduli, ozc_mode_t mode, ozc_algo_t algo) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (num_moduli < OZC_MIN_MODULI || num_moduli > OZC_MAX_MODULI) return OZC_STATUS_INVALID_VALUE;
+    if (mode != OZC_MODE_FAST && mode != OZC_MODE_ACCURATE) return OZC_STATUS_INVALID_VALUE;
+    if (algo != OZC_ALGO_KARATSUBA && algo != OZC_ALGO_4M) return OZC_STATUS_INVALID_VALUE;
+    h->nmod = num_moduli;
+    h->mode = mode;
+    h->algo = algo;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_workspace_size(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
+                                int64_t k, size_t *bytes) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!bytes || !valid_op(ta) || !valid_op(tb) || m < 0 || n < 0 || k < 0)
+        return OZC_STATUS_INVALID_VALUE;
+    if (k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
+    *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(h, m, n, k, false).total;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_set_workspace(ozc_handle_t h, void *ptr, size_t bytes) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (ptr && ((uintptr_t)ptr % kAlign)) return OZC_STATUS_INVALID_VALUE;
+    h->ws_user = ptr;
+    h->ws_user_bytes = ptr ? bytes : 0;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_zgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,
+                       const double alpha[2], const void *A, int64_t lda, const void *B,
+                       int64_t ldb, const double beta[2], void *C, int64_t ldc) {
+    if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
+    return run(h, false, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+}
+
+ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,
+                       const float alpha[2], const void *A, int64_t lda, const void *B,
+                       int64_t ldb, const float beta[2], void *C, int64_t ldc) {
+    if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
+    const double al[2] = {alpha[0], alpha[1]}, be[2] = {beta[0], beta[1]};
+    return run(h, true, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc, nullptr);
+}
+
+ozc_status_t ozc_inspect(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                         int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                         int64_t ldb, int16_t *mu, int16_t *nu, int8_t *resA, int8_t *resB,
+                         int32_t *prods, int8_t *eprime, void *C, int64_t ldc) {
+    const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
+    InspectOut ins{mu, nu, resA, resB, prods, eprime};
+    return run(h, single != 0, ta, tb, m, n, k, one, A, lda, B, ldb, zero, C, ldc, &ins);
+}
+
+ozc_status_t ozc_last_info(ozc_handle_t h, ozc_info_t *info) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!info) return OZC_STATUS_INVALID_VALUE;
+    if (hipSetDevice(h->device) != hipSuccess) return OZC_STATUS_HIP_ERROR;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return OZC_STATUS_HIP_ERROR;
+    uint64_t st = 0;
+    if (hipMemcpy(&st, h->status_dev, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+        return OZC_STATUS_HIP_ERROR;
+    h->last.nonfinite = (int)(st & 1u);
+    *info = h->last;
+    return h->last.nonfinite ? OZC_STATUS_NONFINITE : OZC_STATUS_SUCCESS;
+}
+
+}  // extern "C"

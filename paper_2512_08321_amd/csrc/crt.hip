@@ -1,0 +1,263 @@
+// CRT reconstruction, inverse scaling and alpha/beta (Algorithm 1 Steps
+// V-v, V-vi and VI).
+//
+// For every output entry and each of the real and imaginary parts the kernel
+// forms S = sum_l s_l E'_l with s_l = (P/p_l) q_l, reduces C' = mod(S, P)
+// into [-P/2, P/2) and rounds C' to the nearest double (ties to even), then
+// scales by 2^-(mu_i + nu_j).  The paper evaluates S as an unevaluated sum
+// of two doubles and reduces it in double-double arithmetic (Section II,
+// equation (5); Section IV-A); here S is accumulated exactly in signed
+// 19-bit limbs with 32-bit integer multiply-adds (N * 128 * 2^19 < 2^31 for
+// N <= 24), which removes the reconstruction error altogether and makes the
+// output bit-reproducible against an exact reference.
+#include "internal.h"
+
+namespace ozc {
+namespace {
+
+constexpr int32_t kLimbMask = (1 << kLimbBits) - 1;
+
+template <int L>
+__device__ __forceinline__ void normalize(int32_t (&a)[L]) {
+    int32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < L - 1; ++j) {
+        const int32_t v = a[j] + c;
+        a[j] = v & kLimbMask;
+        c = v >> kLimbBits;  // arithmetic shift: floor division
+    }
+    a[L - 1] += c;
+}
+
+// After normalize(): value >= 0  <=>  top limb >= 0.
+template <int L>
+__device__ __noinline__ void settle_range(int32_t (&a)[L], const NTable *tab) {
+    int32_t t[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) t[j] = 2 * a[j] - tab->Plimb[j];
+    normalize<L>(t);
+    if (t[L - 1] >= 0) {  // 2R >= P
+#pragma unroll
+        for (int j = 0; j < L; ++j) a[j] -= tab->Plimb[j];
+        normalize<L>(a);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) t[j] = 2 * a[j] + tab->Plimb[j];
+    normalize<L>(t);
+    if (t[L - 1] < 0) {  // 2R < -P
+#pragma unroll
+        for (int j = 0; j < L; ++j) a[j] += tab->Plimb[j];
+        normalize<L>(a);
+    }
+}
+
+// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised limbs.
+template <int L>
+__device__ __forceinline__ double reconstruct(int32_t (&a)[L], const NTable *tab, int &sh) {
+    normalize<L>(a);
+    constexpr int lo = L >= 3 ? L - 3 : 0;
+    double sa = 0.0;
+#pragma unroll
+    for (int j = L - 1; j >= lo; --j) sa = sa * (double)(1 << kLimbBits) + (double)a[j];
+    const double x = ldexp(sa, kLimbBits * lo) * tab->inv_P;  // ~ S / P, error < 2^-36
+    const double qd = rint(x);
+    const int32_t q = (int32_t)qd;  // |q| <= 128 N + 1 < 2^12
+#pragma unroll
+    for (int j = 0; j < L; ++j) a[j] -= q * tab->Plimb[j];
+    normalize<L>(a);
+    if (fabs(x - qd) > 0.5 - 1.0 / 1048576.0) settle_range<L>(a, tab);
+
+    const bool neg = a[L - 1] < 0;
+    if (neg) {
+#pragma unroll
+        for (int j = 0; j < L; ++j) a[j] = -a[j];
+        normalize<L>(a);
+    }
+    uint64_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const int o = kLimbBits * j;
+        const uint64_t v = (uint64_t)(uint32_t)a[j];
+        w[o >> 6] |= v << (o & 63);
+        if ((o & 63) + kLimbBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
+    }
+    double d;
+    if ((w[1] | w[2] | w[3]) == 0) {
+        sh = 0;
+        d = (double)w[0];  // exact when < 2^53, otherwise one correct rounding
+    } else {
+        const int wi = w[3] ? 3 : (w[2] ? 2 : 1);
+        const uint64_t top = wi == 3 ? w[3] : (wi == 2 ? w[2] : w[1]);
+        const uint64_t below = wi == 3 ? w[2] : (wi == 2 ? w[1] : w[0]);
+        uint64_t rest = wi == 3 ? (w[1] | w[0]) : (wi == 2 ? w[0] : 0);
+        const int nb = 64 - __clzll((long long)top);  // 1..64
+        uint64_t W;
+        if (nb == 64) {
+            W = top;
+            rest |= below;
+        } else {
+            W = (top << (64 - nb)) | (below >> nb);
+            rest |= below << (64 - nb);
+        }
+        W |= (rest != 0) ? 1ull : 0ull;  // sticky bit below the rounding position
+        sh = 64 * (wi - 1) + nb;
+        d = (double)W;
+    }
+    return neg ? -d : d;
+}
+
+__device__ __forceinline__ void alpha_beta(double cr, double ci, double ar, double ai, double br,
+                                           double bi, bool beta_zero, double Cr, double Ci,
+                                           double &orr, double &oi) {
+    const double xr = fma(ar, cr, -(ai * ci));
+    const double xi = fma(ar, ci, ai * cr);
+    if (beta_zero) {
+        orr = xr;
+        oi = xi;
+    } else {
+        orr = fma(br, Cr, fma(-bi, Ci, xr));
+        oi = fma(br, Ci, fma(bi, Cr, xi));
+    }
+}
+
+template <bool SINGLE>
+__device__ __forceinline__ void load_c(const void *C, int64_t idx, double &re, double &im) {
+    if constexpr (SINGLE) {
+        const float2 v = reinterpret_cast<const float2 *>(C)[idx];
+        re = v.x;
+        im = v.y;
+    } else {
+        const double2 v = reinterpret_cast<const double2 *>(C)[idx];
+        re = v.x;
+        im = v.y;
+    }
+}
+
+template <bool SINGLE>
+__device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double im) {
+    if constexpr (SINGLE) reinterpret_cast<float2 *>(C)[idx] = make_float2((float)re, (float)im);
+    else reinterpret_cast<double2 *>(C)[idx] = make_double2(re, im);
+}
+
+// One thread: 4 consecutive rows i of one column j.
+template <int L, bool SINGLE>
+__global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
+    const int64_t m4 = a.m_pad >> 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i4 = t % m4, j = t / m4;
+    const int64_t ib = i4 * 4;
+    if (j >= a.n || ib >= a.m) return;
+
+    const int64_t planeC = a.n_pad * a.m_pad;
+    int32_t accR[4][L], accI[4][L];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < L; ++q) accR[u][q] = accI[u][q] = 0;
+
+    const int8_t *E = a.eprime + j * a.m_pad + ib;
+    for (int l = 0; l < a.nmod; ++l) {
+        const uint32_t wr = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l) * planeC);
+        const uint32_t wi = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l + 1) * planeC);
+        int er[4], ei[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            er[u] = (int)(int8_t)(wr >> (8 * u));
+            ei[u] = (int)(int8_t)(wi >> (8 * u));
+        }
+        const int32_t *sl = a.tab->mod[l].slimb;
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+            const int32_t s = sl[q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                accR[u][q] += __mul24(s, er[u]);
+                accI[u][q] += __mul24(s, ei[u]);
+            }
+        }
+    }
+
+    const int nuj = a.nu[j];
+    const bool beta_zero = a.beta_r == 0.0 && a.beta_i == 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = ib + u;
+        if (i >= a.m) break;
+        const int mui = a.mu[i];
+        double cr, ci;
+        if (mui == kExpNonfinite || nuj == kExpNonfinite) {
+            cr = ci = __builtin_nan("");
+        } else if (mui == kExpZero || nuj == kExpZero) {
+            cr = ci = 0.0;
+        } else {
+            int shr, shi;
+            const double dr = reconstruct<L>(accR[u], a.tab, shr);
+            const double di = reconstruct<L>(accI[u], a.tab, shi);
+            cr = ldexp(dr, shr - (mui + nuj));
+            ci = ldexp(di, shi - (mui + nuj));
+        }
+        double Cr = 0.0, Ci = 0.0;
+        const int64_t idx = j * a.ldc + i;
+        if (!beta_zero) load_c<SINGLE>(a.C, idx, Cr, Ci);
+        double orr, oi;
+        alpha_beta(cr, ci, a.alpha_r, a.alpha_i, a.beta_r, a.beta_i, beta_zero, Cr, Ci, orr, oi);
+        store_c<SINGLE>(a.C, idx, orr, oi);
+    }
+}
+
+// C := alpha * 0 + beta * C (alpha == 0 or k == 0), with the same operation order.
+template <bool SINGLE>
+__global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, double ar, double ai,
+                               double br, double bi) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * n) return;
+    const int64_t i = t % m, j = t / m;
+    const bool beta_zero = br == 0.0 && bi == 0.0;
+    double Cr = 0.0, Ci = 0.0;
+    if (!beta_zero) load_c<SINGLE>(C, j * ldc + i, Cr, Ci);
+    double orr, oi;
+    alpha_beta(0.0, 0.0, ar, ai, br, bi, beta_zero, Cr, Ci, orr, oi);
+    store_c<SINGLE>(C, j * ldc + i, orr, oi);
+}
+
+template <int L>
+hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
+    const int64_t threads = (a.m_pad / 4) * a.n;
+    dim3 grid((unsigned)((threads + 255) / 256));
+    if (a.single) hipLaunchKernelGGL((crt_output_kernel<L, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((crt_output_kernel<L, false>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s) {
+    if (a.m <= 0 || a.n <= 0) return hipSuccess;
+    if (a.m_pad % 4) return hipErrorInvalidValue;
+    switch (a.nlimbs) {
+        case 1: return launch_L<1>(a, s);
+        case 2: return launch_L<2>(a, s);
+        case 3: return launch_L<3>(a, s);
+        case 4: return launch_L<4>(a, s);
+        case 5: return launch_L<5>(a, s);
+        case 6: return launch_L<6>(a, s);
+        case 7: return launch_L<7>(a, s);
+        case 8: return launch_L<8>(a, s);
+        case 9: return launch_L<9>(a, s);
+        case 10: return launch_L<10>(a, s);
+        case 11: return launch_L<11>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
+                          double ai, double br, double bi, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((m * n + 255) / 256));
+    if (single) hipLaunchKernelGGL(scale_c_kernel<true>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
+    else hipLaunchKernelGGL(scale_c_kernel<false>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
+    return hipGetLastError();
+}
+
+}  // namespace ozc

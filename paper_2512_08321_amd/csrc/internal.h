@@ -1,0 +1,113 @@
+// Internal definitions shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ozc {
+
+constexpr int kMaxModuli = 24;
+constexpr int kLimbBits = 19;       // CRT limbs: N * 128 * (2^19 - 1) < 2^31 for N <= 24
+constexpr int kMaxLimbs = 11;       // ceil((log2 P + 1) / 19) for N <= 24
+constexpr int kChunkBits = 21;      // residue extraction: |a'| split into 21-bit chunks
+constexpr int kMaxChunks = 6;       // |a'| < 2^126
+constexpr int kThr = 64;            // threshold table length for the exponent rules
+constexpr int kSigmaFracBits = 20;  // fast mode: fixed-point fraction bits of sum of squares
+constexpr int kAccuIntBits = 6;     // accurate mode: magnitudes scaled below 2^6
+constexpr int16_t kExpZero = -32768;
+constexpr int16_t kExpNonfinite = 32767;
+
+// Per-modulus constants.
+struct ModConst {
+    uint32_t p;                  // modulus
+    uint32_t half;               // ceil(p / 2): residues >= half map to r - p
+    uint32_t barrett;            // floor(2^32 / p)
+    uint32_t koff;               // multiple of p >= 2^31 (odd p), 0 for p = 256
+    uint32_t w[kMaxChunks];      // 2^(21 j) mod p
+    int32_t slimb[kMaxLimbs];    // 19-bit limbs of s_l = (P / p_l) q_l
+};
+
+// Constants of one moduli count N.
+struct NTable {
+    int32_t n;
+    int32_t nlimbs;               // limbs of P (and of every s_l)
+    int32_t Plimb[kMaxLimbs];     // 19-bit limbs of P
+    double P_approx;              // P rounded to double
+    double inv_P;                 // 1 / P rounded to double
+    int32_t fast_tmax;            // largest t with 2^(2t+5) <= P - 1
+    int32_t accu_thi;             // largest t with 2 * 4^t <= P - 1
+    int32_t max_abits_fast;       // bound on the bit length of |a'| in fast mode
+    int32_t max_abits_accu;       // ... in accurate mode
+    uint64_t fast_thr[kThr];      // sigma <= fast_thr[d]  <=>  t = fast_tmax - d admissible
+    uint64_t accu_thr[kThr];      // X <= accu_thr[d]      <=>  t = accu_thi - d admissible
+    ModConst mod[kMaxModuli];
+};
+
+// Host: build the tables for N = 1..kMaxModuli (index N-1).
+void build_tables(NTable *tables);
+
+// Operand view: `rows` rows of k complex elements; element (r, h) lives at
+// base[r * stride_r + h * stride_h] (in complex elements); conj negates Im.
+struct OperandView {
+    const void *base;
+    int64_t rows, k;
+    int64_t stride_r, stride_h;
+    int conj;
+    int contig_h;  // 1 when stride_h == 1 (rows contiguous), 0 when stride_r == 1
+};
+
+// Kernel launchers (all asynchronous on `stream`).
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbits, hipStream_t s);
+hipError_t launch_row_sigma(const OperandView &v, bool single, const uint64_t *maxbits,
+                            uint64_t *sigma, hipStream_t s);
+hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
+                                 int64_t rows_pad, const NTable *tab, int16_t *mu,
+                                 uint32_t *status, hipStream_t s);
+hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits,
+                        int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s);
+hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int64_t rows,
+                                 int64_t rows_pad, const NTable *tab, int16_t *mu,
+                                 uint32_t *status, hipStream_t s);
+hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
+                        int nmod, int nplanes, int nchunks, int8_t *dst, int64_t rows_pad,
+                        int64_t k_pad, hipStream_t s);
+
+struct GemmArgs {
+    const int8_t *A;      // [N][planes][m_pad][k_pad]
+    const int8_t *B;      // [N][planes][n_pad][k_pad]
+    int64_t m_pad, n_pad, k_pad;
+    int nmod;
+    int algo;             // 0 Karatsuba, 1 expanded (4 products)
+    const NTable *tab;
+    int8_t *eprime;       // [N][2][n_pad][m_pad]
+    int32_t *prods;       // optional raw dump [N][nprod][n_pad][m_pad]
+};
+hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s);
+
+// Accurate-mode bound product: X[i] = max_j max(Cbar_R, Cbar_I)_ij, Y[j] likewise.
+struct BoundArgs {
+    const int8_t *A;      // [3][m_pad][k_pad]: Abar_R, Abar_I, Abar_R - Abar_I
+    const int8_t *B;      // [3][n_pad][k_pad]
+    int64_t m_pad, n_pad, k_pad;
+    int32_t *X, *Y;       // zero-initialised
+};
+hipError_t launch_bound_gemm(const BoundArgs &a, hipStream_t s);
+
+struct CrtArgs {
+    const int8_t *eprime;  // [N][2][n_pad][m_pad]
+    int64_t m, n, m_pad, n_pad;
+    int nmod;
+    int nlimbs;            // limbs of P for this N (host copy of tab->nlimbs)
+    const NTable *tab;     // device pointer
+    const int16_t *mu, *nu;
+    double alpha_r, alpha_i, beta_r, beta_i;
+    void *C;               // complex128 or complex64, column-major
+    int64_t ldc;
+    bool single;
+};
+hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s);
+hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
+                          double ai, double br, double bi, hipStream_t s);
+
+}  // namespace ozc

@@ -1,0 +1,490 @@
+// Scaling and residue split: the two HBM-bound passes over A and B that
+// precede the INT8 products (Section III-B; Algorithm 1 Steps III, IV, V-i/ii).
+//
+// Operands are handled as "rows": the rows of op(A) and the columns of op(B),
+// each a vector of k complex numbers (rows i and i+m of A-hat share one
+// exponent, Section III-B).  Two memory orders occur: rows whose k elements
+// are contiguous (contig_h) and rows that are contiguous with each other
+// (consecutive rows adjacent, stride_r == 1).  Every kernel has a variant for
+// each so that global loads stay coalesced.
+#include "internal.h"
+
+namespace ozc {
+namespace {
+
+constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
+constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
+
+template <bool SINGLE>
+__device__ __forceinline__ void load_elem(const void *base, int64_t idx, double &re, double &im) {
+    if constexpr (SINGLE) {
+        float2 v = reinterpret_cast<const float2 *>(base)[idx];
+        re = (double)v.x;
+        im = (double)v.y;
+    } else {
+        double2 v = reinterpret_cast<const double2 *>(base)[idx];
+        re = v.x;
+        im = v.y;
+    }
+}
+
+__device__ __forceinline__ uint64_t abs_bits(double x) {
+    return (uint64_t)__double_as_longlong(x) & kAbsMask;
+}
+
+// floor(log2 v) for the positive finite double whose bit pattern is `bits`.
+__device__ __forceinline__ int ilogb_bits(uint64_t bits) {
+    int ef = (int)(bits >> 52);
+    if (ef == 0) return -1074 + 63 - __clzll((long long)bits);
+    return ef - 1023;
+}
+
+// |x| = M * 2^E, M < 2^53 integer (x finite).
+__device__ __forceinline__ void decompose(double x, uint64_t &M, int &E) {
+    uint64_t b = abs_bits(x);
+    int ef = (int)(b >> 52);
+    uint64_t mant = b & ((1ull << 52) - 1);
+    if (ef == 0) {
+        M = mant;
+        E = -1074;
+    } else {
+        M = mant | (1ull << 52);
+        E = ef - 1075;
+    }
+}
+
+// ceil(|x| * 2^sh) for finite x when the result is below 2^63.
+__device__ __forceinline__ uint64_t ceil_scaled(double x, int sh) {
+    uint64_t M;
+    int E;
+    decompose(x, M, E);
+    if (M == 0) return 0;
+    int s = E + sh;
+    if (s >= 0) return M << s;
+    if (s <= -64) return 1;
+    int r = -s;
+    return (M + ((1ull << r) - 1)) >> r;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint64_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr int kHChunk = 2048;  // k-elements per block along a row
+
+__global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- row max |x|
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t *maxbits) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    if (r >= v.rows) return;
+    const int64_t h0 = (int64_t)blockIdx.y * kHChunk;
+    const int64_t h1 = min(v.k, h0 + kHChunk);
+    uint64_t m = 0;
+    for (int64_t h = h0 + lane; h < h1; h += 64) {
+        double re, im;
+        load_elem<SINGLE>(v.base, r * v.stride_r + h, re, im);
+        uint64_t a = abs_bits(re), b = abs_bits(im);
+        m = max(m, max(a, b));
+    }
+    m = wave_max_u64(m);
+    if (lane == 0 && m) atomicMax((unsigned long long *)&maxbits[r], (unsigned long long)m);
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= v.rows) return;
+    const int64_t h0 = (int64_t)blockIdx.y * (kHChunk / 8);
+    const int64_t h1 = min(v.k, h0 + kHChunk / 8);
+    uint64_t m = 0;
+    for (int64_t h = h0; h < h1; ++h) {
+        double re, im;
+        load_elem<SINGLE>(v.base, r + h * v.stride_h, re, im);
+        m = max(m, max(abs_bits(re), abs_bits(im)));
+    }
+    if (m) atomicMax((unsigned long long *)&maxbits[r], (unsigned long long)m);
+}
+
+// ---------------------------------------------------------------- fast-mode sum of squares
+// sigma_r = sum over the 2k reals of ceil(|x| 2^(F - e_r))^2, e_r = floor(log2 max|x|):
+// an integer upper bound of 2^(2F) ||row / 2^e_r||_2^2, independent of summation order.
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uint64_t *maxbits,
+                                                        uint64_t *sigma) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    if (r >= v.rows) return;
+    const uint64_t mb = maxbits[r];
+    if (mb == 0 || mb >= kInfBits) return;
+    const int sh = kSigmaFracBits - ilogb_bits(mb);
+    const int64_t h0 = (int64_t)blockIdx.y * kHChunk;
+    const int64_t h1 = min(v.k, h0 + kHChunk);
+    uint64_t s = 0;
+    for (int64_t h = h0 + lane; h < h1; h += 64) {
+        double re, im;
+        load_elem<SINGLE>(v.base, r * v.stride_r + h, re, im);
+        uint64_t a = ceil_scaled(re, sh), b = ceil_scaled(im, sh);
+        s += a * a + b * b;
+    }
+    s = wave_sum_u64(s);
+    if (lane == 0 && s) atomicAdd((unsigned long long *)&sigma[r], (unsigned long long)s);
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const uint64_t *maxbits,
+                                                         uint64_t *sigma) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= v.rows) return;
+    const uint64_t mb = maxbits[r];
+    if (mb == 0 || mb >= kInfBits) return;
+    const int sh = kSigmaFracBits - ilogb_bits(mb);
+    const int64_t h0 = (int64_t)blockIdx.y * (kHChunk / 8);
+    const int64_t h1 = min(v.k, h0 + kHChunk / 8);
+    uint64_t s = 0;
+    for (int64_t h = h0; h < h1; ++h) {
+        double re, im;
+        load_elem<SINGLE>(v.base, r + h * v.stride_h, re, im);
+        uint64_t a = ceil_scaled(re, sh), b = ceil_scaled(im, sh);
+        s += a * a + b * b;
+    }
+    if (s) atomicAdd((unsigned long long *)&sigma[r], (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------- exponents
+// Fast mode: mu_r = t - e_r with t the largest integer <= P'_fast - 1 such that
+// 8 sigma 4^t <= (P - 1) 2^(2F)  (the Cauchy-Schwarz rule of Section III-B in
+// exact integer form).  Accurate mode: mu_r = (5 - e_r) + t with t the largest
+// integer such that 2 X_r 4^t <= P - 1, X_r the row maximum of the bound product.
+
+__global__ void fast_exponents_kernel(const uint64_t *maxbits, const uint64_t *sigma,
+                                      int64_t rows, int64_t rows_pad, const NTable *tab,
+                                      int16_t *mu, uint32_t *status) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_pad) return;
+    int16_t out = kExpZero;
+    if (r < rows) {
+        const uint64_t mb = maxbits[r];
+        if (mb >= kInfBits) {
+            out = kExpNonfinite;
+            atomicOr(status, 1u);
+        } else if (mb != 0) {
+            const uint64_t s = sigma[r];
+            int d = 0;
+            while (d < kThr - 1 && tab->fast_thr[d] < s) ++d;
+            out = (int16_t)(tab->fast_tmax - d - ilogb_bits(mb));
+        }
+    }
+    mu[r] = out;
+}
+
+__global__ void accu_exponents_kernel(const uint64_t *maxbits, const int32_t *X, int64_t rows,
+                                      int64_t rows_pad, const NTable *tab, int16_t *mu,
+                                      uint32_t *status) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_pad) return;
+    int16_t out = kExpZero;
+    if (r < rows) {
+        const uint64_t mb = maxbits[r];
+        if (mb >= kInfBits) {
+            out = kExpNonfinite;
+            atomicOr(status, 1u);
+        } else if (mb != 0 && X[r] > 0) {
+            const uint64_t x = (uint64_t)X[r];
+            int d = 0;
+            while (d < kThr - 1 && tab->accu_thr[d] < x) ++d;
+            out = (int16_t)((kAccuIntBits - 1) - ilogb_bits(mb) + tab->accu_thi - d);
+        }
+    }
+    mu[r] = out;
+}
+
+// ---------------------------------------------------------------- residue split
+// Tile of 32 rows x 64 k-elements per block.  Each thread converts 8
+// elements to the integer chunks of |trunc(x 2^mu)| once, then for every
+// modulus computes the symmetric residues (and, for Karatsuba, the reduced
+// sum of the real and imaginary residues), stages them in LDS and writes
+// k-contiguous rows, zero-padded to rows_pad x k_pad.
+//
+// CEIL7 (accurate mode): instead of residues, writes the 7-bit magnitudes
+// ceil(|x| 2^(5 - e)) of the real and imaginary parts and their difference.
+
+constexpr int kTileR = 32, kTileH = 64, kLdsPitch = 80;
+
+template <int NCHUNK>
+__device__ __forceinline__ void trunc_chunks(double x, int mu, uint32_t (&c)[NCHUNK], bool &neg) {
+    uint64_t M;
+    int E;
+    decompose(x, M, E);
+    neg = x < 0.0;
+    const int s = E + mu;
+    uint64_t lo = 0, hi = 0;
+    if (M != 0) {
+        if (s >= 64) {
+            hi = M << (s - 64);
+        } else if (s > 0) {
+            lo = M << s;
+            hi = M >> (64 - s);
+        } else if (s > -64) {
+            lo = M >> (-s);
+        }
+    }
+    constexpr uint64_t mask = (1ull << kChunkBits) - 1;
+#pragma unroll
+    for (int j = 0; j < NCHUNK; ++j) {
+        const int o = kChunkBits * j;
+        uint64_t v;
+        if (o + kChunkBits <= 64) v = lo >> o;
+        else if (o >= 64) v = hi >> (o - 64);
+        else v = (lo >> o) | (hi << (64 - o));
+        c[j] = (uint32_t)(v & mask);
+    }
+}
+
+template <int NCHUNK>
+__device__ __forceinline__ int residue(const uint32_t (&c)[NCHUNK], bool neg, const ModConst &mc) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < NCHUNK; ++j) x += __umul24(c[j], mc.w[j]);
+    uint32_t r = x - __umulhi(x, mc.barrett) * mc.p;
+    if (r >= mc.p) r -= mc.p;
+    if (neg && r != 0) r = mc.p - r;
+    int s = (int)r;
+    if (r >= mc.half) s -= (int)mc.p;
+    return s;
+}
+
+__device__ __forceinline__ int sum_residue(int a, int b, const ModConst &mc) {
+    int s = a + b;
+    if (s >= (int)mc.half) s -= (int)mc.p;
+    else if (s < (int)mc.half - (int)mc.p) s += (int)mc.p;
+    return s;
+}
+
+template <bool SINGLE, bool CONTIG_H, int NPLANES, int NCHUNK, bool CEIL7>
+__global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *mu,
+                                                    const uint64_t *maxbits, const NTable *tab,
+                                                    int nmod, int8_t *dst, int64_t rows_pad,
+                                                    int64_t k_pad) {
+    __shared__ __align__(16) int8_t lds[NPLANES][kTileR][kLdsPitch];
+    const int tid = threadIdx.x;
+    const int64_t h0 = (int64_t)blockIdx.x * kTileH;
+    const int64_t r0 = (int64_t)blockIdx.y * kTileR;
+    const int64_t plane_pitch = rows_pad * k_pad;
+
+    // element coordinates of this thread (8 elements)
+    int rl[8], hl[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (CONTIG_H) {
+            hl[e] = tid & 63;
+            rl[e] = (tid >> 6) + 4 * e;
+        } else {
+            rl[e] = tid & 31;
+            hl[e] = (tid >> 5) + 8 * e;
+        }
+    }
+
+    uint32_t cR[8][NCHUNK], cI[8][NCHUNK];
+    bool nR[8], nI[8];
+    int bar[8][3];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t r = r0 + rl[e], h = h0 + hl[e];
+        double re = 0.0, im = 0.0;
+        int ex = kExpZero;
+        if (r < v.rows && h < v.k) {
+            if constexpr (CEIL7) {
+                const uint64_t mb = maxbits[r];
+                if (mb != 0 && mb < kInfBits) ex = ilogb_bits(mb);
+            } else {
+                ex = mu[r];
+            }
+            if (ex != kExpZero && ex != kExpNonfinite) {
+                load_elem<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
+                if (v.conj) im = -im;
+            } else {
+                ex = kExpZero;
+            }
+        }
+        if constexpr (CEIL7) {
+            int a = 0, b = 0;
+            if (ex != kExpZero) {
+                a = (int)ceil_scaled(re, (kAccuIntBits - 1) - ex);
+                b = (int)ceil_scaled(im, (kAccuIntBits - 1) - ex);
+            }
+            bar[e][0] = a;
+            bar[e][1] = b;
+            bar[e][2] = a - b;
+        } else {
+            if (ex == kExpZero) {
+                re = 0.0;
+                im = 0.0;
+                ex = 0;
+            }
+            trunc_chunks<NCHUNK>(re, ex, cR[e], nR[e]);
+            trunc_chunks<NCHUNK>(im, ex, cI[e], nI[e]);
+        }
+    }
+
+    const int nl = CEIL7 ? 1 : nmod;
+    for (int l = 0; l < nl; ++l) {
+        if constexpr (CEIL7) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int pl = 0; pl < NPLANES; ++pl) lds[pl][rl[e]][hl[e]] = (int8_t)bar[e][pl];
+        } else {
+            const ModConst &mc = tab->mod[l];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int a = residue<NCHUNK>(cR[e], nR[e], mc);
+                const int b = residue<NCHUNK>(cI[e], nI[e], mc);
+                lds[0][rl[e]][hl[e]] = (int8_t)a;
+                lds[1][rl[e]][hl[e]] = (int8_t)b;
+                if constexpr (NPLANES == 3) lds[2][rl[e]][hl[e]] = (int8_t)sum_residue(a, b, mc);
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
+            const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
+            const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
+            int8_t *out = dst + ((int64_t)l * NPLANES + pl) * plane_pitch + (r0 + row) * k_pad +
+                          h0 + seg * 16;
+            *reinterpret_cast<uint4 *>(out) = val;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool SINGLE, bool CONTIG_H, int NPLANES, bool CEIL7>
+hipError_t split_dispatch_chunks(const OperandView &v, const int16_t *mu, const uint64_t *maxbits,
+                                 const NTable *tab, int nmod, int nchunks, int8_t *dst,
+                                 int64_t rows_pad, int64_t k_pad, hipStream_t s) {
+    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kTileR));
+#define OZC_SPLIT_CASE(NC)                                                                   \
+    case NC:                                                                                 \
+        hipLaunchKernelGGL((split_kernel<SINGLE, CONTIG_H, NPLANES, NC, CEIL7>), grid,       \
+                           dim3(256), 0, s, v, mu, maxbits, tab, nmod, dst, rows_pad, k_pad); \
+        break;
+    switch (CEIL7 ? 1 : nchunks) {
+        OZC_SPLIT_CASE(1)
+        OZC_SPLIT_CASE(2)
+        OZC_SPLIT_CASE(3)
+        OZC_SPLIT_CASE(4)
+        OZC_SPLIT_CASE(5)
+        OZC_SPLIT_CASE(6)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef OZC_SPLIT_CASE
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbits, hipStream_t s) {
+    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+    if (v.contig_h) {
+        dim3 grid((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kHChunk - 1) / kHChunk));
+        if (single) hipLaunchKernelGGL(row_maxabs_contig<true>, grid, dim3(256), 0, s, v, maxbits);
+        else hipLaunchKernelGGL(row_maxabs_contig<false>, grid, dim3(256), 0, s, v, maxbits);
+    } else {
+        const int hc = kHChunk / 8;
+        dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
+        if (single) hipLaunchKernelGGL(row_maxabs_strided<true>, grid, dim3(256), 0, s, v, maxbits);
+        else hipLaunchKernelGGL(row_maxabs_strided<false>, grid, dim3(256), 0, s, v, maxbits);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row_sigma(const OperandView &v, bool single, const uint64_t *maxbits,
+                            uint64_t *sigma, hipStream_t s) {
+    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+    if (v.contig_h) {
+        dim3 grid((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kHChunk - 1) / kHChunk));
+        if (single) hipLaunchKernelGGL(row_sigma_contig<true>, grid, dim3(256), 0, s, v, maxbits, sigma);
+        else hipLaunchKernelGGL(row_sigma_contig<false>, grid, dim3(256), 0, s, v, maxbits, sigma);
+    } else {
+        const int hc = kHChunk / 8;
+        dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
+        if (single) hipLaunchKernelGGL(row_sigma_strided<true>, grid, dim3(256), 0, s, v, maxbits, sigma);
+        else hipLaunchKernelGGL(row_sigma_strided<false>, grid, dim3(256), 0, s, v, maxbits, sigma);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
+                                 int64_t rows_pad, const NTable *tab, int16_t *mu,
+                                 uint32_t *status, hipStream_t s) {
+    if (rows_pad <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fast_exponents_kernel, dim3((unsigned)((rows_pad + 255) / 256)), dim3(256),
+                       0, s, maxbits, sigma, rows, rows_pad, tab, mu, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int64_t rows,
+                                 int64_t rows_pad, const NTable *tab, int16_t *mu,
+                                 uint32_t *status, hipStream_t s) {
+    if (rows_pad <= 0) return hipSuccess;
+    hipLaunchKernelGGL(accu_exponents_kernel, dim3((unsigned)((rows_pad + 255) / 256)), dim3(256),
+                       0, s, maxbits, X, rows, rows_pad, tab, mu, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
+                        int nmod, int nplanes, int nchunks, int8_t *dst, int64_t rows_pad,
+                        int64_t k_pad, hipStream_t s) {
+    if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
+#define OZC_SPLIT_ARGS v, mu, nullptr, tab, nmod, nchunks, dst, rows_pad, k_pad, s
+    if (single) {
+        if (v.contig_h) return nplanes == 3 ? split_dispatch_chunks<true, true, 3, false>(OZC_SPLIT_ARGS)
+                                            : split_dispatch_chunks<true, true, 2, false>(OZC_SPLIT_ARGS);
+        return nplanes == 3 ? split_dispatch_chunks<true, false, 3, false>(OZC_SPLIT_ARGS)
+                            : split_dispatch_chunks<true, false, 2, false>(OZC_SPLIT_ARGS);
+    }
+    if (v.contig_h) return nplanes == 3 ? split_dispatch_chunks<false, true, 3, false>(OZC_SPLIT_ARGS)
+                                        : split_dispatch_chunks<false, true, 2, false>(OZC_SPLIT_ARGS);
+    return nplanes == 3 ? split_dispatch_chunks<false, false, 3, false>(OZC_SPLIT_ARGS)
+                        : split_dispatch_chunks<false, false, 2, false>(OZC_SPLIT_ARGS);
+#undef OZC_SPLIT_ARGS
+}
+
+hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits, int8_t *dst,
+                        int64_t rows_pad, int64_t k_pad, hipStream_t s) {
+    if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
+#define OZC_C7_ARGS v, nullptr, maxbits, nullptr, 1, 1, dst, rows_pad, k_pad, s
+    if (single) {
+        return v.contig_h ? split_dispatch_chunks<true, true, 3, true>(OZC_C7_ARGS)
+                          : split_dispatch_chunks<true, false, 3, true>(OZC_C7_ARGS);
+    }
+    return v.contig_h ? split_dispatch_chunks<false, true, 3, true>(OZC_C7_ARGS)
+                      : split_dispatch_chunks<false, false, 3, true>(OZC_C7_ARGS);
+#undef OZC_C7_ARGS
+}
+
+}  // namespace ozc

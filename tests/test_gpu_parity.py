@@ -1,0 +1,233 @@
+"""GPU path (through the C-ABI) against the CPU oracle, element by element.
+
+Bar: exponents, residues, INT32 products and E' bit-exact; outputs bit-exact
+(the reconstruction is exact on both sides, and alpha/beta follow the same
+fused multiply-add order).  NaN outputs compare as NaN.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import from_device, oracle_exp, stored, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import torch
+
+    import paper_2512_08321_amd as ozc
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    h = ozc.Handle(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import core
+
+    return core
+
+
+def _same(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nan_a = np.isnan(a.real) | np.isnan(a.imag)
+    nan_b = np.isnan(b.real) | np.isnan(b.imag)
+    return np.array_equal(nan_a, nan_b) and np.array_equal(a[~nan_a], b[~nan_b])
+
+
+def _run_inspect(h, orc, A, B, N, mode, algo, ta="N", tb="N", single=False, lda_pad=0, ldb_pad=0):
+    import torch
+
+    print(f"inspect m,n,k={A.shape[0]},{B.shape[1]},{A.shape[1]} N={N} {mode} {algo} {ta}{tb} "
+          f"single={single}", flush=True)
+    m, k = A.shape
+    n = B.shape[1]
+    h.set_config(N, mode, algo)
+    As, Bs = stored(A, ta), stored(B, tb)
+    dA, lda = to_device(As, As.shape[0] + lda_pad)
+    dB, ldb = to_device(Bs, Bs.shape[0] + ldb_pad)
+    planes = 3 if algo == "karatsuba" else 2
+    nprod = 3 if algo == "karatsuba" else 4
+    dev = "cuda"
+    mu = torch.zeros(m, dtype=torch.int16, device=dev)
+    nu = torch.zeros(n, dtype=torch.int16, device=dev)
+    rA = torch.zeros((N, planes, m, k), dtype=torch.int8, device=dev)
+    rB = torch.zeros((N, planes, n, k), dtype=torch.int8, device=dev)
+    pr = torch.zeros((N, nprod, n, m), dtype=torch.int32, device=dev)
+    ep = torch.zeros((N, 2, n, m), dtype=torch.int8, device=dev)
+    dC, ldc = to_device(np.zeros((m, n), dtype=A.dtype))
+    h.inspect(single, ta, tb, m, n, k, dA, lda, dB, ldb, mu, nu, rA, rB, pr, ep, dC, ldc)
+    torch.cuda.synchronize()
+    ref = orc.emulate(A, B, N, mode, algo, single=single, want_raw=True)
+    return dict(mu=mu.cpu().numpy(), nu=nu.cpu().numpy(), rA=rA.cpu().numpy(), rB=rB.cpu().numpy(),
+                pr=pr.cpu().numpy(), ep=ep.cpu().numpy(), out=from_device(dC, m, n, ldc)), ref
+
+
+def _check_inspect(g, ref, algo):
+    planes = 3 if algo == "karatsuba" else 2
+    assert np.array_equal(g["mu"], oracle_exp(ref["mu"], ref["fa"])), "mu"
+    assert np.array_equal(g["nu"], oracle_exp(ref["nu"], ref["fb"])), "nu"
+    assert np.array_equal(g["rA"], ref["resA"][:, :planes]), "residues of A"
+    assert np.array_equal(g["rB"], ref["resB"][:, :planes]), "residues of B"
+    assert np.array_equal(g["pr"].transpose(0, 1, 3, 2), ref["raw"].astype(np.int32)), "INT32 products"
+    assert np.array_equal(g["ep"].transpose(0, 1, 3, 2), ref["Ep"]), "E'"
+    assert _same(g["out"], ref["out"]), "output"
+
+
+# several tiles in every dimension plus ragged tails
+@pytest.mark.parametrize("mode", ["fast", "accurate"])
+@pytest.mark.parametrize("algo", ["karatsuba", "4m"])
+def test_intermediates_bit_exact(handle, orc, mode, algo):
+    A = workloads.complex_matrix(300, 150, 1.0, 11)
+    B = workloads.complex_matrix(150, 200, 1.0, 12)
+    g, ref = _run_inspect(handle, orc, A, B, 14, mode, algo)
+    _check_inspect(g, ref, algo)
+
+
+@pytest.mark.parametrize("ta,tb", [("N", "T"), ("T", "N"), ("C", "C"), ("T", "C"), ("C", "N")])
+def test_transpose_ops(handle, orc, ta, tb):
+    A = workloads.complex_matrix(131, 77, 2.0, 21)
+    B = workloads.complex_matrix(77, 140, 2.0, 22)
+    g, ref = _run_inspect(handle, orc, A, B, 13, "fast", "karatsuba", ta, tb, lda_pad=3, ldb_pad=5)
+    _check_inspect(g, ref, "karatsuba")
+
+
+@pytest.mark.parametrize("N", [2, 3, 6, 9, 12, 16, 20, 24])
+def test_moduli_counts(handle, orc, N):
+    A = workloads.complex_matrix(129, 64, 4.0, 30 + N)
+    B = workloads.complex_matrix(64, 130, 4.0, 60 + N)
+    for mode in ("fast", "accurate"):
+        g, ref = _run_inspect(handle, orc, A, B, N, mode, "karatsuba")
+        _check_inspect(g, ref, "karatsuba")
+
+
+@pytest.mark.parametrize("N", [6, 8, 12])
+def test_cgemm_intermediates(handle, orc, N):
+    A = workloads.complex_matrix(200, 96, 0.5, 41, dtype=np.complex64)
+    B = workloads.complex_matrix(96, 160, 0.5, 42, dtype=np.complex64)
+    for algo in ("karatsuba", "4m"):
+        g, ref = _run_inspect(handle, orc, A, B, N, "fast", algo, single=True)
+        _check_inspect(g, ref, algo)
+        assert g["out"].dtype == np.complex64
+
+
+def _gemm_call(h, A, B, C, alpha, beta, N, mode="fast", algo="karatsuba", ta="N", tb="N"):
+    import torch
+
+    m, k = A.shape
+    n = B.shape[1]
+    h.set_config(N, mode, algo)
+    As, Bs = stored(A, ta), stored(B, tb)
+    dA, lda = to_device(As)
+    dB, ldb = to_device(Bs)
+    dC, ldc = to_device(np.asfortranarray(C.astype(A.dtype)), m + 2)
+    fn = h.zgemm if A.dtype == np.complex128 else h.cgemm
+    fn(ta, tb, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc)
+    torch.cuda.synchronize()
+    return from_device(dC, m, n, ldc)
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_alpha_beta(handle, orc, single):
+    dt = np.complex64 if single else np.complex128
+    A = workloads.complex_matrix(70, 33, 1.0, 51, dtype=dt)
+    B = workloads.complex_matrix(33, 90, 1.0, 52, dtype=dt)
+    C = workloads.complex_matrix(70, 90, 1.0, 53, dtype=dt)
+    for alpha, beta in [(0.5 - 2j, 1.5 + 0.25j), (-1.0, 0.75j), (2.0, 0.0), (1.0, 1.0)]:
+        got = _gemm_call(handle, A, B, C, alpha, beta, 11)
+        ref = orc.emulate(A, B, 11, alpha=alpha, beta=beta, C=C, single=single)["out"]
+        assert _same(got, ref), (alpha, beta)
+
+
+def test_edge_cases(handle, orc):
+    import torch
+
+    # 1x1x1, zero rows/columns, integer-valued inputs
+    for (m, n, k) in [(1, 1, 1), (1, 7, 3), (5, 1, 200), (128, 128, 64), (129, 127, 65)]:
+        A = workloads.complex_matrix(m, k, 1.0, m + k)
+        B = workloads.complex_matrix(k, n, 1.0, n + k)
+        if m > 2:
+            A[1, :] = 0
+        if n > 2:
+            B[:, 2] = 0
+        got = _gemm_call(handle, A, B, np.zeros((m, n)), 1.0, 0.0, 14)
+        assert _same(got, orc.emulate(A, B, 14)["out"]), (m, n, k)
+    A = workloads.integer_matrix(64, 512, 12, 1)
+    B = workloads.integer_matrix(512, 48, 12, 2)
+    got = _gemm_call(handle, A, B, np.zeros((64, 48)), 1.0, 0.0, 14, "accurate")
+    assert np.array_equal(got, A @ B)
+    # k == 0 and alpha == 0: C := beta C
+    C = workloads.complex_matrix(9, 11, 1.0, 5)
+    A = workloads.complex_matrix(9, 4, 1.0, 6)
+    B = workloads.complex_matrix(4, 11, 1.0, 7)
+    got = _gemm_call(handle, A, B, C, 0.0, 0.5 - 1j, 14)
+    ref = orc.emulate(A, B, 14, alpha=0.0, beta=0.5 - 1j, C=C)["out"]
+    assert _same(got, ref)
+    got = _gemm_call(handle, A[:, :0], B[:0, :], C, 2.0, -1.0, 14)
+    ref = orc.emulate(A[:, :0], B[:0, :], 14, alpha=2.0, beta=-1.0, C=C)["out"]
+    assert _same(got, ref)
+    # m == 0: nothing happens
+    handle.zgemm("N", "N", 0, 5, 5, 1.0, 0, 1, 0, 5, 0.0, 0, 1)
+    torch.cuda.synchronize()
+
+
+def test_nonfinite_inputs(handle, orc):
+    A = workloads.complex_matrix(40, 20, 1.0, 71)
+    B = workloads.complex_matrix(20, 30, 1.0, 72)
+    A[3, 5] = complex(np.inf, 0)
+    B[7, 9] = complex(0, np.nan)
+    got = _gemm_call(handle, A, B, np.zeros((40, 30)), 1.0, 0.0, 12)
+    info = handle.last_info()
+    assert info["nonfinite"] == 1
+    ref = orc.emulate(A, B, 12)["out"]
+    assert _same(got, ref)
+    assert np.isnan(got[3, :].real).all() and np.isnan(got[:, 9].real).all()
+
+
+def test_argument_errors(handle):
+    import paper_2512_08321_amd as ozc
+
+    with pytest.raises(ozc.OzcError) as e:
+        handle.zgemm("N", "N", 4, 4, 4, 1.0, 1, 3, 1, 4, 0.0, 1, 4)  # lda < m
+    assert e.value.status == 1
+    with pytest.raises(ozc.OzcError) as e:
+        handle.zgemm("N", "N", 4, 4, ozc.MAX_K + 1, 1.0, 1, 4, 1, ozc.MAX_K + 1, 0.0, 1, 4)
+    assert e.value.status == 2
+    with pytest.raises(ozc.OzcError):
+        handle.set_config(25)
+    handle.set_config(14)
+
+
+def test_config0_workload_bit_exact(handle, orc):
+    """256^3 complex128, 14 moduli, 4-GEMM products, alpha = 1, beta = 0, phi = 0.5."""
+    A = workloads.complex_matrix(256, 256, 0.5, workloads.seed_for(0, 0, "A"))
+    B = workloads.complex_matrix(256, 256, 0.5, workloads.seed_for(0, 0, "B"))
+    got = _gemm_call(handle, A, B, np.zeros((256, 256)), 1.0, 0.0, 14, "fast", "4m")
+    ref = orc.emulate(A, B, 14, "fast", "4m")["out"]
+    assert _same(got, ref)
+    hi, lo = orc.dd_gemm(A, B)
+    err = orc.err_nc(got, hi, lo, orc.abs_product(A, B))
+    assert err <= 4 * 256 * 2.0 ** -53
+
+
+def test_deterministic_and_row_major_api(handle):
+    import torch
+
+    import paper_2512_08321_amd as ozc
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    A = torch.randn(300, 257, dtype=torch.complex128, device="cuda", generator=g)
+    B = torch.randn(257, 190, dtype=torch.complex128, device="cuda", generator=g)
+    c1 = ozc.gemm(A, B, num_moduli=14, handle=handle)
+    c2 = ozc.gemm(A, B, num_moduli=14, handle=handle)
+    assert torch.equal(c1, c2)
+    ref = (A.cpu() @ B.cpu())
+    rel = ((c1.cpu() - ref).abs() / (A.cpu().abs() @ B.cpu().abs())).max().item()
+    assert rel < 4 * 257 * 2.0 ** -53
