@@ -1,0 +1,211 @@
+"""Benchmark of the emulated ZGEMM (Ozaki-II on INT8 matrix cores) on one MI355X.
+
+One step = one ozc_zgemm call (scaling, residue split, INT8 residue products,
+CRT reconstruction and output) on inputs already resident in HBM.
+
+Default workload: ZGEMM m = n = k = 16384, complex128, 14 moduli, fast-mode
+scaling, Karatsuba products, alpha = 1, beta = 0, entries (u - 0.5) exp(0.5 g)
+(the paper's generator, Section IV-A), drawn on the device with a seeded
+generator.
+
+Prints one JSON line with the throughput 8mnk/t, the live roofline of the
+INT8 residue-product kernel (HIP events on the library's stream around that
+kernel, averaged over the timed steps), the INT8 MFMA utilisation, a
+correctness gate on sampled output entries (bit-exact against the CPU oracle,
+and the error against a double-double reference within 4k 2^-53), and the
+CPU oracle timed on that bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "emulated ZGEMM eff. TFLOPS (8mnk/t) at err<=FP64 bound; INT8 MFMA util %"
+INT8_PEAK_TOPS = 5033.2  # MI355X dense INT8 (Table I)
+GEMM_SOURCE = os.path.join(ROOT, "paper_2512_08321_amd", "csrc", "gemm.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gemm_source_hash() -> str:
+    with open(GEMM_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_key: str):
+    """HBM bytes per launch of the residue-product kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "residue_gemm_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload_key)
+    if not e or e.get("gemm_source_sha") != gemm_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=16384, help="m = n = k")
+    ap.add_argument("--m", type=int, default=0)
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--moduli", type=int, default=14)
+    ap.add_argument("--mode", default="fast", choices=["fast", "accurate"])
+    ap.add_argument("--algo", default="karatsuba", choices=["karatsuba", "4m"])
+    ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--single", action="store_true", help="CGEMM (complex64) instead of ZGEMM")
+    ap.add_argument("--sample-rows", type=int, default=512)
+    ap.add_argument("--sample-cols", type=int, default=1536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the emulation shards by output blocks with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    import workloads
+
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    N = args.moduli
+    cdt = torch.complex64 if args.single else torch.complex128
+    prec = "complex64" if args.single else "complex128"
+    kind = "CGEMM" if args.single else "ZGEMM"
+    cfg_id = 1 if args.single else 2
+
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {kind} {m}x{n}x{k} inputs (phi={args.phi}) on the device")
+    A = workloads.complex_matrix_torch(m, k, args.phi, workloads.seed_for(cfg_id, 0, "A"), cdt)
+    B = workloads.complex_matrix_torch(k, n, args.phi, workloads.seed_for(cfg_id, 0, "B"), cdt)
+    C = torch.zeros((n, m), dtype=cdt, device="cuda")  # column-major m x n
+    torch.cuda.synchronize()
+
+    h = ozc.Handle(0, num_moduli=N, mode=args.mode, algo=args.algo)
+    call = h.cgemm if args.single else h.zgemm
+
+    def step():
+        call("N", "N", m, n, k, 1.0, A, m, B, k, 0.0, C, m)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_read()
+    h.set_profiling(True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = h.profile_read()
+    h.set_profiling(False)
+    info = h.last_info()
+    ms = (t1 - t0) * 1e3 / args.steps
+    flops = 8.0 * m * n * k
+    value = flops / (ms * 1e-3) / 1e12
+    nprod = 3 if args.algo == "karatsuba" else 4
+    ops_launch = 2.0 * nprod * N * m * n * k
+    gemm_ms = prof["gemm_ms"] / max(1, prof["calls"])
+    achieved = ops_launch / (gemm_ms * 1e-3) / 1e12
+    extra_ops = 6.0 * m * n * k if args.mode == "accurate" else 0.0
+    util_e2e = (ops_launch + extra_ops) / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS
+    log(f"[bench] {ms:.2f} ms/step, {value:.1f} TFLOPS, gemm kernel {gemm_ms:.2f} ms "
+        f"({achieved:.0f} TOPS)")
+
+    # ---------------------------------------------------------- correctness gate on a sample
+    rng = np.random.default_rng(12345)
+    sr = np.unique(np.concatenate([[0, m - 1], rng.choice(m, size=min(m, args.sample_rows) - 2,
+                                                          replace=False)]))
+    sc = np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=min(n, args.sample_cols) - 2,
+                                                          replace=False)]))
+    A_rows = A[:, torch.from_numpy(sr).cuda()].T.cpu().numpy()      # op(A) rows (|sr| x k)
+    B_cols = B[torch.from_numpy(sc).cuda(), :].T.cpu().numpy()      # op(B) columns (k x |sc|)
+    C_smp = C[torch.from_numpy(sc).cuda()][:, torch.from_numpy(sr).cuda()].T.cpu().numpy()
+    parity = None
+    err = None
+    cpu = None
+    if args.mode == "fast":  # fast-mode exponents depend only on their own row/column
+        from oracle import core
+
+        log(f"[bench] CPU oracle on a {len(sr)}x{len(sc)} sample of the output (k={k})")
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        tc0 = time.perf_counter()
+        ref = core.emulate(A_rows, B_cols, N, args.mode, args.algo, single=args.single)["out"]
+        tc1 = time.perf_counter()
+        same = np.array_equal(ref, C_smp)
+        parity = {"entries": int(ref.size), "bit_exact": bool(same),
+                  "mismatches": int(np.sum(ref != C_smp))}
+        hi, lo = core.dd_gemm(A_rows, B_cols)
+        absab = core.abs_product(A_rows, B_cols)
+        err = core.err_nc(C_smp, hi, lo, absab)
+        if not args.no_cpu_baseline:
+            cpu = {"value": 8.0 * len(sr) * len(sc) * k / (tc1 - tc0) / 1e12, "unit": "TFLOPS",
+                   "cores": threads, "kind": "oracle",
+                   "sample": f"{len(sr)} rows x {len(sc)} columns of the {m}x{n}x{k} output "
+                             f"(full k, same inputs), {tc1 - tc0:.1f} s"}
+    bound = 4 * k * 2.0 ** -53 if not args.single else 4 * k * 2.0 ** -24
+
+    workload_key = f"{kind} {m}x{n}x{k} N={N} {args.mode} {args.algo}"
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"{kind} {m}x{n}x{k} {prec}, {N} moduli, {args.mode} mode, "
+                               f"{args.algo} products, phi={args.phi}, alpha=1, beta=0",
+                   "m": m, "n": n, "k": k, "moduli": N, "mode": args.mode, "algo": args.algo,
+                   "phi": args.phi, "precision": prec},
+        "int8_mfma_util": {"gemm_kernel": round(achieved / INT8_PEAK_TOPS, 4),
+                           "end_to_end": round(util_e2e, 4)},
+        "err_nc_sample": err,
+        "err_bound": bound,
+        "err_ok": (err is not None and err <= bound),
+        "parity_sample": parity,
+        "phase_ms": {key: round(prof[key] / max(1, prof["calls"]), 4)
+                     for key in ("scale_ms", "split_ms", "gemm_ms", "crt_ms", "total_ms")},
+        "roofline": {"bound": "mfma", "kernel": "residue_gemm_kernel",
+                     "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / INT8_PEAK_TOPS, 4),
+                     "traffic": traffic_from_profiles(workload_key)},
+        "cpu_baseline": cpu,
+        "workspace_gib": round(info["workspace"] / 2 ** 30, 2),
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,23 @@ typedef struct {
     double int8_ops;     /* INT8 MFMA operations of the residue products (2 per MAC)  */
 } ozc_info_t;
 
+/* Phase timing.  While enabled, every ozc_zgemm/ozc_cgemm call records HIP
+ * events on the handle's stream around its phases (scaling statistics and
+ * exponents; residue split; INT8 residue products; CRT reconstruction and
+ * output).  ozc_profile_read synchronises the stream, returns the sums over
+ * all calls since the previous read (or since enabling) and resets them. */
+typedef struct {
+    int calls;
+    double scale_ms;     /* Step III: statistics, bound product, exponents        */
+    double split_ms;     /* Steps IV, V-i/ii: truncation and residues             */
+    double gemm_ms;      /* Step V-iii/iv: INT8 products with the reduce epilogue */
+    double crt_ms;       /* Steps V-v, V-vi, VI                                   */
+    double total_ms;     /* first to last event of each call                      */
+} ozc_profile_t;
+
+ozc_status_t ozc_set_profiling(ozc_handle_t handle, int enable);
+ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
+
 /* Synchronises the handle's stream and reports on the last call.  Returns
  * NONFINITE when the last call met inf/NaN input (info still filled). */
 ozc_status_t ozc_last_info(ozc_handle_t handle, ozc_info_t *info);

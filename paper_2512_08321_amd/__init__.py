@@ -45,6 +45,11 @@ class Info(ctypes.Structure):
                 ("k", ctypes.c_int64), ("workspace", ctypes.c_size_t), ("int8_ops", ctypes.c_double)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int), ("scale_ms", ctypes.c_double), ("split_ms", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("crt_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 _VP, _I64, _INT = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
 _D2 = ctypes.c_double * 2
@@ -62,6 +67,8 @@ EXPORTS = {
     "ozc_inspect": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _VP,
                     _VP, _VP, _VP, _VP, _I64],
     "ozc_last_info": [_VP, ctypes.POINTER(Info)],
+    "ozc_set_profiling": [_VP, _INT],
+    "ozc_profile_read": [_VP, ctypes.POINTER(Profile)],
     "ozc_status_string": [_INT],
 }
 
@@ -157,6 +164,14 @@ class Handle:
                                  _ptr(A), lda, _ptr(B), ldb, _ptr(mu), _ptr(nu), _ptr(resA),
                                  _ptr(resB), _ptr(prods), _ptr(eprime), _ptr(C), ldc),
                "ozc_inspect")
+
+    def set_profiling(self, enable: bool):
+        _check(lib().ozc_set_profiling(self._h, int(bool(enable))), "ozc_set_profiling")
+
+    def profile_read(self) -> dict:
+        prof = Profile()
+        _check(lib().ozc_profile_read(self._h, ctypes.byref(prof)), "ozc_profile_read")
+        return {f: getattr(prof, f) for f, _ in Profile._fields_}
 
     def last_info(self, raise_nonfinite: bool = False) -> dict:
         info = Info()

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <array>
 #include <new>
 #include <vector>
 
@@ -25,6 +26,9 @@ struct ozc_context {
     std::vector<NTable> tab_host;
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
     ozc_info_t last{};
+    bool profiling = false;
+    std::vector<std::array<hipEvent_t, 5>> prof_pending;  // per call: phase boundaries
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -159,6 +163,34 @@ ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t 
     return OZC_STATUS_SUCCESS;
 }
 
+// Phase events of one call (a no-op unless profiling is enabled).
+struct PhaseEvents {
+    ozc_context *h;
+    std::array<hipEvent_t, 5> ev{};
+    bool on;
+    PhaseEvents(ozc_context *ctx) : h(ctx), on(ctx->profiling) {
+        if (!on) return;
+        for (auto &e : ev) {
+            if (!h->event_pool.empty()) {
+                e = h->event_pool.back();
+                h->event_pool.pop_back();
+            } else if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+        }
+    }
+    hipError_t mark(int i) { return on ? hipEventRecord(ev[i], h->stream) : hipSuccess; }
+    void commit() {
+        if (on) h->prof_pending.push_back(ev);
+        on = false;
+    }
+    ~PhaseEvents() {
+        if (on)
+            for (auto e : ev) h->event_pool.push_back(e);
+    }
+};
+
 struct InspectOut {
     int16_t *mu, *nu;
     int8_t *resA, *resB;
@@ -211,7 +243,10 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     const OperandView vA = view_A(A, ta, m, k, lda);
     const OperandView vB = view_B(B, tb, n, k, ldb);
 
+    PhaseEvents pe(h);
+    if (ins) pe.on = false;
     // Step III: scaling exponents
+    OZC_TRY(pe.mark(0));
     OZC_TRY(launch_fill_u64(maxA, L.m_pad, 0, s));
     OZC_TRY(launch_fill_u64(maxB, L.n_pad, 0, s));
     OZC_TRY(launch_row_maxabs(vA, single, maxA, s));
@@ -242,13 +277,16 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     if (nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
 
     // Steps IV, V-i/ii: truncation and residues
+    OZC_TRY(pe.mark(1));
     OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, nchunks, resA, L.m_pad, L.k_pad, s));
     OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, nchunks, resB, L.n_pad, L.k_pad, s));
 
     // Step V-iii/iv: INT8 products and their residues
+    OZC_TRY(pe.mark(2));
     GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, h->algo == OZC_ALGO_KARATSUBA ? 0 : 1,
                 tab, ep, prods};
     OZC_TRY(launch_residue_gemm(ga, s));
+    OZC_TRY(pe.mark(3));
 
     // Steps V-v, V-vi, VI
     if (C) {
@@ -272,6 +310,8 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         ca.single = single;
         OZC_TRY(launch_crt_output(ca, s));
     }
+    OZC_TRY(pe.mark(4));
+    pe.commit();
 
     if (ins) {
         if (ins->mu) OZC_TRY(hipMemcpyAsync(ins->mu, muA, 2 * (size_t)m, hipMemcpyDeviceToDevice, s));
@@ -349,6 +389,9 @@ ozc_status_t ozc_destroy(ozc_handle_t h) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    for (auto &ev : h->prof_pending)
+        for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
     if (h->ws_own) (void)hipFree(h->ws_own);
     (void)hipFree(h->tab_dev);
     (void)hipFree(h->status_dev);
@@ -413,6 +456,37 @@ ozc_status_t ozc_inspect(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, i
     const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
     InspectOut ins{mu, nu, resA, resB, prods, eprime};
     return run(h, single != 0, ta, tb, m, n, k, one, A, lda, B, ldb, zero, C, ldc, &ins);
+}
+
+ozc_status_t ozc_set_profiling(ozc_handle_t h, int enable) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    h->profiling = enable != 0;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_profile_read(ozc_handle_t h, ozc_profile_t *out) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!out) return OZC_STATUS_INVALID_VALUE;
+    *out = ozc_profile_t{};
+    if (hipSetDevice(h->device) != hipSuccess) return OZC_STATUS_HIP_ERROR;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return OZC_STATUS_HIP_ERROR;
+    ozc_status_t st = OZC_STATUS_SUCCESS;
+    for (auto &ev : h->prof_pending) {
+        float t[4] = {0, 0, 0, 0}, tot = 0;
+        bool ok = true;
+        for (int i = 0; i < 4; ++i) ok = ok && hipEventElapsedTime(&t[i], ev[i], ev[i + 1]) == hipSuccess;
+        ok = ok && hipEventElapsedTime(&tot, ev[0], ev[4]) == hipSuccess;
+        if (!ok) st = OZC_STATUS_HIP_ERROR;
+        out->calls += 1;
+        out->scale_ms += t[0];
+        out->split_ms += t[1];
+        out->gemm_ms += t[2];
+        out->crt_ms += t[3];
+        out->total_ms += tot;
+        for (auto e : ev) h->event_pool.push_back(e);
+    }
+    h->prof_pending.clear();
+    return st;
 }
 
 ozc_status_t ozc_last_info(ozc_handle_t h, ozc_info_t *info) {
