@@ -33,13 +33,14 @@ struct ozc_context {
 
 namespace {
 
-constexpr int64_t kTileM = 128, kTileN = 128, kTileK = 64;
+constexpr int64_t kTileK = 64;
 constexpr size_t kAlign = 256;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
+    int tile;
     int64_t m_pad, n_pad, k_pad;
     int planes, nprod;
     size_t maxA, maxB, sigA, sigB, XA, YB, muA, nuB, barA, barB, resA, resB, ep, prods, total;
@@ -47,8 +48,9 @@ struct Layout {
 
 Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool with_prods) {
     Layout L{};
-    L.m_pad = round_up(m > 0 ? m : 1, kTileM);
-    L.n_pad = round_up(n > 0 ? n : 1, kTileN);
+    L.tile = gemm_tile_for(m, n);
+    L.m_pad = round_up(m > 0 ? m : 1, L.tile);
+    L.n_pad = round_up(n > 0 ? n : 1, L.tile);
     L.k_pad = round_up(k > 0 ? k : 1, kTileK);
     L.planes = h->algo == OZC_ALGO_KARATSUBA ? 3 : 2;
     L.nprod = h->algo == OZC_ALGO_KARATSUBA ? 3 : 4;
@@ -266,7 +268,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         OZC_TRY(launch_fill_u64((uint64_t *)YB, L.n_pad / 2, 0, s));
         OZC_TRY(launch_ceil7(vA, single, maxA, barA, L.m_pad, L.k_pad, s));
         OZC_TRY(launch_ceil7(vB, single, maxB, barB, L.n_pad, L.k_pad, s));
-        BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB};
+        BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB, L.tile};
         OZC_TRY(launch_bound_gemm(ba, s));
         OZC_TRY(launch_accu_exponents(maxA, XA, m, L.m_pad, tab, muA, status, s));
         OZC_TRY(launch_accu_exponents(maxB, YB, n, L.n_pad, tab, nuB, status, s));
@@ -284,7 +286,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     // Step V-iii/iv: INT8 products and their residues
     OZC_TRY(pe.mark(2));
     GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, h->algo == OZC_ALGO_KARATSUBA ? 0 : 1,
-                tab, ep, prods};
+                tab, ep, prods, L.tile};
     OZC_TRY(launch_residue_gemm(ga, s));
     OZC_TRY(pe.mark(3));
 

@@ -82,8 +82,11 @@ struct GemmArgs {
     const NTable *tab;
     int8_t *eprime;       // [N][2][n_pad][m_pad]
     int32_t *prods;       // optional raw dump [N][nprod][n_pad][m_pad]
+    int tile;             // output tile edge (128 or 256); m_pad, n_pad are multiples
 };
 hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s);
+// Output tile edge used for an m x n product (the padding of every buffer follows it).
+int gemm_tile_for(int64_t m, int64_t n);
 
 // Accurate-mode bound product: X[i] = max_j max(Cbar_R, Cbar_I)_ij, Y[j] likewise.
 struct BoundArgs {
@@ -91,6 +94,7 @@ struct BoundArgs {
     const int8_t *B;      // [3][n_pad][k_pad]
     int64_t m_pad, n_pad, k_pad;
     int32_t *X, *Y;       // zero-initialised
+    int tile;
 };
 hipError_t launch_bound_gemm(const BoundArgs &a, hipStream_t s);
 

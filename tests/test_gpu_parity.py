@@ -90,6 +90,15 @@ def test_intermediates_bit_exact(handle, orc, mode, algo):
     _check_inspect(g, ref, algo)
 
 
+@pytest.mark.parametrize("mode,algo", [("fast", "karatsuba"), ("accurate", "4m")])
+def test_large_tile_path_bit_exact(handle, orc, mode, algo):
+    """m, n >= 1024 selects the 256 x 256 product tile; ragged edges in every dimension."""
+    A = workloads.complex_matrix(1100, 96, 2.0, 91)
+    B = workloads.complex_matrix(96, 1030, 2.0, 92)
+    g, ref = _run_inspect(handle, orc, A, B, 13, mode, algo)
+    _check_inspect(g, ref, algo)
+
+
 @pytest.mark.parametrize("ta,tb", [("N", "T"), ("T", "N"), ("C", "C"), ("T", "C"), ("C", "N")])
 def test_transpose_ops(handle, orc, ta, tb):
     A = workloads.complex_matrix(131, 77, 2.0, 21)
