@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--sample-rows", type=int, default=512)
     ap.add_argument("--sample-cols", type=int, default=1536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -102,6 +104,15 @@ def main():
     B = workloads.complex_matrix_torch(k, n, args.phi, workloads.seed_for(cfg_id, 0, "B"), cdt)
     C = torch.zeros((n, m), dtype=cdt, device="cuda")  # column-major m x n
     torch.cuda.synchronize()
+
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * 2 ** 30)
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb} bytes done")
+        del src, dst
 
     h = ozc.Handle(0, num_moduli=N, mode=args.mode, algo=args.algo)
     call = h.cgemm if args.single else h.zgemm

@@ -20,7 +20,7 @@ __all__ = ["Handle", "OzcError", "gemm", "lib", "OP", "MODE", "ALGO", "MAX_K", "
            "MAX_MODULI", "EXP_ZERO", "EXP_NONFINITE", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-library_path = os.path.join(_HERE, "libozc.so")
+library_path = os.environ.get("OZC_LIBRARY") or os.path.join(_HERE, "libozc.so")
 
 OP = {"N": 0, "T": 1, "C": 2}
 MODE = {"fast": 0, "accurate": 1}

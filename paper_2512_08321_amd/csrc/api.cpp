@@ -33,7 +33,6 @@ struct ozc_context {
 
 namespace {
 
-constexpr int64_t kTileK = 64;
 constexpr size_t kAlign = 256;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -51,7 +50,7 @@ Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool w
     L.tile = gemm_tile_for(m, n);
     L.m_pad = round_up(m > 0 ? m : 1, L.tile);
     L.n_pad = round_up(n > 0 ? n : 1, L.tile);
-    L.k_pad = round_up(k > 0 ? k : 1, kTileK);
+    L.k_pad = round_up(k > 0 ? k : 1, gemm_kstep_for(L.tile));
     L.planes = h->algo == OZC_ALGO_KARATSUBA ? 3 : 2;
     L.nprod = h->algo == OZC_ALGO_KARATSUBA ? 3 : 4;
     const size_t N = (size_t)h->nmod;

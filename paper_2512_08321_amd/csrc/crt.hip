@@ -31,7 +31,7 @@ __device__ __forceinline__ void normalize(int32_t (&a)[L]) {
 
 // After normalize(): value >= 0  <=>  top limb >= 0.
 template <int L>
-__device__ __noinline__ void settle_range(int32_t (&a)[L], const NTable *tab) {
+__device__ __forceinline__ void settle_range(int32_t (&a)[L], const NTable *tab) {
     int32_t t[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) t[j] = 2 * a[j] - tab->Plimb[j];
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int64_t i = ib + u;
-        if (i >= a.m) break;
+        if (i >= a.m) continue;
         const int mui = a.mu[i];
         double cr, ci;
         if (mui == kExpNonfinite || nuj == kExpNonfinite) {

@@ -29,6 +29,8 @@
 // product does not depend on how the hardware orders k inside the 32-wide
 // step.  Accumulator register r of lane l holds row 8(r/4) + 4(l/32) + (r mod 4),
 // column (l mod 32).
+#include <utility>
+
 #include "internal.h"
 
 namespace ozc {
@@ -74,7 +76,25 @@ __device__ __forceinline__ uint32_t pack4(const int (&v)[4]) {
 
 __device__ __forceinline__ int byte_of(uint32_t w, int u) { return (int)(int8_t)(w >> (8 * u)); }
 
-__device__ __forceinline__ int swz(int row, int seg) { return row * 4 + (seg ^ ((row >> 1) & 3)); }
+// LDS tile layout: 64-byte rows of four 16-byte granules; granule g of row r is
+// stored at position g ^ sw(r).  With sw(r) = r2 | (r1 ^ r3) << 1 (ri = bit i of
+// r), 8 and 16 consecutive rows read at one granule position hit distinct bank
+// groups (32- and 64-bank LDS), and so do the row-major 16-byte stores.
+__device__ __forceinline__ int swz_bits(int row) {
+    return ((row >> 2) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1);
+}
+__device__ __forceinline__ int swz(int row, int seg) { return row * 4 + (seg ^ swz_bits(row)); }
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1, so that
+// register arrays are only ever indexed by constants.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ __forceinline__ void map_tile(int64_t L, int64_t TR, int64_t TC, int64_t total, int &l,
                                          int64_t &ti, int64_t &tj) {
@@ -91,24 +111,58 @@ __device__ __forceinline__ void map_tile(int64_t L, int64_t TR, int64_t TC, int6
     tj = rem / rows;
 }
 
-template <int WM_, int WN_, int BM_, int BN_>
+// WM x WN waves of BM x BN blocks; KS 64-byte k sub-slabs per pipeline stage.
+// DMA: k-slabs are copied global -> LDS by the load units directly (gfx950
+// global_load_lds_dwordx4) into a ring of NSTAGE buffers, NSTAGE - 1 slabs
+// ahead of the matrix cores; otherwise they are staged through registers
+// one slab ahead into two LDS buffers.
+template <int WM_, int WN_, int BM_, int BN_, int KS_, int DMA_ = 0>
 struct TileCfg {
-    static constexpr int WM = WM_, WN = WN_, BM = BM_, BN = BN_;
+    static constexpr int WM = WM_, WN = WN_, BM = BM_, BN = BN_, KS = KS_;
+    static constexpr bool DMA = DMA_ != 0;
+    static constexpr int NSTAGE = DMA ? 4 : 2;
     static constexpr int TM = WM * BM * 32, TN = WN * BN * 32;
     static constexpr int THREADS = 64 * WM * WN;
-    static constexpr int NLA = TM * 4 / THREADS;  // 16-byte loads per thread per k-step (A)
+    static constexpr int NLA = TM * 4 / THREADS;  // 16-byte loads per thread per sub-slab (A)
     static constexpr int NLB = TN * 4 / THREADS;  // (B)
     static constexpr int ROWS_PER_LOAD = THREADS / 4;
+    static constexpr int STAGE = (TM + TN) * 4;   // uint4 per sub-slab in LDS
+    static constexpr int KSTEP = BK * KS;
 };
-using CfgLarge = TileCfg<2, 4, 4, 2>;  // 256 x 256, 512 threads
-using CfgSmall = TileCfg<2, 2, 2, 2>;  // 128 x 128, 256 threads
+#ifndef OZC_LARGE_CFG
+#define OZC_LARGE_CFG 2, 4, 4, 2, 1, 1
+#endif
+using CfgLarge = TileCfg<OZC_LARGE_CFG>;  // 256 x 256 output tiles
+using CfgSmall = TileCfg<2, 2, 2, 2, 1>;  // 128 x 128, 256 threads
+
+__device__ __forceinline__ uint4 ld16(const int8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+// One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS
+// starting at lds_base (lane i -> lds_base + 16 i).  Issued as inline
+// assembly so that the compiler does not serialise later LDS reads behind it;
+// completion is tracked explicitly with vmcnt_wait() before the barrier.
+// M0 is written only here in these kernels (checked in the generated code); the
+// clobber entry documents it although the compiler treats M0 as reserved.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(const int8_t *g, uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g),
+                 "s"(lds_base)
+                 : "memory", "m0");
+}
+#pragma clang diagnostic pop
+template <int N>
+__device__ __forceinline__ void vmcnt_wait() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void block_barrier() { __builtin_amdgcn_s_barrier(); }
 
 template <int KIND, typename C, bool DUMP>
 __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, BoundArgs b) {
     using P = Plan<KIND>;
-    constexpr int TM = C::TM, TN = C::TN, BM = C::BM, BN = C::BN;
+    constexpr int TM = C::TM, TN = C::TN, BM = C::BM, BN = C::BN, KS = C::KS;
     constexpr int WTM = BM * 32, WTN = BN * 32;  // wave tile
-    __shared__ uint4 lds[2][(TM + TN) * 4];
+    __shared__ uint4 lds[C::NSTAGE][KS * C::STAGE];  // [buffer][sub-slab][A rows, B rows]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % C::WM, wn = wave / C::WM;
@@ -129,14 +183,14 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
     const int8_t *baseB = (bound ? b.B : a.B) + (int64_t)l * P::nplanes * planeB + j0 * k_pad;
 
     const int lrow = tid >> 2, lseg = tid & 3;
-    const int nk = (int)(k_pad / BK);
+    const int nk = (int)(k_pad / C::KSTEP);
     const int64_t rstep = (int64_t)C::ROWS_PER_LOAD * k_pad;
+    constexpr int NLA = C::NLA, NLB = C::NLB;
 
     ModConst mc;
     if constexpr (!bound) mc = a.tab->mod[l];
     const int64_t planeC = bound ? 0 : a.n_pad * a.m_pad;
 
-    uint32_t keep[BM][BN][4];
     v16i acc[BM][BN];
 
 #pragma unroll 1
@@ -144,144 +198,216 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
         const int8_t *Ap = baseA + (int64_t)P::pa(sgi) * planeA + (int64_t)lrow * k_pad + lseg * 16;
         const int8_t *Bp = baseB + (int64_t)P::pb(sgi) * planeB + (int64_t)lrow * k_pad + lseg * 16;
         if (!bound || sgi == 0) {
-#pragma unroll
-            for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < BN; ++bj) acc[bi][bj] = v16i{};
+            static_for<BM>([&](auto bi) { static_for<BN>([&](auto bj) { acc[bi][bj] = v16i{}; }); });
         }
-        // two 16-byte loads per thread per operand and k-step (both tile shapes);
-        // named registers rather than arrays keep them out of scratch memory
-        static_assert(C::NLA == 2 && C::NLB == 2, "loader assumes two loads per operand");
-        const int r1 = lrow + C::ROWS_PER_LOAD;
-        uint4 ra0 = *reinterpret_cast<const uint4 *>(Ap);
-        uint4 ra1 = *reinterpret_cast<const uint4 *>(Ap + rstep);
-        uint4 rb0 = *reinterpret_cast<const uint4 *>(Bp);
-        uint4 rb1 = *reinterpret_cast<const uint4 *>(Bp + rstep);
-        lds[0][swz(lrow, lseg)] = ra0;
-        lds[0][swz(r1, lseg)] = ra1;
-        lds[0][TM * 4 + swz(lrow, lseg)] = rb0;
-        lds[0][TM * 4 + swz(r1, lseg)] = rb1;
-        __syncthreads();
-
-        for (int s = 0; s < nk; ++s) {
-            const int cur = s & 1;
-            const bool more = s + 1 < nk;
-            if (more) {
-                const int64_t ko = (int64_t)(s + 1) * BK;
-                ra0 = *reinterpret_cast<const uint4 *>(Ap + ko);
-                ra1 = *reinterpret_cast<const uint4 *>(Ap + rstep + ko);
-                rb0 = *reinterpret_cast<const uint4 *>(Bp + ko);
-                rb1 = *reinterpret_cast<const uint4 *>(Bp + rstep + ko);
-            }
-            const uint4 *LA = lds[cur];
-            const uint4 *LB = lds[cur] + TM * 4;
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const int seg = kk * 2 + (lane >> 5);
-                v4i fa[BM], fb[BN];
-#pragma unroll
-                for (int bi = 0; bi < BM; ++bi) {
-                    const uint4 t = LA[swz(wm * WTM + bi * 32 + (lane & 31), seg)];
-                    fa[bi] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
-                }
-#pragma unroll
-                for (int bj = 0; bj < BN; ++bj) {
-                    const uint4 t = LB[swz(wn * WTN + bj * 32 + (lane & 31), seg)];
-                    fb[bj] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
-                }
-#pragma unroll
-                for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < BN; ++bj)
-                        acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[bi], fb[bj],
-                                                                           acc[bi][bj], 0, 0, 0);
-            }
-            if (more) {
-                lds[cur ^ 1][swz(lrow, lseg)] = ra0;
-                lds[cur ^ 1][swz(r1, lseg)] = ra1;
-                lds[cur ^ 1][TM * 4 + swz(lrow, lseg)] = rb0;
-                lds[cur ^ 1][TM * 4 + swz(r1, lseg)] = rb1;
-            }
+        // Fragments of one 32-wide half (kk) of a 64-wide k-slab held in LDS buffer Lbuf.
+        auto read_frags = [&](const uint4 *Lbuf, int kk, v4i (&fa)[BM], v4i (&fb)[BN]) {
+            // fragment rows are (multiple of 32) + (lane mod 32): the swizzle depends on the lane only
+            const int g = (kk * 2 + (lane >> 5)) ^ swz_bits(lane & 31);
+            const uint4 *FA = Lbuf + (wm * WTM + (lane & 31)) * 4 + g;
+            const uint4 *FB = Lbuf + TM * 4 + (wn * WTN + (lane & 31)) * 4 + g;
+            static_for<BM>([&](auto bi) {
+                const uint4 t = FA[bi * 32 * 4];
+                fa[bi] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            });
+            static_for<BN>([&](auto bj) {
+                const uint4 t = FB[bj * 32 * 4];
+                fb[bj] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            });
+        };
+        auto mfmas = [&](const v4i (&fa)[BM], const v4i (&fb)[BN]) {
+            static_for<BM>([&](auto bi) {
+                static_for<BN>([&](auto bj) {
+                    acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[bi], fb[bj], acc[bi][bj], 0, 0, 0);
+                });
+            });
+        };
+        auto compute = [&](const uint4 *Lbuf) {
+            static_for<KS>([&](auto ks) {
+                static_for<2>([&](auto kk) {
+                    v4i fa[BM], fb[BN];
+                    read_frags(Lbuf + ks * C::STAGE, kk, fa, fb);
+                    mfmas(fa, fb);
+                });
+            });
+        };
+        if constexpr (C::DMA) {
+            // Each wave fills whole 1 KB chunks (16 rows) of the A and B slabs: lane i of a
+            // chunk writes LDS granule i, i.e. row 16c + i/4 at position i mod 4, which holds
+            // the swizzled global granule (i mod 4) ^ swz_bits(row).  A ring stage holds KS
+            // consecutive 64-wide k-slabs.
+            constexpr int CA = TM / 16, CB = TN / 16, NW = C::WM * C::WN;
+            static_assert(CA % NW == 0 && CB % NW == 0, "chunks per wave");
+            // a stage is waited for one stage before it is consumed and issued AHEAD >= 2
+            // stages ahead, so its buffer was released by the barrier of the stage before
+            static_assert(C::NSTAGE >= 3, "DMA ring needs at least three buffers");
+            constexpr int QA = CA / NW, QB = CB / NW, NLOAD = KS * (QA + QB);  // loads per wave per stage
+            const int crow = lane >> 2;
+            const int cg = (lane & 3) ^ swz_bits(crow);  // chunk rows start at multiples of 16
+            const int8_t *pa = baseA + (int64_t)P::pa(sgi) * planeA + (int64_t)crow * k_pad + cg * 16;
+            const int8_t *pb = baseB + (int64_t)P::pb(sgi) * planeB + (int64_t)crow * k_pad + cg * 16;
+            const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint4 *)(&lds[0][0]);
+            auto issue = [&](int st) {  // ring stage st -> buffer st % NSTAGE
+                const uint32_t buf = lbase + (uint32_t)((st % C::NSTAGE) * KS * C::STAGE * 16);
+                static_for<KS>([&](auto ks) {
+                    const int64_t ko = (int64_t)st * C::KSTEP + ks * BK;
+                    const uint32_t sb = buf + (uint32_t)(ks * C::STAGE * 16);
+                    static_for<QA>([&](auto q) {
+                        const int c = wave * QA + q;
+                        dma16(pa + (int64_t)c * 16 * k_pad + ko, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(c * 1024)));
+                    });
+                    static_for<QB>([&](auto q) {
+                        const int c = wave * QB + q;
+                        dma16(pb + (int64_t)c * 16 * k_pad + ko,
+                              __builtin_amdgcn_readfirstlane(sb + (uint32_t)(TM * 64 + c * 1024)));
+                    });
+                });
+            };
+            // Software pipeline over half-slabs (32-wide k): the fragments of the next half
+            // are read while the current half's matrix instructions run.  The one barrier
+            // per stage sits before the last half's MFMAs, after the wait for the next
+            // stage, so queued MFMAs keep the matrix pipe busy while the waves meet; after
+            // it the oldest buffer is free and receives the stage AHEAD steps ahead.
+            constexpr int AHEAD = C::NSTAGE - 1, NH = 2 * KS;
+            static_for<AHEAD>([&](auto st) {
+                if (st < nk) issue(st);
+            });
+            if (nk > 2 && AHEAD >= 3) vmcnt_wait<2 * NLOAD>();
+            else if (nk > 1 && AHEAD >= 2) vmcnt_wait<NLOAD>();
+            else vmcnt_wait<0>();
+            block_barrier();
+            v4i fa[2][BM], fb[2][BN];
+            read_frags(lds[0], 0, fa[0], fb[0]);
+            auto stage = [&](int s, bool handover, auto wait_tag) {
+                const uint4 *cur = lds[s % C::NSTAGE];
+                static_for<NH>([&](auto h) {
+                    constexpr int nb = (h + 1) & 1;
+                    if constexpr (h + 1 < NH) {
+                        read_frags(cur + ((h + 1) / 2) * C::STAGE, (h + 1) & 1, fa[nb], fb[nb]);
+                    } else {
+                        if (handover) {
+                            vmcnt_wait<decltype(wait_tag)::value>();
+                            block_barrier();  // stage s+1 visible; stage s-1's buffer free
+                            if (s + AHEAD < nk) issue(s + AHEAD);
+                            read_frags(lds[(s + 1) % C::NSTAGE], 0, fa[0], fb[0]);
+                        }
+                    }
+                    mfmas(fa[h & 1], fb[h & 1]);
+                });
+            };
+            // stages issued after stage s+1 when it is awaited: min(AHEAD - 2, nk - 2 - s)
+            constexpr int LATER = AHEAD >= 2 ? AHEAD - 2 : 0;
+            int s = 0;
+            for (; s + 1 + LATER < nk; ++s) stage(s, true, std::integral_constant<int, LATER * NLOAD>{});
+            for (; s + 1 < nk; ++s) stage(s, true, std::integral_constant<int, 0>{});
+            stage(s, false, std::integral_constant<int, 0>{});
+            block_barrier();  // all waves done with the ring before it is refilled
+        } else {
+            uint4 ra[KS * NLA], rb[KS * NLB];
+            auto gload = [&](int64_t ko) {
+                static_for<KS>([&](auto ks) {
+                    static_for<NLA>([&](auto q) { ra[ks * NLA + q] = ld16(Ap + q * rstep + ko + ks * BK); });
+                    static_for<NLB>([&](auto q) { rb[ks * NLB + q] = ld16(Bp + q * rstep + ko + ks * BK); });
+                });
+            };
+            // rows handled by one thread differ by multiples of 16, so they share swz_bits
+            auto lstore = [&](uint4 *L) {
+                uint4 *Ls = L + lrow * 4 + (lseg ^ swz_bits(lrow));
+                static_for<KS>([&](auto ks) {
+                    static_for<NLA>([&](auto q) { Ls[ks * C::STAGE + q * C::ROWS_PER_LOAD * 4] = ra[ks * NLA + q]; });
+                    static_for<NLB>([&](auto q) {
+                        Ls[ks * C::STAGE + TM * 4 + q * C::ROWS_PER_LOAD * 4] = rb[ks * NLB + q];
+                    });
+                });
+            };
+            gload(0);
+            lstore(lds[0]);
             __syncthreads();
+
+            for (int s = 0; s < nk; ++s) {
+                const int cur = s & 1;
+                const bool more = s + 1 < nk;
+                if (more) gload((int64_t)(s + 1) * C::KSTEP);
+                compute(lds[cur]);
+                if (more) lstore(lds[cur ^ 1]);
+                __syncthreads();
+            }
         }
 
         // ------------------------------------------------ per-product epilogue
+        // (compile-time loops only: the accumulators must stay in registers)
         if constexpr (DUMP) {
             int32_t *D = a.prods + ((int64_t)l * P::nseg + sgi) * planeC;
-#pragma unroll
-            for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < BN; ++bj)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
+            static_for<BM>([&](auto bi) {
+                static_for<BN>([&](auto bj) {
+                    static_for<16>([&](auto r) {
                         const int64_t i = i0 + wm * WTM + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                         const int64_t j = j0 + wn * WTN + bj * 32 + (lane & 31);
-                        D[j * a.m_pad + i] = acc[bi][bj][r];
-                    }
+                        D[j * a.m_pad + i] = acc[bi][bj][(int)r];
+                    });
+                });
+            });
         }
         if constexpr (bound) {
             if (sgi >= 1) {  // acc holds Cbar_I after the second product, Cbar_R after the third
-#pragma unroll
-                for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        int x = acc[bi][0][r];
-#pragma unroll
-                        for (int bj = 1; bj < BN; ++bj) x = max(x, acc[bi][bj][r]);
+                static_for<BM>([&](auto bi) {
+                    static_for<16>([&](auto r) {
+                        int x = acc[bi][0][(int)r];
+                        static_for<BN>([&](auto bj) { x = max(x, acc[bi][bj][(int)r]); });
 #pragma unroll
                         for (int off = 16; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
                         if ((lane & 31) == 0 && x > 0) {
                             const int64_t i = i0 + wm * WTM + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                             atomicMax(&b.X[i], x);
                         }
-                    }
-#pragma unroll
-                for (int bj = 0; bj < BN; ++bj) {
+                    });
+                });
+                static_for<BN>([&](auto bj) {
                     int y = 0;
-#pragma unroll
-                    for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) y = max(y, acc[bi][bj][r]);
+                    static_for<BM>([&](auto bi) { static_for<16>([&](auto r) { y = max(y, acc[bi][bj][(int)r]); }); });
                     y = max(y, __shfl_xor(y, 32, 64));
                     if (lane < 32 && y > 0) atomicMax(&b.Y[j0 + wn * WTN + bj * 32 + lane], y);
-                }
+                });
             }
         } else {
+            // The residue carried from one product to the next (mod(D) then mod(D + E) for
+            // Karatsuba, mod(RR) and mod(RI) for the expanded form) is parked in this
+            // thread's own E'_I words, which receive the final E'_I last; each lane
+            // re-reads only what it wrote, so no synchronisation is needed.
             int8_t *ER = a.eprime + (int64_t)l * 2 * planeC;
             int8_t *EI = ER + planeC;
-            const bool karatsuba = KIND == KIND_KARATSUBA;
-#pragma unroll
-            for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < BN; ++bj)
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
+            constexpr bool karatsuba = KIND == KIND_KARATSUBA;
+            static_for<BM>([&](auto bi) {
+                static_for<BN>([&](auto bj) {
+                    static_for<4>([&](auto g) {
                         const int64_t i = i0 + wm * WTM + bi * 32 + 8 * g + 4 * (lane >> 5);
                         const int64_t j = j0 + wn * WTN + bj * 32 + (lane & 31);
+                        uint32_t *er = reinterpret_cast<uint32_t *>(ER + j * a.m_pad + i);
+                        uint32_t *ei = reinterpret_cast<uint32_t *>(EI + j * a.m_pad + i);
                         int v[4], o[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) v[u] = reduce_acc(acc[bi][bj][4 * g + u], mc);
-                        const uint32_t w = keep[bi][bj][g];
+                        static_for<4>([&](auto u) { v[u] = reduce_acc(acc[bi][bj][4 * (int)g + (int)u], mc); });
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
-                            keep[bi][bj][g] = pack4(v);
+                            *ei = pack4(v);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) o[u] = reduce_acc(byte_of(w, u) - v[u], mc);
-                            *reinterpret_cast<uint32_t *>(ER + j * a.m_pad + i) = pack4(o);
-                            if (karatsuba) {
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) o[u] = reduce_acc(byte_of(w, u) + v[u], mc);
-                                keep[bi][bj][g] = pack4(o);
+                            const uint32_t w = *ei;
+                            static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) - v[u], mc); });
+                            *er = pack4(o);
+                            if constexpr (karatsuba) {
+                                static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) + v[u], mc); });
+                                *ei = pack4(o);
                             }
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
+                            const uint32_t w = *ei;
+                            static_for<4>([&](auto u) {
                                 o[u] = reduce_acc(karatsuba ? v[u] - byte_of(w, u) : byte_of(w, u) + v[u], mc);
-                            *reinterpret_cast<uint32_t *>(EI + j * a.m_pad + i) = pack4(o);
+                            });
+                            *ei = pack4(o);
                         }
-                    }
+                    });
+                });
+            });
         }
     }
 }
@@ -295,10 +421,12 @@ void launch_kind(const GemmArgs &a, const BoundArgs &b, bool dump, int64_t block
 }  // namespace
 
 int gemm_tile_for(int64_t m, int64_t n) { return (m >= 1024 && n >= 1024) ? 256 : 128; }
+int gemm_kstep_for(int tile) { return tile == 256 ? CfgLarge::KSTEP : CfgSmall::KSTEP; }
 
 hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s) {
     const int tile = a.tile;
-    if ((tile != 128 && tile != 256) || a.m_pad % tile || a.n_pad % tile || a.k_pad % BK || a.nmod < 1)
+    if ((tile != 128 && tile != 256) || a.m_pad % tile || a.n_pad % tile ||
+        a.k_pad % gemm_kstep_for(tile) || a.nmod < 1)
         return hipErrorInvalidValue;
     const int64_t blocks = (int64_t)a.nmod * (a.m_pad / tile) * (a.n_pad / tile);
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;

@@ -87,6 +87,8 @@ struct GemmArgs {
 hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s);
 // Output tile edge used for an m x n product (the padding of every buffer follows it).
 int gemm_tile_for(int64_t m, int64_t n);
+// k padding granule of the product kernel for a tile edge (every buffer's k_pad follows it).
+int gemm_kstep_for(int tile);
 
 // Accurate-mode bound product: X[i] = max_j max(Cbar_R, Cbar_I)_ij, Y[j] likewise.
 struct BoundArgs {
