@@ -79,7 +79,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the emulation shards by output blocks with no communication; see DESIGN.md)",
+              "(the emulation shards by output blocks of C with no communication)",
               file=sys.stderr)
         sys.exit(2)
 

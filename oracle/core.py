@@ -214,13 +214,16 @@ def crt_output(Ep, mu, fa, nu, fb, n_moduli, alpha=1.0, beta=0.0, Cin=None, want
 
 
 def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, C=None,
-            single=False, want_raw=False, want_cp=False, exponents=None):
+            single=False, want_raw=False, want_cp=False, exponents=None, fault=0):
     """alpha * A @ B + beta * C by the complex Ozaki-II scheme, computed exactly.
 
     A: (m, k) op(A); B: (k, n) op(B).  ``single`` rounds the result to
     complex64 (CGEMM: inputs promoted exactly, output rounded once more).
     ``exponents`` may carry precomputed (mu, fa, nu, fb) (e.g. for sampled
     entries of a large accurate-mode problem).
+    ``fault`` = 1 plants a mistake for tests of the verification step: the
+    real part of E'_1 at entry (0, 0) has its bits 0x5a flipped before the
+    reconstruction.
     Returns a dict of the intermediates and ``out``.
     """
     Are, Aim = rows_of_A(A)
@@ -237,6 +240,10 @@ def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, 
     resA = residues(Are, Aim, mu, fa, n_moduli)
     resB = residues(Bre, Bim, nu, fb, n_moduli)
     Ep, raw = products(resA, resB, n_moduli, algo, want_raw)
+    if fault == 1 and Ep.size:
+        Ep[0, 0, 0, 0] = np.int8(Ep[0, 0, 0, 0] ^ np.int8(0x5A))
+    elif fault:
+        raise ValueError(fault)
     Cin = None if C is None else np.asarray(C, dtype=np.complex128)
     al, be = complex(alpha), complex(beta)
     if single:

@@ -17,7 +17,7 @@ The steps follow the paper (arXiv 2512.08321):
 * Section III-B: fast-mode scaling (Cauchy-Schwarz bound) and accurate-mode
   scaling (an extra product of 7-bit ceiling matrices).
 
-Readings of passages that the paper leaves open (each is listed in the design doc):
+Readings of passages that the paper leaves open:
 
 * The moduli are the greedy descending pairwise-coprime integers <= 256, in
   that order; the first N are used.
