@@ -55,7 +55,8 @@ typedef enum {
     OZC_STATUS_ALLOC_FAILED = 3,    /* device allocation of the workspace failed          */
     OZC_STATUS_HIP_ERROR = 4,       /* a HIP runtime call or kernel launch failed          */
     OZC_STATUS_NONFINITE = 5,       /* reported by ozc_last_info: an input was inf or NaN  */
-    OZC_STATUS_INVALID_HANDLE = 6
+    OZC_STATUS_INVALID_HANDLE = 6,
+    OZC_STATUS_VERIFY_FAILED = 7    /* the Freivalds check still failed at the largest N */
 } ozc_status_t;
 
 typedef enum { OZC_OP_N = 0, OZC_OP_T = 1, OZC_OP_C = 2 } ozc_op_t;
@@ -159,7 +160,34 @@ typedef struct {
     int64_t m, n, k;     /* shape of the last call                                   */
     size_t workspace;    /* bytes of workspace the last call used                    */
     double int8_ops;     /* INT8 MFMA operations of the residue products (2 per MAC)  */
+    int verified;        /* 1 if the last call ran the Freivalds check                */
+    int escalations;     /* reruns with more moduli after a failed check             */
+    int64_t verify_failed_rows; /* rows over tolerance in the final check             */
+    double verify_ratio; /* max_i |residual_i| / tolerance_i of the final check       */
 } ozc_info_t;
+
+/* Freivalds verification (an addition of this library, not in the paper).
+ * When enabled, every ozc_zgemm/ozc_cgemm call checks its result with one
+ * random sign vector x (x_j = +-1 from SplitMix64(seed, j)):
+ *   w = C x,  z = op(A) (op(B) x),  v = C_in x  (v only when beta != 0),
+ *   accepted iff for every row i
+ *   |w_i - alpha z_i - beta v_i| <= rel (|alpha| (|A||B||x|)_i + |beta| (|C_in||x|)_i)
+ *                                    + g (|C||x| + |alpha| |A||B||x| + |beta| |C_in||x|)_i
+ * with g = 4 (n + k + 4) 2^-53 covering the double-precision evaluation.  rel <= 0
+ * selects 4 k 2^-53 for ZGEMM and 4 k 2^-24 for CGEMM.  On failure, with
+ * escalate != 0, the call reruns with N + 2 moduli (at most OZC_MAX_MODULI;
+ * C_in is saved first when beta != 0) and finally returns
+ * OZC_STATUS_VERIFY_FAILED with C holding the last result.  A verified call
+ * synchronises the stream.  Extra device memory: O(m + n + k) vectors, plus
+ * m x n elements when beta != 0. */
+ozc_status_t ozc_set_verify(ozc_handle_t handle, int enable, double rel, int escalate,
+                            uint64_t seed);
+
+/* Test hook that corrupts the pipeline on purpose so that the check above can
+ * be exercised: 0 none; 1 flip one byte of E' (modulus 1, entry (0,0)) on the
+ * first attempt of each call only; 2 raise the exponent of row 0 of op(A) by
+ * 12 on every attempt (breaks the uniqueness condition (4) for that row). */
+ozc_status_t ozc_debug_inject(ozc_handle_t handle, int fault);
 
 /* Phase timing.  While enabled, every ozc_zgemm/ozc_cgemm call records HIP
  * events on the handle's stream around its phases (scaling statistics and

@@ -30,7 +30,7 @@ MIN_MODULI, MAX_MODULI = 2, 24
 EXP_ZERO, EXP_NONFINITE = -32768, 32767
 
 STATUS = {0: "success", 1: "invalid value", 2: "not supported", 3: "device allocation failed",
-          4: "HIP runtime error", 5: "non-finite input", 6: "invalid handle"}
+          4: "HIP runtime error", 5: "non-finite input", 6: "invalid handle", 7: "verification failed"}
 
 
 class OzcError(RuntimeError):
@@ -42,7 +42,9 @@ class OzcError(RuntimeError):
 class Info(ctypes.Structure):
     _fields_ = [("num_moduli", ctypes.c_int), ("mode", ctypes.c_int), ("algo", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
-                ("k", ctypes.c_int64), ("workspace", ctypes.c_size_t), ("int8_ops", ctypes.c_double)]
+                ("k", ctypes.c_int64), ("workspace", ctypes.c_size_t), ("int8_ops", ctypes.c_double),
+                ("verified", ctypes.c_int), ("escalations", ctypes.c_int),
+                ("verify_failed_rows", ctypes.c_int64), ("verify_ratio", ctypes.c_double)]
 
 
 class Profile(ctypes.Structure):
@@ -69,6 +71,8 @@ EXPORTS = {
     "ozc_last_info": [_VP, ctypes.POINTER(Info)],
     "ozc_set_profiling": [_VP, _INT],
     "ozc_profile_read": [_VP, ctypes.POINTER(Profile)],
+    "ozc_set_verify": [_VP, _INT, ctypes.c_double, _INT, ctypes.c_uint64],
+    "ozc_debug_inject": [_VP, _INT],
     "ozc_status_string": [_INT],
 }
 
@@ -164,6 +168,14 @@ class Handle:
                                  _ptr(A), lda, _ptr(B), ldb, _ptr(mu), _ptr(nu), _ptr(resA),
                                  _ptr(resB), _ptr(prods), _ptr(eprime), _ptr(C), ldc),
                "ozc_inspect")
+
+    def set_verify(self, enable: bool = True, rel: float = 0.0, escalate: bool = True,
+                   seed: int = 0x5EED):
+        _check(lib().ozc_set_verify(self._h, int(bool(enable)), float(rel), int(bool(escalate)),
+                                    int(seed)), "ozc_set_verify")
+
+    def debug_inject(self, fault: int):
+        _check(lib().ozc_debug_inject(self._h, int(fault)), "ozc_debug_inject")
 
     def set_profiling(self, enable: bool):
         _check(lib().ozc_set_profiling(self._h, int(bool(enable))), "ozc_set_profiling")

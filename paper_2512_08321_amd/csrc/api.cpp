@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <new>
 #include <vector>
@@ -27,6 +28,15 @@ struct ozc_context {
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
     ozc_info_t last{};
     bool profiling = false;
+    // verification
+    bool verify = false;
+    bool escalate = true;
+    double verify_rel = 0.0;
+    uint64_t verify_seed = 0x5eed;
+    void *vws = nullptr;
+    size_t vws_bytes = 0;
+    int fault = 0;
+    int attempt = 0;
     std::vector<std::array<hipEvent_t, 5>> prof_pending;  // per call: phase boundaries
     std::vector<hipEvent_t> event_pool;
 };
@@ -246,6 +256,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
 
     PhaseEvents pe(h);
     if (ins) pe.on = false;
+    const int fault = h->fault;
     // Step III: scaling exponents
     OZC_TRY(pe.mark(0));
     OZC_TRY(launch_fill_u64(maxA, L.m_pad, 0, s));
@@ -273,6 +284,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         OZC_TRY(launch_accu_exponents(maxB, YB, n, L.n_pad, tab, nuB, status, s));
         abits = th.max_abits_accu;
     }
+    if (fault == 2) OZC_TRY(launch_debug_add_exp(muA, 12, s));
     int nchunks = (abits + kChunkBits - 1) / kChunkBits;
     if (nchunks < 1) nchunks = 1;
     if (nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
@@ -287,6 +299,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, h->algo == OZC_ALGO_KARATSUBA ? 0 : 1,
                 tab, ep, prods, L.tile};
     OZC_TRY(launch_residue_gemm(ga, s));
+    if (fault == 1 && h->attempt == 0) OZC_TRY(launch_debug_xor_byte(ep, s));
     OZC_TRY(pe.mark(3));
 
     // Steps V-v, V-vi, VI
@@ -339,6 +352,118 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     return OZC_STATUS_SUCCESS;
 }
 
+ozc_status_t ensure_vws(ozc_context *h, size_t bytes) {
+    if (bytes <= h->vws_bytes) return OZC_STATUS_SUCCESS;
+    if (h->vws) {
+        OZC_TRY(hipStreamSynchronize(h->stream));
+        OZC_TRY(hipFree(h->vws));
+        h->vws = nullptr;
+        h->vws_bytes = 0;
+    }
+    if (hipMalloc(&h->vws, bytes) != hipSuccess) {
+        h->vws = nullptr;
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    h->vws_bytes = bytes;
+    return OZC_STATUS_SUCCESS;
+}
+
+// One call with the Freivalds check and moduli escalation (see ozc_set_verify).
+ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                          int64_t n, int64_t k, const double alpha[2], const void *A,
+                          int64_t lda, const void *B, int64_t ldb, const double beta[2], void *C,
+                          int64_t ldc) {
+    h->attempt = 0;
+    if (!h->verify) return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+    ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    const bool alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0;
+    if (m == 0 || n == 0 || k == 0 || alpha_zero)
+        return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+    hipStream_t s = h->stream;
+    OZC_TRY(hipSetDevice(h->device));
+    const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
+    const size_t es = single ? 8 : 16;
+    // vectors: y (k), z, w, v (m) as double2 + abs; scratch for partial sums; saved C_in
+    const int64_t vk = k > 0 ? k : 1, vm = m;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b);
+        return o;
+    };
+    const size_t o_y = take(16 * vk), o_ya = take(8 * vk);
+    const size_t o_z = take(16 * vm), o_za = take(8 * vm);
+    const size_t o_w = take(16 * vm), o_wa = take(8 * vm);
+    const size_t o_v = take(16 * vm), o_va = take(8 * vm);
+    size_t scr = gemv_scratch_bytes(m, n);
+    if (ta == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(m, k));
+    if (tb == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(k, n));
+    const size_t o_scr = take(scr);
+    const size_t o_word = take(16);
+    const size_t o_cin = take(beta_zero ? 0 : es * (size_t)m * (size_t)n);
+    st = ensure_vws(h, off);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    char *vw = (char *)h->vws;
+    double2 *y = (double2 *)(vw + o_y), *z = (double2 *)(vw + o_z), *w = (double2 *)(vw + o_w),
+            *v = (double2 *)(vw + o_v);
+    double *ya = (double *)(vw + o_ya), *za = (double *)(vw + o_za), *wa = (double *)(vw + o_wa),
+           *va = (double *)(vw + o_va);
+    void *scratch = vw + o_scr;
+    unsigned long long *word = (unsigned long long *)(vw + o_word);
+    void *cin = vw + o_cin;
+    const uint64_t seed = h->verify_seed;
+    const double rel = h->verify_rel > 0.0 ? h->verify_rel
+                                            : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
+    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-53;
+    if (!beta_zero) {
+        OZC_TRY(hipMemcpy2DAsync(cin, es * m, C, es * ldc, es * m, n, hipMemcpyDeviceToDevice, s));
+        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, seed, v, va, scratch, s));
+    }
+    struct RestoreN {
+        ozc_context *h;
+        int n0;
+        ~RestoreN() { h->nmod = n0; }
+    } restore{h, h->nmod};
+    int N = h->nmod, escalations = 0;
+    double ratio = 0.0;
+    int64_t failed = 0;
+    for (;;) {
+        h->nmod = N;
+        st = run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+        if (st != OZC_STATUS_SUCCESS) break;
+        // y = op(B) x (k), z = op(A) y (m), w = C x (m)
+        if (tb == OZC_OP_N) OZC_TRY(launch_gemv(B, single, 0, k, n, ldb, nullptr, nullptr, seed, y, ya, scratch, s));
+        else OZC_TRY(launch_gemv(B, single, (int)tb, n, k, ldb, nullptr, nullptr, seed, y, ya, scratch, s));
+        if (ta == OZC_OP_N) OZC_TRY(launch_gemv(A, single, 0, m, k, lda, y, ya, 0, z, za, scratch, s));
+        else OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, y, ya, 0, z, za, scratch, s));
+        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, seed, w, wa, scratch, s));
+        OZC_TRY(launch_freivalds_rows(w, wa, z, za, beta_zero ? nullptr : v, va, m, alpha, beta, rel,
+                                      gam, word, s));
+        unsigned long long host[2] = {0, 0};
+        OZC_TRY(hipMemcpyAsync(host, word, sizeof(host), hipMemcpyDeviceToHost, s));
+        OZC_TRY(hipStreamSynchronize(s));
+        memcpy(&ratio, &host[0], sizeof(double));
+        failed = (int64_t)host[1];
+        if (failed == 0) break;
+        if (!h->escalate || N >= OZC_MAX_MODULI) {
+            st = OZC_STATUS_VERIFY_FAILED;
+            break;
+        }
+        N = std::min(OZC_MAX_MODULI, N + 2);
+        ++escalations;
+        ++h->attempt;
+        if (!beta_zero)
+            OZC_TRY(hipMemcpy2DAsync(C, es * ldc, cin, es * m, es * m, n, hipMemcpyDeviceToDevice, s));
+    }
+    h->last.verified = 1;
+    h->last.escalations = escalations;
+    h->last.verify_failed_rows = failed;
+    h->last.verify_ratio = ratio;
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -352,6 +477,7 @@ const char *ozc_status_string(ozc_status_t s) {
         case OZC_STATUS_HIP_ERROR: return "HIP runtime error";
         case OZC_STATUS_NONFINITE: return "non-finite input";
         case OZC_STATUS_INVALID_HANDLE: return "invalid handle";
+        case OZC_STATUS_VERIFY_FAILED: return "verification failed";
     }
     return "unknown status";
 }
@@ -394,6 +520,7 @@ ozc_status_t ozc_destroy(ozc_handle_t h) {
         for (auto e : ev) (void)hipEventDestroy(e);
     for (auto e : h->event_pool) (void)hipEventDestroy(e);
     if (h->ws_own) (void)hipFree(h->ws_own);
+    if (h->vws) (void)hipFree(h->vws);
     (void)hipFree(h->tab_dev);
     (void)hipFree(h->status_dev);
     delete h;
@@ -439,7 +566,7 @@ ozc_status_t ozc_zgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int6
                        const double alpha[2], const void *A, int64_t lda, const void *B,
                        int64_t ldb, const double beta[2], void *C, int64_t ldc) {
     if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
-    return run(h, false, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+    return run_verified(h, false, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,
@@ -447,7 +574,24 @@ ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int6
                        int64_t ldb, const float beta[2], void *C, int64_t ldc) {
     if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
     const double al[2] = {alpha[0], alpha[1]}, be[2] = {beta[0], beta[1]};
-    return run(h, true, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc, nullptr);
+    return run_verified(h, true, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
+}
+
+ozc_status_t ozc_set_verify(ozc_handle_t h, int enable, double rel, int escalate, uint64_t seed) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!(rel == rel)) return OZC_STATUS_INVALID_VALUE;
+    h->verify = enable != 0;
+    h->verify_rel = rel;
+    h->escalate = escalate != 0;
+    h->verify_seed = seed;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_debug_inject(ozc_handle_t h, int fault) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (fault < 0 || fault > 2) return OZC_STATUS_INVALID_VALUE;
+    h->fault = fault;
+    return OZC_STATUS_SUCCESS;
 }
 
 ozc_status_t ozc_inspect(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, int64_t m,

@@ -116,4 +116,16 @@ hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s);
 hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
                           double ai, double br, double bi, hipStream_t s);
 
+// Verification (Freivalds) and test hooks.
+hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t cols, int64_t ld,
+                       const double2 *xv, const double *xa, uint64_t seed, double2 *y, double *ya,
+                       void *scratch, hipStream_t s);
+size_t gemv_scratch_bytes(int64_t rows, int64_t cols);
+hipError_t launch_freivalds_rows(const double2 *w, const double *wa, const double2 *z,
+                                 const double *za, const double2 *v, const double *va, int64_t m,
+                                 const double alpha[2], const double beta[2], double rel,
+                                 double gam, unsigned long long *worst, hipStream_t s);
+hipError_t launch_debug_xor_byte(int8_t *p, hipStream_t s);
+hipError_t launch_debug_add_exp(int16_t *mu, int delta, hipStream_t s);
+
 }  // namespace ozc
