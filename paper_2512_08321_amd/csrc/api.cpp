@@ -343,8 +343,23 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
             }
             return hipSuccess;
         };
-        if (ins->resA) OZC_TRY(planes(ins->resA, resA, (size_t)k, (size_t)L.k_pad, m, L.m_pad, N * L.planes));
-        if (ins->resB) OZC_TRY(planes(ins->resB, resB, (size_t)k, (size_t)L.k_pad, n, L.n_pad, N * L.planes));
+        // residue planes are stored slab-major: k-slab kb of a plane is rows_pad x 64 bytes
+        auto slab_planes = [&](int8_t *dst, const int8_t *src, int64_t rows, int64_t rows_pad,
+                               int64_t count) -> hipError_t {
+            for (int64_t q = 0; q < count; ++q) {
+                for (int64_t kb = 0; kb * 64 < k; ++kb) {
+                    const size_t w = (size_t)std::min<int64_t>(64, k - kb * 64);
+                    hipError_t e = hipMemcpy2DAsync(
+                        dst + (size_t)q * rows * k + kb * 64, (size_t)k,
+                        src + (size_t)q * rows_pad * L.k_pad + (size_t)kb * rows_pad * 64, 64, w,
+                        (size_t)rows, hipMemcpyDeviceToDevice, s);
+                    if (e != hipSuccess) return e;
+                }
+            }
+            return hipSuccess;
+        };
+        if (ins->resA) OZC_TRY(slab_planes(ins->resA, resA, m, L.m_pad, N * L.planes));
+        if (ins->resB) OZC_TRY(slab_planes(ins->resB, resB, n, L.n_pad, N * L.planes));
         if (ins->eprime) OZC_TRY(planes(ins->eprime, ep, (size_t)m, (size_t)L.m_pad, n, L.n_pad, N * 2));
         if (ins->prods)
             OZC_TRY(planes(ins->prods, prods, 4 * (size_t)m, 4 * (size_t)L.m_pad, n, L.n_pad, N * L.nprod));

@@ -178,13 +178,15 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
     map_tile((int64_t)blockIdx.x, TR, TC, (int64_t)nmod * TR * TC, l, ti, tj);
     const int64_t i0 = ti * TM, j0 = tj * TN;
 
+    // planes are slab-major: k-slab s (64 wide) of a plane is m_pad x 64 bytes at s * slabA
     const int64_t planeA = m_pad * k_pad, planeB = n_pad * k_pad;
-    const int8_t *baseA = (bound ? b.A : a.A) + (int64_t)l * P::nplanes * planeA + i0 * k_pad;
-    const int8_t *baseB = (bound ? b.B : a.B) + (int64_t)l * P::nplanes * planeB + j0 * k_pad;
+    const int64_t slabA = m_pad * BK, slabB = n_pad * BK;
+    const int8_t *baseA = (bound ? b.A : a.A) + (int64_t)l * P::nplanes * planeA + i0 * BK;
+    const int8_t *baseB = (bound ? b.B : a.B) + (int64_t)l * P::nplanes * planeB + j0 * BK;
 
     const int lrow = tid >> 2, lseg = tid & 3;
     const int nk = (int)(k_pad / C::KSTEP);
-    const int64_t rstep = (int64_t)C::ROWS_PER_LOAD * k_pad;
+    constexpr int64_t rstep = (int64_t)C::ROWS_PER_LOAD * BK;
     constexpr int NLA = C::NLA, NLB = C::NLB;
 
     ModConst mc;
@@ -195,8 +197,8 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
 
 #pragma unroll 1
     for (int sgi = 0; sgi < P::nseg; ++sgi) {
-        const int8_t *Ap = baseA + (int64_t)P::pa(sgi) * planeA + (int64_t)lrow * k_pad + lseg * 16;
-        const int8_t *Bp = baseB + (int64_t)P::pb(sgi) * planeB + (int64_t)lrow * k_pad + lseg * 16;
+        const int8_t *Ap = baseA + (int64_t)P::pa(sgi) * planeA + lrow * BK + lseg * 16;
+        const int8_t *Bp = baseB + (int64_t)P::pb(sgi) * planeB + lrow * BK + lseg * 16;
         if (!bound || sgi == 0) {
             static_for<BM>([&](auto bi) { static_for<BN>([&](auto bj) { acc[bi][bj] = v16i{}; }); });
         }
@@ -244,21 +246,21 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
             constexpr int QA = CA / NW, QB = CB / NW, NLOAD = KS * (QA + QB);  // loads per wave per stage
             const int crow = lane >> 2;
             const int cg = (lane & 3) ^ swz_bits(crow);  // chunk rows start at multiples of 16
-            const int8_t *pa = baseA + (int64_t)P::pa(sgi) * planeA + (int64_t)crow * k_pad + cg * 16;
-            const int8_t *pb = baseB + (int64_t)P::pb(sgi) * planeB + (int64_t)crow * k_pad + cg * 16;
+            const int8_t *pa = baseA + (int64_t)P::pa(sgi) * planeA + crow * BK + cg * 16;
+            const int8_t *pb = baseB + (int64_t)P::pb(sgi) * planeB + crow * BK + cg * 16;
             const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint4 *)(&lds[0][0]);
             auto issue = [&](int st) {  // ring stage st -> buffer st % NSTAGE
                 const uint32_t buf = lbase + (uint32_t)((st % C::NSTAGE) * KS * C::STAGE * 16);
                 static_for<KS>([&](auto ks) {
-                    const int64_t ko = (int64_t)st * C::KSTEP + ks * BK;
+                    const int64_t ks_idx = (int64_t)st * KS + ks;
                     const uint32_t sb = buf + (uint32_t)(ks * C::STAGE * 16);
                     static_for<QA>([&](auto q) {
                         const int c = wave * QA + q;
-                        dma16(pa + (int64_t)c * 16 * k_pad + ko, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(c * 1024)));
+                        dma16(pa + c * 1024 + ks_idx * slabA, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(c * 1024)));
                     });
                     static_for<QB>([&](auto q) {
                         const int c = wave * QB + q;
-                        dma16(pb + (int64_t)c * 16 * k_pad + ko,
+                        dma16(pb + c * 1024 + ks_idx * slabB,
                               __builtin_amdgcn_readfirstlane(sb + (uint32_t)(TM * 64 + c * 1024)));
                     });
                 });
@@ -278,36 +280,61 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
             block_barrier();
             v4i fa[2][BM], fb[2][BN];
             read_frags(lds[0], 0, fa[0], fb[0]);
-            auto stage = [&](int s, bool handover, auto wait_tag) {
+            // The fragment reads of the next half are interleaved with this half's matrix
+            // instructions (MFMA, read, MFMA, read, ...) so that they are all in flight
+            // early; otherwise the scheduler tends to sink them behind the MFMAs and the
+            // LDS latency shows at the start of the next half.
+            auto interleave = [&]() {
+                static_for<BM + BN>([&](auto) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+                });
+                __builtin_amdgcn_sched_group_barrier(0x008, BM * BN - (BM + BN), 0);
+            };
+            static_assert(BM * BN >= BM + BN, "interleave needs an MFMA per fragment read");
+            // HANDOVER: wait for stage s+1 (WAIT loads of later stages may stay in flight),
+            // then ISSUE stage s + AHEAD into the buffer released by the barrier.
+            auto stage = [&](int s, auto handover_tag, auto issue_tag, auto wait_tag) {
+                constexpr bool HANDOVER = decltype(handover_tag)::value;
+                constexpr bool ISSUE = decltype(issue_tag)::value;
                 const uint4 *cur = lds[s % C::NSTAGE];
                 static_for<NH>([&](auto h) {
                     constexpr int nb = (h + 1) & 1;
                     if constexpr (h + 1 < NH) {
                         read_frags(cur + ((h + 1) / 2) * C::STAGE, (h + 1) & 1, fa[nb], fb[nb]);
+                        mfmas(fa[h & 1], fb[h & 1]);
+                        interleave();
+                    } else if constexpr (HANDOVER) {
+                        vmcnt_wait<decltype(wait_tag)::value>();
+                        block_barrier();  // stage s+1 visible; stage s-1's buffer free
+                        if constexpr (ISSUE) issue(s + AHEAD);
+                        read_frags(lds[(s + 1) % C::NSTAGE], 0, fa[0], fb[0]);
+                        mfmas(fa[h & 1], fb[h & 1]);
+                        interleave();
                     } else {
-                        if (handover) {
-                            vmcnt_wait<decltype(wait_tag)::value>();
-                            block_barrier();  // stage s+1 visible; stage s-1's buffer free
-                            if (s + AHEAD < nk) issue(s + AHEAD);
-                            read_frags(lds[(s + 1) % C::NSTAGE], 0, fa[0], fb[0]);
-                        }
+                        mfmas(fa[h & 1], fb[h & 1]);
                     }
-                    mfmas(fa[h & 1], fb[h & 1]);
                 });
             };
+            using T = std::true_type;
+            using F = std::false_type;
             // stages issued after stage s+1 when it is awaited: min(AHEAD - 2, nk - 2 - s)
             constexpr int LATER = AHEAD >= 2 ? AHEAD - 2 : 0;
+            using WL = std::integral_constant<int, LATER * NLOAD>;
+            using W0 = std::integral_constant<int, 0>;
             int s = 0;
-            for (; s + 1 + LATER < nk; ++s) stage(s, true, std::integral_constant<int, LATER * NLOAD>{});
-            for (; s + 1 < nk; ++s) stage(s, true, std::integral_constant<int, 0>{});
-            stage(s, false, std::integral_constant<int, 0>{});
+            for (; s + AHEAD < nk; ++s) stage(s, T{}, T{}, WL{});
+            for (; s + 1 + LATER < nk; ++s) stage(s, T{}, F{}, WL{});
+            for (; s + 1 < nk; ++s) stage(s, T{}, F{}, W0{});
+            stage(s, F{}, F{}, W0{});
             block_barrier();  // all waves done with the ring before it is refilled
         } else {
             uint4 ra[KS * NLA], rb[KS * NLB];
-            auto gload = [&](int64_t ko) {
+            auto gload = [&](int64_t st) {
                 static_for<KS>([&](auto ks) {
-                    static_for<NLA>([&](auto q) { ra[ks * NLA + q] = ld16(Ap + q * rstep + ko + ks * BK); });
-                    static_for<NLB>([&](auto q) { rb[ks * NLB + q] = ld16(Bp + q * rstep + ko + ks * BK); });
+                    const int64_t ks_idx = st * KS + ks;
+                    static_for<NLA>([&](auto q) { ra[ks * NLA + q] = ld16(Ap + q * rstep + ks_idx * slabA); });
+                    static_for<NLB>([&](auto q) { rb[ks * NLB + q] = ld16(Bp + q * rstep + ks_idx * slabB); });
                 });
             };
             // rows handled by one thread differ by multiples of 16, so they share swz_bits
@@ -327,7 +354,7 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
             for (int s = 0; s < nk; ++s) {
                 const int cur = s & 1;
                 const bool more = s + 1 < nk;
-                if (more) gload((int64_t)(s + 1) * C::KSTEP);
+                if (more) gload((int64_t)(s + 1));
                 compute(lds[cur]);
                 if (more) lstore(lds[cur ^ 1]);
                 __syncthreads();

@@ -221,8 +221,10 @@ __global__ void accu_exponents_kernel(const uint64_t *maxbits, const int32_t *X,
 // Tile of 32 rows x 64 k-elements per block.  Each thread converts 8
 // elements to the integer chunks of |trunc(x 2^mu)| once, then for every
 // modulus computes the symmetric residues (and, for Karatsuba, the reduced
-// sum of the real and imaginary residues), stages them in LDS and writes
-// k-contiguous rows, zero-padded to rows_pad x k_pad.
+// sum of the real and imaginary residues), stages them in LDS and writes them
+// zero-padded to rows_pad x k_pad in slab-major order: the 64-wide k-slab kb
+// of a plane is a contiguous rows_pad x 64-byte block (row r at byte 64 r),
+// so that the product kernels stream whole cache lines.
 //
 // CEIL7 (accurate mode): instead of residues, writes the 7-bit magnitudes
 // ceil(|x| 2^(5 - e)) of the real and imaginary parts and their difference.
@@ -367,8 +369,8 @@ __global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t
         for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
             const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
             const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
-            int8_t *out = dst + ((int64_t)l * NPLANES + pl) * plane_pitch + (r0 + row) * k_pad +
-                          h0 + seg * 16;
+            int8_t *out = dst + ((int64_t)l * NPLANES + pl) * plane_pitch +
+                          ((int64_t)blockIdx.x * rows_pad + r0 + row) * kTileH + seg * 16;
             *reinterpret_cast<uint4 *>(out) = val;
         }
         __syncthreads();

@@ -81,11 +81,11 @@ def test_clean_call_passes_without_escalation(handle, orc, single, ta, tb):
         got, info, st = _call(handle, A, B, C, alpha, beta, N, ta, tb)
         ref = orc.emulate(A, B, N, alpha=alpha, beta=beta, C=C, single=single)["out"]
         assert st == 0 and _same(got, ref)
-        assert info.verified == 1 and info.escalations == 0 and info.verify_failed_rows == 0
+        assert info["verified"] == 1 and info["escalations"] == 0 and info["verify_failed_rows"] == 0
         al = complex(np.complex64(alpha)) if single else alpha
         be = complex(np.complex64(beta)) if single else beta
         ratio, failed = fv.check(A, B, ref, al, be, C, single=single)
-        assert failed == 0 and info.verify_ratio < 1.0
+        assert failed == 0 and info["verify_ratio"] < 1.0
 
 
 @pytest.mark.parametrize("single", [False, True])
@@ -108,12 +108,12 @@ def test_flipped_residue_rejected_then_escalated(handle, orc, single):
     assert _same(got, bad)
     ratio, failed = fv.check(A, B, bad, al, be, C, single=single)
     assert failed == 1 and ratio[0] > 1.0
-    assert st == 7 and info.verify_failed_rows == 1 and info.escalations == 0
-    assert info.verify_ratio == pytest.approx(ratio.max(), rel=1e-6)
+    assert st == 7 and info["verify_failed_rows"] == 1 and info["escalations"] == 0
+    assert info["verify_ratio"] == pytest.approx(ratio.max(), rel=1e-6)
     # with escalation: one rerun with N + 2 moduli from the saved C_in
     got, info, st = _call(handle, A, B, C, alpha, beta, N, fault=1)
     ref = orc.emulate(A, B, N + 2, alpha=alpha, beta=beta, C=C, single=single)["out"]
-    assert st == 0 and info.escalations == 1 and info.verify_failed_rows == 0
+    assert st == 0 and info["escalations"] == 1 and info["verify_failed_rows"] == 0
     assert _same(got, ref)
 
 
@@ -134,7 +134,7 @@ def test_too_few_moduli_escalate_until_accepted(handle, orc):
     # the CPU verdicts must not sit at the threshold for the comparison to be meaningful
     assert all(abs(np.log2(max(r, 1e-300))) > 0.5 for _, r in verdicts.values() if r > 0)
     got, info, st = _call(handle, A, B, C, 1.0, 0.0, 6)
-    assert st == 0 and info.escalations == (expect - 6) // 2
+    assert st == 0 and info["escalations"] == (expect - 6) // 2
     assert _same(got, orc.emulate(A, B, expect)["out"])
 
 
@@ -145,7 +145,7 @@ def test_exponent_fault_persists_and_fails(handle):
     B = workloads.complex_matrix(48, 32, 0.5, 92)
     C = np.zeros((64, 32), np.complex128)
     got, info, st = _call(handle, A, B, C, 1.0, 0.0, 20, fault=2)
-    assert st == 7 and info.escalations == 2 and info.verify_failed_rows >= 1
+    assert st == 7 and info["escalations"] == 2 and info["verify_failed_rows"] >= 1
 
 
 def test_verify_is_deterministic_and_off_by_default(handle, orc):
@@ -154,7 +154,7 @@ def test_verify_is_deterministic_and_off_by_default(handle, orc):
     C = np.zeros((33, 17), np.complex128)
     g1, i1, _ = _call(handle, A, B, C, 1.0, 0.0, 14)
     g2, i2, _ = _call(handle, A, B, C, 1.0, 0.0, 14)
-    assert _same(g1, g2) and i1.verify_ratio == i2.verify_ratio
+    assert _same(g1, g2) and i1["verify_ratio"] == i2["verify_ratio"]
     # a plain call after set_verify(False) reports no verification
     import torch
 
@@ -164,4 +164,4 @@ def test_verify_is_deterministic_and_off_by_default(handle, orc):
     dC, ldc = to_device(C)
     handle.zgemm("N", "N", 33, 17, 65, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc)
     torch.cuda.synchronize()
-    assert handle.last_info().verified == 0
+    assert handle.last_info()["verified"] == 0
