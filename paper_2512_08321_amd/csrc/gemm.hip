@@ -137,20 +137,32 @@ using CfgSmall = TileCfg<2, 2, 2, 2, 1>;  // 128 x 128, 256 threads
 
 __device__ __forceinline__ uint4 ld16(const int8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
 
-// One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS
-// starting at lds_base (lane i -> lds_base + 16 i).  Issued as inline
+// One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS:
+// lane i reads sbase + voff_i + OFF and writes lds_base + OFF + 16 i (the
+// instruction offset applies to both addresses).  The base address and the
+// LDS base are wave-uniform scalars and the per-lane offset is fixed for the
+// whole kernel, so a copy costs no vector instructions.  Issued as inline
 // assembly so that the compiler does not serialise later LDS reads behind it;
 // completion is tracked explicitly with vmcnt_wait() before the barrier.
 // M0 is written only here in these kernels (checked in the generated code); the
 // clobber entry documents it although the compiler treats M0 as reserved.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void dma16(const int8_t *g, uint32_t lds_base) {
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g),
-                 "s"(lds_base)
+template <int OFF>
+__device__ __forceinline__ void dma16(const int8_t *sbase, uint32_t voff, uint32_t lds_base) {
+    static_assert(OFF >= 0 && OFF < 4096, "instruction offset range");
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1 offset:%3" ::"v"(voff),
+                 "s"(sbase), "s"(lds_base), "n"(OFF)
                  : "memory", "m0");
 }
 #pragma clang diagnostic pop
+// A wave-uniform pointer forced into scalar registers.
+__device__ __forceinline__ const int8_t *uniform_ptr(const int8_t *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const int8_t *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
 template <int N>
 __device__ __forceinline__ void vmcnt_wait() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
@@ -208,13 +220,18 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
             const int g = (kk * 2 + (lane >> 5)) ^ swz_bits(lane & 31);
             const uint4 *FA = Lbuf + (wm * WTM + (lane & 31)) * 4 + g;
             const uint4 *FB = Lbuf + TM * 4 + (wn * WTN + (lane & 31)) * 4 + g;
-            static_for<BM>([&](auto bi) {
-                const uint4 t = FA[bi * 32 * 4];
-                fa[bi] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
-            });
-            static_for<BN>([&](auto bj) {
-                const uint4 t = FB[bj * 32 * 4];
-                fb[bj] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            // issue order B0 A0 B1 A1 A2 ...: the MFMAs (A-block outer, B-block inner) can
+            // start after the first two reads and consume the rest as they arrive
+            constexpr int NR = BM > BN ? BM : BN;
+            static_for<NR>([&](auto i) {
+                if constexpr (i < BN) {
+                    const uint4 t = FB[i * 32 * 4];
+                    fb[i] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+                }
+                if constexpr (i < BM) {
+                    const uint4 t = FA[i * 32 * 4];
+                    fa[i] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+                }
             });
         };
         auto mfmas = [&](const v4i (&fa)[BM], const v4i (&fb)[BN]) {
@@ -244,25 +261,24 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
             // stages ahead, so its buffer was released by the barrier of the stage before
             static_assert(C::NSTAGE >= 3, "DMA ring needs at least three buffers");
             constexpr int QA = CA / NW, QB = CB / NW, NLOAD = KS * (QA + QB);  // loads per wave per stage
+            static_assert(QA <= 4 && QB <= 4, "chunk offsets must fit the instruction offset");
             const int crow = lane >> 2;
             const int cg = (lane & 3) ^ swz_bits(crow);  // chunk rows start at multiples of 16
-            const int8_t *pa = baseA + (int64_t)P::pa(sgi) * planeA + crow * BK + cg * 16;
-            const int8_t *pb = baseB + (int64_t)P::pb(sgi) * planeB + crow * BK + cg * 16;
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            // per-lane offsets inside the wave's first chunk (same for every stage and product)
+            const uint32_t voffA = (uint32_t)(wv * QA * 1024 + crow * BK + cg * 16);
+            const uint32_t voffB = (uint32_t)(wv * QB * 1024 + crow * BK + cg * 16);
+            const int8_t *sa = uniform_ptr(baseA + (int64_t)P::pa(sgi) * planeA);
+            const int8_t *sb_ = uniform_ptr(baseB + (int64_t)P::pb(sgi) * planeB);
             const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint4 *)(&lds[0][0]);
             auto issue = [&](int st) {  // ring stage st -> buffer st % NSTAGE
                 const uint32_t buf = lbase + (uint32_t)((st % C::NSTAGE) * KS * C::STAGE * 16);
                 static_for<KS>([&](auto ks) {
                     const int64_t ks_idx = (int64_t)st * KS + ks;
-                    const uint32_t sb = buf + (uint32_t)(ks * C::STAGE * 16);
-                    static_for<QA>([&](auto q) {
-                        const int c = wave * QA + q;
-                        dma16(pa + c * 1024 + ks_idx * slabA, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(c * 1024)));
-                    });
-                    static_for<QB>([&](auto q) {
-                        const int c = wave * QB + q;
-                        dma16(pb + c * 1024 + ks_idx * slabB,
-                              __builtin_amdgcn_readfirstlane(sb + (uint32_t)(TM * 64 + c * 1024)));
-                    });
+                    const uint32_t la = buf + (uint32_t)(ks * C::STAGE * 16 + wv * QA * 1024);
+                    const uint32_t lb = buf + (uint32_t)(ks * C::STAGE * 16 + TM * 64 + wv * QB * 1024);
+                    static_for<QA>([&](auto q) { dma16<q * 1024>(sa + ks_idx * slabA, voffA, la); });
+                    static_for<QB>([&](auto q) { dma16<q * 1024>(sb_ + ks_idx * slabB, voffB, lb); });
                 });
             };
             // Software pipeline over half-slabs (32-wide k): the fragments of the next half
