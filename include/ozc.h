@@ -157,7 +157,7 @@ typedef struct {
     int mode;            /* ozc_mode_t                                               */
     int algo;            /* ozc_algo_t                                               */
     int nonfinite;       /* 1 if the last call met an inf/NaN input                  */
-    int64_t m, n, k;     /* shape of the last call                                   */
+    int64_t m, n, k;     /* shape of the last call (batched: sums over the problems)  */
     size_t workspace;    /* bytes of workspace the last call used                    */
     double int8_ops;     /* INT8 MFMA operations of the residue products (2 per MAC)  */
     int verified;        /* 1 if the last call ran the Freivalds check                */
@@ -205,6 +205,64 @@ typedef struct {
 
 ozc_status_t ozc_set_profiling(ozc_handle_t handle, int enable);
 ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems of uneven shapes (an addition of this library;
+ * the paper treats one product at a time).  Problem p computes
+ *   C_p = alpha_p op(A_p) op(B_p) + beta_p C_p
+ * with exactly the semantics and the bit-exact results of ozc_zgemm /
+ * ozc_cgemm on the same arguments (fixed moduli order, Section II), using
+ * the handle's moduli count and algorithm.  Arguments are host arrays of
+ * `count` entries: transa, transb, m, n, k, lda, ldb, ldc; A, B, C hold device
+ * pointers; alpha and beta hold 2 * count values (re, im of problem p at
+ * 2p, 2p + 1).  Every problem is validated as ozc_zgemm does; the first
+ * invalid one makes the call return INVALID_VALUE before any work starts.
+ * Problems with m == 0 or n == 0 are skipped; k == 0 or alpha == 0 give
+ * C_p = beta_p C_p.
+ *
+ * The whole batch runs as one launch per phase (statistics, exponents,
+ * residue split, products, reconstruction); the products run in a
+ * persistent kernel that takes (problem, moduli group, tile) items from a
+ * device work queue, largest k first.  The launch sequence is recorded once
+ * into a HIP graph per distinct argument list (pointers included) and
+ * replayed when the same list comes again.  The batch owns a workspace of its
+ * own (kept until the handle is destroyed or a larger batch needs more).
+ * Fast mode only: NOT_SUPPORTED in accurate mode.  Problems must not overlap
+ * in C.  Asynchronous on the handle's stream; non-finite inputs are
+ * reported by ozc_last_info as for a single call. */
+ozc_status_t ozc_zgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,
+                                const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                                const int64_t *k, const double *alpha, const void *const *A,
+                                const int64_t *lda, const void *const *B, const int64_t *ldb,
+                                const double *beta, void *const *C, const int64_t *ldc);
+ozc_status_t ozc_cgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,
+                                const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                                const int64_t *k, const float *alpha, const void *const *A,
+                                const int64_t *lda, const void *const *B, const int64_t *ldb,
+                                const float *beta, void *const *C, const int64_t *ldc);
+
+/* Schedule of the batched products. */
+typedef struct {
+    int tile_threshold;  /* problems with min(m, n) >= this use 256 x 256 output tiles,
+                            the others 128 x 128 (default 1024)                          */
+    int moduli_group;    /* moduli computed one after another per work item (>= 1;
+                            default 1)                                                   */
+    int use_graph;       /* record and replay HIP graphs (default 1)                     */
+} ozc_batch_policy_t;
+ozc_status_t ozc_set_batch_policy(ozc_handle_t handle, const ozc_batch_policy_t *policy);
+ozc_status_t ozc_get_batch_policy(ozc_handle_t handle, ozc_batch_policy_t *policy);
+
+/* Autotuner: for the given batch, times the product phase under candidate
+ * schedules (tile thresholds 256, 512, 1024, 2048 and never, times moduli
+ * groups 1, 2, 4 and N; the preparation phases run once per threshold),
+ * keeps the fastest as the handle's batch policy and returns it in *chosen
+ * (may be NULL).  C is neither read nor written.  Synchronises the stream.
+ * `single` selects complex64 operands. */
+ozc_status_t ozc_batch_tune(ozc_handle_t handle, int single, int count, const ozc_op_t *transa,
+                            const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                            const int64_t *k, const void *const *A, const int64_t *lda,
+                            const void *const *B, const int64_t *ldb,
+                            ozc_batch_policy_t *chosen);
 
 /* Synchronises the handle's stream and reports on the last call.  Returns
  * NONFINITE when the last call met inf/NaN input (info still filled). */

@@ -47,6 +47,11 @@ class Info(ctypes.Structure):
                 ("verify_failed_rows", ctypes.c_int64), ("verify_ratio", ctypes.c_double)]
 
 
+class BatchPolicy(ctypes.Structure):
+    _fields_ = [("tile_threshold", ctypes.c_int), ("moduli_group", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int), ("scale_ms", ctypes.c_double), ("split_ms", ctypes.c_double),
                 ("gemm_ms", ctypes.c_double), ("crt_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
@@ -73,6 +78,14 @@ EXPORTS = {
     "ozc_profile_read": [_VP, ctypes.POINTER(Profile)],
     "ozc_set_verify": [_VP, _INT, ctypes.c_double, _INT, ctypes.c_uint64],
     "ozc_debug_inject": [_VP, _INT],
+    "ozc_zgemm_vbatched": [_VP, _INT, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                           _VP, _VP],
+    "ozc_cgemm_vbatched": [_VP, _INT, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                           _VP, _VP],
+    "ozc_set_batch_policy": [_VP, ctypes.POINTER(BatchPolicy)],
+    "ozc_get_batch_policy": [_VP, ctypes.POINTER(BatchPolicy)],
+    "ozc_batch_tune": [_VP, _INT, _INT, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                       ctypes.POINTER(BatchPolicy)],
     "ozc_status_string": [_INT],
 }
 
@@ -177,6 +190,35 @@ class Handle:
     def debug_inject(self, fault: int):
         _check(lib().ozc_debug_inject(self._h, int(fault)), "ozc_debug_inject")
 
+    def gemm_vbatched(self, problems, single: bool = False, stream=None):
+        """Batched ozc_zgemm_vbatched / ozc_cgemm_vbatched.  ``problems``: list of dicts
+        with keys transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc
+        (A, B, C device tensors or pointers)."""
+        self.set_stream(stream)
+        b = _BatchArgs(problems, single)
+        fn = lib().ozc_cgemm_vbatched if single else lib().ozc_zgemm_vbatched
+        _check(fn(self._h, b.count, b.ta, b.tb, b.m, b.n, b.k, b.alpha, b.A, b.lda, b.B, b.ldb,
+                  b.beta, b.C, b.ldc), "ozc_gemm_vbatched")
+
+    def set_batch_policy(self, tile_threshold: int = 1024, moduli_group: int = 1,
+                         use_graph: bool = True):
+        p = BatchPolicy(int(tile_threshold), int(moduli_group), int(bool(use_graph)))
+        _check(lib().ozc_set_batch_policy(self._h, ctypes.byref(p)), "ozc_set_batch_policy")
+
+    def batch_policy(self) -> dict:
+        p = BatchPolicy()
+        _check(lib().ozc_get_batch_policy(self._h, ctypes.byref(p)), "ozc_get_batch_policy")
+        return _policy_dict(p)
+
+    def batch_tune(self, problems, single: bool = False, stream=None) -> dict:
+        """ozc_batch_tune on the A/B operands of ``problems``; returns the chosen policy."""
+        self.set_stream(stream)
+        b = _BatchArgs(problems, single, with_c=False)
+        p = BatchPolicy()
+        _check(lib().ozc_batch_tune(self._h, int(bool(single)), b.count, b.ta, b.tb, b.m, b.n, b.k,
+                                    b.A, b.lda, b.B, b.ldb, ctypes.byref(p)), "ozc_batch_tune")
+        return _policy_dict(p)
+
     def set_profiling(self, enable: bool):
         _check(lib().ozc_set_profiling(self._h, int(bool(enable))), "ozc_set_profiling")
 
@@ -191,6 +233,44 @@ class Handle:
         if st not in (0, 5) or (st == 5 and raise_nonfinite):
             _check(st, "ozc_last_info")
         return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+def _arr(ctype, values):
+    a = (ctype * max(1, len(values)))(*values)
+    return a
+
+
+class _BatchArgs:
+    """Host arrays of one batched call (kept alive for the duration of the call)."""
+
+    def __init__(self, problems, single: bool, with_c: bool = True):
+        cnt = len(problems)
+        self.count = cnt
+        get = lambda key, default=None: [p.get(key, default) for p in problems]
+        self.ta = _arr(_INT, [OP[t] for t in get("transa", "N")])
+        self.tb = _arr(_INT, [OP[t] for t in get("transb", "N")])
+        self.m = _arr(_I64, get("m"))
+        self.n = _arr(_I64, get("n"))
+        self.k = _arr(_I64, get("k"))
+        self.lda = _arr(_I64, get("lda"))
+        self.ldb = _arr(_I64, get("ldb"))
+        self.A = _arr(_VP, [_ptr(x) for x in get("A")])
+        self.B = _arr(_VP, [_ptr(x) for x in get("B")])
+        if with_c:
+            real = ctypes.c_float if single else ctypes.c_double
+            al, be = [], []
+            for p in problems:
+                a, b = complex(p.get("alpha", 1.0)), complex(p.get("beta", 0.0))
+                al += [a.real, a.imag]
+                be += [b.real, b.imag]
+            self.alpha = _arr(real, al)
+            self.beta = _arr(real, be)
+            self.C = _arr(_VP, [_ptr(x) for x in get("C")])
+            self.ldc = _arr(_I64, get("ldc"))
+
+
+def _policy_dict(p: BatchPolicy) -> dict:
+    return {f: getattr(p, f) for f, _ in BatchPolicy._fields_}
 
 
 _handles: dict = {}

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libozc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["tables.cpp", "api.cpp", "prep.hip", "gemm.hip", "crt.hip", "verify.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "batched.cpp", "prep.hip", "gemm.hip", "crt.hip", "verify.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -8,45 +8,12 @@
 #include <new>
 #include <vector>
 
-#include "../../include/ozc.h"
-#include "internal.h"
+#include "context.h"
 
 using namespace ozc;
 
-struct ozc_context {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    int nmod = 14;
-    ozc_mode_t mode = OZC_MODE_FAST;
-    ozc_algo_t algo = OZC_ALGO_KARATSUBA;
-    void *ws_own = nullptr;
-    size_t ws_own_bytes = 0;
-    void *ws_user = nullptr;
-    size_t ws_user_bytes = 0;
-    NTable *tab_dev = nullptr;          // kMaxModuli tables, index N - 1
-    std::vector<NTable> tab_host;
-    uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
-    ozc_info_t last{};
-    bool profiling = false;
-    // verification
-    bool verify = false;
-    bool escalate = true;
-    double verify_rel = 0.0;
-    uint64_t verify_seed = 0x5eed;
-    void *vws = nullptr;
-    size_t vws_bytes = 0;
-    int fault = 0;
-    int attempt = 0;
-    std::vector<std::array<hipEvent_t, 5>> prof_pending;  // per call: phase boundaries
-    std::vector<hipEvent_t> event_pool;
-};
-
 namespace {
 
-constexpr size_t kAlign = 256;
-
-int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     int tile;
@@ -89,11 +56,6 @@ Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool w
     return L;
 }
 
-#define OZC_TRY(expr)                                      \
-    do {                                                   \
-        hipError_t e_ = (expr);                            \
-        if (e_ != hipSuccess) return OZC_STATUS_HIP_ERROR; \
-    } while (0)
 
 ozc_status_t ensure_workspace(ozc_context *h, size_t bytes, char **ws) {
     if (h->ws_user) {
@@ -118,6 +80,10 @@ ozc_status_t ensure_workspace(ozc_context *h, size_t bytes, char **ws) {
     *ws = (char *)h->ws_own;
     return OZC_STATUS_SUCCESS;
 }
+
+}  // namespace
+
+namespace ozc {
 
 OperandView view_A(const void *A, ozc_op_t ta, int64_t m, int64_t k, int64_t lda) {
     OperandView v{};
@@ -155,7 +121,7 @@ OperandView view_B(const void *B, ozc_op_t tb, int64_t n, int64_t k, int64_t ldb
     return v;
 }
 
-bool valid_op(ozc_op_t t) { return t == OZC_OP_N || t == OZC_OP_T || t == OZC_OP_C; }
+static bool valid_op(ozc_op_t t) { return t == OZC_OP_N || t == OZC_OP_T || t == OZC_OP_C; }
 
 ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k, const void *A,
                         int64_t lda, const void *B, int64_t ldb, const void *C, int64_t ldc,
@@ -173,6 +139,10 @@ ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t 
     if (m > ((int64_t)1 << 31) || n > ((int64_t)1 << 31)) return OZC_STATUS_NOT_SUPPORTED;
     return OZC_STATUS_SUCCESS;
 }
+
+}  // namespace ozc
+
+namespace {
 
 // Phase events of one call (a no-op unless profiling is enabled).
 struct PhaseEvents {
@@ -536,6 +506,7 @@ ozc_status_t ozc_destroy(ozc_handle_t h) {
     for (auto e : h->event_pool) (void)hipEventDestroy(e);
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->vws) (void)hipFree(h->vws);
+    batch_release(h);
     (void)hipFree(h->tab_dev);
     (void)hipFree(h->status_dev);
     delete h;

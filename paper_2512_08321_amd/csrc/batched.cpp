@@ -1,0 +1,615 @@
+// Batched products (include/ozc.h, "batches"): the plan of one batch (padding,
+// workspace layout, per-phase block and work-item numbering), its launch
+// sequence, the HIP graph that replays it, and the schedule autotuner.
+//
+// Every problem goes through the same kernels as a single call (the batched
+// kernels only add the lookup of their problem), so the results are
+// bit-identical to ozc_zgemm on the same arguments.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "context.h"
+
+namespace ozc {
+
+namespace {
+
+struct Problem {
+    ozc_op_t ta, tb;
+    int64_t m, n, k, lda, ldb, ldc;
+    const void *A, *B;
+    void *C;
+    double alpha[2], beta[2];
+};
+
+}  // namespace
+
+struct BatchPlan {
+    std::vector<uint64_t> key;
+    bool single = false;
+    int nmod = 0, algo = 0, planes = 0, nchunks = 1, nlimbs = 1, group = 1;
+    size_t ws_bytes = 0;
+    std::vector<BatchOperand> ops;
+    std::vector<BatchGemm> gm[2];  // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
+    std::vector<BatchCrt> crt;
+    int64_t blk_scan = 0, blk_exp = 0, blk_split = 0, items[2] = {0, 0}, crt_blocks = 0;
+    size_t stats_off = 0, stats_words = 0, counter_off = 0;
+    std::vector<Problem> degenerate;  // k == 0 or alpha == 0: C = beta C
+    char *desc = nullptr;             // device copy of ops, gm[0], gm[1], crt
+    BatchOperand *ops_dev = nullptr;
+    BatchGemm *gm_dev[2] = {nullptr, nullptr};
+    BatchCrt *crt_dev = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double int8_ops = 0.0;
+    int64_t sum_m = 0, sum_n = 0, sum_k = 0;
+
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (desc) (void)hipFree(desc);
+        exec = nullptr;
+        desc = nullptr;
+    }
+};
+
+struct BatchState {
+    ozc_batch_policy_t policy{1024, 1, 1};
+    BatchPlan plan;
+    bool have_plan = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    int grid[2] = {0, 0};  // resident blocks of the persistent product kernel per tile size
+};
+
+void batch_release(ozc_context *h) {
+    if (!h->batch) return;
+    BatchState *bs = h->batch;
+    bs->plan.release();
+    if (bs->ws) (void)hipFree(bs->ws);
+    if (bs->cap) (void)hipStreamDestroy(bs->cap);
+    delete bs;
+    h->batch = nullptr;
+}
+
+namespace {
+
+BatchState *state_of(ozc_context *h) {
+    if (!h->batch) h->batch = new (std::nothrow) BatchState();
+    return h->batch;
+}
+
+ozc_status_t gather(int count, const ozc_op_t *ta, const ozc_op_t *tb, const int64_t *m,
+                    const int64_t *n, const int64_t *k, const double *alpha, const void *const *A,
+                    const int64_t *lda, const void *const *B, const int64_t *ldb,
+                    const double *beta, void *const *C, const int64_t *ldc, bool need_c,
+                    std::vector<Problem> &out) {
+    if (count < 0) return OZC_STATUS_INVALID_VALUE;
+    if (count == 0) return OZC_STATUS_SUCCESS;
+    if (!ta || !tb || !m || !n || !k || !A || !lda || !B || !ldb) return OZC_STATUS_INVALID_VALUE;
+    if (need_c && (!alpha || !beta || !C || !ldc)) return OZC_STATUS_INVALID_VALUE;
+    out.resize((size_t)count);
+    for (int p = 0; p < count; ++p) {
+        Problem &q = out[(size_t)p];
+        q.ta = ta[p];
+        q.tb = tb[p];
+        q.m = m[p];
+        q.n = n[p];
+        q.k = k[p];
+        q.lda = lda[p];
+        q.ldb = ldb[p];
+        q.ldc = need_c ? ldc[p] : (m[p] > 1 ? m[p] : 1);
+        q.A = A[p];
+        q.B = B[p];
+        q.C = need_c ? C[p] : nullptr;
+        for (int c = 0; c < 2; ++c) {
+            q.alpha[c] = need_c ? alpha[2 * p + c] : (c == 0 ? 1.0 : 0.0);
+            q.beta[c] = need_c ? beta[2 * p + c] : 0.0;
+        }
+        ozc_status_t st = check_args(q.ta, q.tb, q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C,
+                                     q.ldc, !need_c);
+        if (st != OZC_STATUS_SUCCESS) return st;
+    }
+    return OZC_STATUS_SUCCESS;
+}
+
+bool is_degenerate(const Problem &q) {
+    return q.k == 0 || (q.alpha[0] == 0.0 && q.alpha[1] == 0.0);
+}
+
+std::vector<uint64_t> make_key(const ozc_context *h, bool single, const ozc_batch_policy_t &pol,
+                               const std::vector<Problem> &probs) {
+    std::vector<uint64_t> key;
+    key.reserve(8 + probs.size() * 16);
+    key.push_back(single);
+    key.push_back((uint64_t)h->nmod);
+    key.push_back((uint64_t)h->algo);
+    key.push_back((uint64_t)pol.tile_threshold);
+    key.push_back((uint64_t)pol.moduli_group);
+    key.push_back((uint64_t)pol.use_graph);
+    key.push_back(probs.size());
+    for (const Problem &q : probs) {
+        uint64_t w[16];
+        w[0] = (uint64_t)q.ta | ((uint64_t)q.tb << 8);
+        w[1] = (uint64_t)q.m;
+        w[2] = (uint64_t)q.n;
+        w[3] = (uint64_t)q.k;
+        w[4] = (uint64_t)q.lda;
+        w[5] = (uint64_t)q.ldb;
+        w[6] = (uint64_t)q.ldc;
+        w[7] = (uint64_t)(uintptr_t)q.A;
+        w[8] = (uint64_t)(uintptr_t)q.B;
+        w[9] = (uint64_t)(uintptr_t)q.C;
+        memcpy(&w[10], q.alpha, 16);
+        memcpy(&w[12], q.beta, 16);
+        w[14] = w[15] = 0;
+        key.insert(key.end(), w, w + 16);
+    }
+    return key;
+}
+
+// Padding, workspace layout and descriptors of a batch (host side only).
+ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_policy_t &pol,
+                        const std::vector<Problem> &probs, BatchPlan &P) {
+    P.single = single;
+    P.nmod = h->nmod;
+    P.algo = h->algo == OZC_ALGO_KARATSUBA ? 0 : 1;
+    P.planes = P.algo == 0 ? 3 : 2;
+    P.group = std::max(1, std::min(pol.moduli_group, h->nmod));
+    const NTable &th = h->tab_host[(size_t)h->nmod - 1];
+    P.nlimbs = th.nlimbs;
+    P.nchunks = std::max(1, (th.max_abits_fast + kChunkBits - 1) / kChunkBits);
+    if (P.nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
+    const int nprod = P.algo == 0 ? 3 : 4;
+
+    struct Pad {
+        int tile;
+        int64_t m_pad, n_pad, k_pad;
+        size_t sA, sB, muA, muB, resA, resB, ep;
+        size_t p;  // index into probs
+    };
+    std::vector<Pad> pads;
+    const size_t N = (size_t)P.nmod;
+    size_t stats_words = 0, mu_bytes = 0, res_bytes = 0, ep_bytes = 0;
+    for (size_t p = 0; p < probs.size(); ++p) {
+        const Problem &q = probs[p];
+        if (q.m == 0 || q.n == 0) continue;
+        if (is_degenerate(q)) {
+            P.degenerate.push_back(q);
+            continue;
+        }
+        Pad d{};
+        d.p = p;
+        d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
+        d.m_pad = round_up(q.m, d.tile);
+        d.n_pad = round_up(q.n, d.tile);
+        d.k_pad = round_up(q.k, gemm_kstep_for(d.tile));
+        d.sA = stats_words;
+        stats_words += 2 * (size_t)d.m_pad;  // maxbits, sigma
+        d.sB = stats_words;
+        stats_words += 2 * (size_t)d.n_pad;
+        d.muA = mu_bytes;
+        mu_bytes = align_up(mu_bytes + 2 * (size_t)d.m_pad);
+        d.muB = mu_bytes;
+        mu_bytes = align_up(mu_bytes + 2 * (size_t)d.n_pad);
+        d.resA = res_bytes;
+        res_bytes = align_up(res_bytes + N * P.planes * (size_t)d.m_pad * d.k_pad);
+        d.resB = res_bytes;
+        res_bytes = align_up(res_bytes + N * P.planes * (size_t)d.n_pad * d.k_pad);
+        d.ep = ep_bytes;
+        ep_bytes = align_up(ep_bytes + N * 2 * (size_t)d.m_pad * d.n_pad);
+        pads.push_back(d);
+        P.int8_ops += 2.0 * nprod * (double)P.nmod * (double)q.m * (double)q.n * (double)q.k;
+        P.sum_m += q.m;
+        P.sum_n += q.n;
+        P.sum_k += q.k;
+    }
+    size_t off = 0;
+    P.counter_off = off;
+    off = align_up(off + 64);
+    P.stats_off = off;
+    P.stats_words = stats_words;
+    off = align_up(off + 8 * stats_words);
+    const size_t mu_off = off;
+    off = align_up(off + mu_bytes);
+    const size_t res_off = off;
+    off = align_up(off + res_bytes);
+    const size_t ep_off = off;
+    off = align_up(off + ep_bytes);
+    P.ws_bytes = off;
+
+    // Descriptors hold offsets from the workspace base until bind() adds it.
+    P.ops.clear();
+    P.crt.clear();
+    P.gm[0].clear();
+    P.gm[1].clear();
+    for (const Pad &d : pads) {
+        const Problem &q = probs[d.p];
+        BatchOperand a{}, b{};
+        a.v = view_A(q.A, q.ta, q.m, q.k, q.lda);
+        b.v = view_B(q.B, q.tb, q.n, q.k, q.ldb);
+        a.maxbits = (uint64_t *)(uintptr_t)(P.stats_off + 8 * d.sA);
+        a.sigma = (uint64_t *)(uintptr_t)(P.stats_off + 8 * (d.sA + d.m_pad));
+        b.maxbits = (uint64_t *)(uintptr_t)(P.stats_off + 8 * d.sB);
+        b.sigma = (uint64_t *)(uintptr_t)(P.stats_off + 8 * (d.sB + d.n_pad));
+        a.mu = (int16_t *)(uintptr_t)(mu_off + d.muA);
+        b.mu = (int16_t *)(uintptr_t)(mu_off + d.muB);
+        a.res = (int8_t *)(uintptr_t)(res_off + d.resA);
+        b.res = (int8_t *)(uintptr_t)(res_off + d.resB);
+        a.rows_pad = d.m_pad;
+        b.rows_pad = d.n_pad;
+        a.k_pad = b.k_pad = d.k_pad;
+        for (BatchOperand *o : {&a, &b}) {
+            o->blk_scan = P.blk_scan;
+            P.blk_scan += batch_scan_blocks(o->v);
+            o->blk_exp = P.blk_exp;
+            P.blk_exp += batch_exp_blocks(o->rows_pad);
+            o->blk_split = P.blk_split;
+            P.blk_split += batch_split_blocks(o->rows_pad, o->k_pad);
+            P.ops.push_back(*o);
+        }
+        BatchCrt c{};
+        c.a.eprime = (const int8_t *)(uintptr_t)(ep_off + d.ep);
+        c.a.m = q.m;
+        c.a.n = q.n;
+        c.a.m_pad = d.m_pad;
+        c.a.n_pad = d.n_pad;
+        c.a.nmod = P.nmod;
+        c.a.nlimbs = P.nlimbs;
+        c.a.tab = nullptr;  // bound later
+        c.a.mu = a.mu;
+        c.a.nu = b.mu;
+        c.a.alpha_r = q.alpha[0];
+        c.a.alpha_i = q.alpha[1];
+        c.a.beta_r = q.beta[0];
+        c.a.beta_i = q.beta[1];
+        c.a.C = q.C;
+        c.a.ldc = q.ldc;
+        c.a.single = single;
+        c.blk0 = P.crt_blocks;
+        P.crt_blocks += batch_crt_blocks(d.m_pad, q.n);
+        P.crt.push_back(c);
+        BatchGemm g{};
+        g.A = a.res;
+        g.B = b.res;
+        g.eprime = (int8_t *)(uintptr_t)(ep_off + d.ep);
+        g.m_pad = d.m_pad;
+        g.n_pad = d.n_pad;
+        g.k_pad = d.k_pad;
+        g.TR = (int32_t)(d.m_pad / d.tile);
+        g.TC = (int32_t)(d.n_pad / d.tile);
+        P.gm[d.tile == 256 ? 0 : 1].push_back(g);
+    }
+    // largest k first, so that the long items start early and the short ones fill the tail
+    const int ngroups = (P.nmod + P.group - 1) / P.group;
+    for (int t = 0; t < 2; ++t) {
+        std::stable_sort(P.gm[t].begin(), P.gm[t].end(),
+                         [](const BatchGemm &x, const BatchGemm &y) { return x.k_pad > y.k_pad; });
+        P.items[t] = 0;
+        for (BatchGemm &g : P.gm[t]) {
+            g.item0 = P.items[t];
+            P.items[t] += (int64_t)ngroups * g.TR * g.TC;
+        }
+    }
+    if (P.blk_scan >= ((int64_t)1 << 31) || P.blk_split >= ((int64_t)1 << 31) ||
+        P.crt_blocks >= ((int64_t)1 << 31) || P.items[0] >= ((int64_t)1 << 32) ||
+        P.items[1] >= ((int64_t)1 << 32))
+        return OZC_STATUS_NOT_SUPPORTED;
+    return OZC_STATUS_SUCCESS;
+}
+
+// Turn workspace offsets into addresses and copy the descriptors to the device.
+ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
+    const uintptr_t base = (uintptr_t)ws;
+    const NTable *tab = h->tab_dev + (P.nmod - 1);
+    for (BatchOperand &o : P.ops) {
+        o.maxbits = (uint64_t *)(base + (uintptr_t)o.maxbits);
+        o.sigma = (uint64_t *)(base + (uintptr_t)o.sigma);
+        o.mu = (int16_t *)(base + (uintptr_t)o.mu);
+        o.res = (int8_t *)(base + (uintptr_t)o.res);
+    }
+    for (int t = 0; t < 2; ++t)
+        for (BatchGemm &g : P.gm[t]) {
+            g.A = (const int8_t *)(base + (uintptr_t)g.A);
+            g.B = (const int8_t *)(base + (uintptr_t)g.B);
+            g.eprime = (int8_t *)(base + (uintptr_t)g.eprime);
+        }
+    for (BatchCrt &c : P.crt) {
+        c.a.eprime = (const int8_t *)(base + (uintptr_t)c.a.eprime);
+        c.a.mu = (const int16_t *)(base + (uintptr_t)c.a.mu);
+        c.a.nu = (const int16_t *)(base + (uintptr_t)c.a.nu);
+        c.a.tab = tab;
+    }
+    const size_t b_ops = align_up(sizeof(BatchOperand) * P.ops.size());
+    const size_t b_g0 = align_up(sizeof(BatchGemm) * P.gm[0].size());
+    const size_t b_g1 = align_up(sizeof(BatchGemm) * P.gm[1].size());
+    const size_t b_crt = align_up(sizeof(BatchCrt) * P.crt.size());
+    const size_t total = b_ops + b_g0 + b_g1 + b_crt;
+    if (total == 0) return OZC_STATUS_SUCCESS;
+    std::vector<char> host(total, 0);
+    memcpy(host.data(), P.ops.data(), sizeof(BatchOperand) * P.ops.size());
+    memcpy(host.data() + b_ops, P.gm[0].data(), sizeof(BatchGemm) * P.gm[0].size());
+    memcpy(host.data() + b_ops + b_g0, P.gm[1].data(), sizeof(BatchGemm) * P.gm[1].size());
+    memcpy(host.data() + b_ops + b_g0 + b_g1, P.crt.data(), sizeof(BatchCrt) * P.crt.size());
+    if (hipMalloc(&P.desc, total) != hipSuccess) {
+        P.desc = nullptr;
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    OZC_TRY(hipMemcpy(P.desc, host.data(), total, hipMemcpyHostToDevice));
+    P.ops_dev = (BatchOperand *)P.desc;
+    P.gm_dev[0] = (BatchGemm *)(P.desc + b_ops);
+    P.gm_dev[1] = (BatchGemm *)(P.desc + b_ops + b_g0);
+    P.crt_dev = (BatchCrt *)(P.desc + b_ops + b_g0 + b_g1);
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ensure_batch_ws(ozc_context *h, BatchState *bs, size_t bytes) {
+    if (bytes <= bs->ws_bytes) return OZC_STATUS_SUCCESS;
+    OZC_TRY(hipStreamSynchronize(h->stream));
+    if (bs->have_plan) {  // its graph points into the old workspace
+        bs->plan.release();
+        bs->have_plan = false;
+    }
+    if (bs->ws) (void)hipFree(bs->ws);
+    bs->ws = nullptr;
+    bs->ws_bytes = 0;
+    if (hipMalloc(&bs->ws, bytes) != hipSuccess) {
+        bs->ws = nullptr;
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    bs->ws_bytes = bytes;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t grid_sizes(ozc_context *h, BatchState *bs) {
+    if (bs->grid[0] > 0) return OZC_STATUS_SUCCESS;
+    int cus = 0;
+    OZC_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    bs->grid[0] = cus * batch_gemm_blocks_per_cu(256);
+    bs->grid[1] = cus * batch_gemm_blocks_per_cu(128);
+    return OZC_STATUS_SUCCESS;
+}
+
+enum { PH_PREP = 1, PH_GEMM = 2, PH_CRT = 4, PH_ALL = 7 };
+
+// The launch sequence of a bound plan (no host synchronisation, no memset nodes).
+ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, char *ws,
+                          hipStream_t s, int phases, int group) {
+    const NTable *tab = h->tab_dev + (P.nmod - 1);
+    uint32_t *counters = (uint32_t *)(ws + P.counter_off);
+    const int nops = (int)P.ops.size();
+    if (phases & PH_PREP) {
+        OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
+        OZC_TRY(launch_fill_u64((uint64_t *)(ws + P.stats_off), (int64_t)P.stats_words, 0, s));
+        OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, false, s));
+        OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
+        OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, tab,
+                                            (uint32_t *)h->status_dev, s));
+        OZC_TRY(launch_batch_split(P.ops_dev, nops, P.blk_split, P.single, tab, P.nmod, P.planes,
+                                   P.nchunks, s));
+    }
+    if (phases & PH_GEMM) {
+        OZC_TRY(launch_fill_u32(counters, 2, 0, s));
+        const int tiles[2] = {256, 128};
+        for (int t = 0; t < 2; ++t) {
+            if (P.items[t] == 0) continue;
+            OZC_TRY(launch_batch_gemm(P.gm_dev[t], (int)P.gm[t].size(), P.items[t], tiles[t], group,
+                                      P.nmod, P.algo, tab, counters + t, bs->grid[t], s));
+        }
+    }
+    if (phases & PH_CRT) {
+        OZC_TRY(launch_batch_crt(P.crt_dev, (int)P.crt.size(), P.crt_blocks, P.nlimbs, P.single, s));
+        for (const Problem &q : P.degenerate)
+            OZC_TRY(launch_scale_c(q.C, q.m, q.n, q.ldc, P.single, q.alpha[0], q.alpha[1], q.beta[0],
+                                   q.beta[1], s));
+    }
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t record_graph(ozc_context *h, BatchState *bs, BatchPlan &P) {
+    if (!bs->cap) OZC_TRY(hipStreamCreateWithFlags(&bs->cap, hipStreamNonBlocking));
+    OZC_TRY(hipStreamBeginCapture(bs->cap, hipStreamCaptureModeThreadLocal));
+    ozc_status_t st = launch_batch(h, bs, P, bs->ws, bs->cap, PH_ALL, P.group);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(bs->cap, &g);
+    if (st == OZC_STATUS_SUCCESS && e != hipSuccess) st = OZC_STATUS_HIP_ERROR;
+    if (st == OZC_STATUS_SUCCESS && hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        P.exec = nullptr;
+        st = OZC_STATUS_HIP_ERROR;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
+ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t *ta,
+                          const ozc_op_t *tb, const int64_t *m, const int64_t *n,
+                          const int64_t *k, const double *alpha, const void *const *A,
+                          const int64_t *lda, const void *const *B, const int64_t *ldb,
+                          const double *beta, void *const *C, const int64_t *ldc) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (h->mode != OZC_MODE_FAST) return OZC_STATUS_NOT_SUPPORTED;
+    std::vector<Problem> probs;
+    ozc_status_t st = gather(count, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, true, probs);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    OZC_TRY(hipSetDevice(h->device));
+    BatchState *bs = state_of(h);
+    if (!bs) return OZC_STATUS_ALLOC_FAILED;
+    OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, h->stream));
+    h->last = ozc_info_t{};
+    h->last.num_moduli = h->nmod;
+    h->last.mode = h->mode;
+    h->last.algo = h->algo;
+    if (probs.empty()) return OZC_STATUS_SUCCESS;
+    st = grid_sizes(h, bs);
+    if (st != OZC_STATUS_SUCCESS) return st;
+
+    const ozc_batch_policy_t pol = bs->policy;
+    std::vector<uint64_t> key = make_key(h, single, pol, probs);
+    if (!(bs->have_plan && bs->plan.key == key)) {
+        if (bs->have_plan) {
+            OZC_TRY(hipStreamSynchronize(h->stream));  // the old graph may still run
+            bs->plan.release();
+            bs->have_plan = false;
+        }
+        bs->plan = BatchPlan{};
+        BatchPlan &P = bs->plan;
+        st = plan_batch(h, single, pol, probs, P);
+        if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, P.ws_bytes);
+        if (st == OZC_STATUS_SUCCESS) st = bind(h, P, bs->ws);
+        if (st == OZC_STATUS_SUCCESS && pol.use_graph) st = record_graph(h, bs, P);
+        if (st != OZC_STATUS_SUCCESS) {
+            P.release();
+            return st;
+        }
+        P.key = std::move(key);
+        bs->have_plan = true;
+    }
+    BatchPlan &P = bs->plan;
+    if (P.exec) OZC_TRY(hipGraphLaunch(P.exec, h->stream));
+    else {
+        st = launch_batch(h, bs, P, bs->ws, h->stream, PH_ALL, P.group);
+        if (st != OZC_STATUS_SUCCESS) return st;
+    }
+    h->last.m = P.sum_m;
+    h->last.n = P.sum_n;
+    h->last.k = P.sum_k;
+    h->last.workspace = P.ws_bytes;
+    h->last.int8_ops = P.int8_ops;
+    return OZC_STATUS_SUCCESS;
+}
+
+// Median of the product phase over `reps` runs.
+ozc_status_t time_gemm(ozc_context *h, BatchState *bs, const BatchPlan &P, int group, int reps,
+                       float *ms) {
+    hipEvent_t e0, e1;
+    OZC_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return OZC_STATUS_HIP_ERROR;
+    }
+    std::vector<float> t;
+    ozc_status_t st = launch_batch(h, bs, P, bs->ws, h->stream, PH_GEMM, group);  // warm-up
+    for (int r = 0; r < reps && st == OZC_STATUS_SUCCESS; ++r) {
+        float x = 0.f;
+        if (hipEventRecord(e0, h->stream) != hipSuccess) st = OZC_STATUS_HIP_ERROR;
+        if (st == OZC_STATUS_SUCCESS) st = launch_batch(h, bs, P, bs->ws, h->stream, PH_GEMM, group);
+        if (st == OZC_STATUS_SUCCESS && (hipEventRecord(e1, h->stream) != hipSuccess ||
+                                         hipEventSynchronize(e1) != hipSuccess ||
+                                         hipEventElapsedTime(&x, e0, e1) != hipSuccess))
+            st = OZC_STATUS_HIP_ERROR;
+        t.push_back(x);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return OZC_STATUS_SUCCESS;
+}
+
+}  // namespace
+
+}  // namespace ozc
+
+using namespace ozc;
+
+extern "C" {
+
+ozc_status_t ozc_zgemm_vbatched(ozc_handle_t h, int count, const ozc_op_t *transa,
+                                const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                                const int64_t *k, const double *alpha, const void *const *A,
+                                const int64_t *lda, const void *const *B, const int64_t *ldb,
+                                const double *beta, void *const *C, const int64_t *ldc) {
+    return run_vbatched(h, false, count, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+ozc_status_t ozc_cgemm_vbatched(ozc_handle_t h, int count, const ozc_op_t *transa,
+                                const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                                const int64_t *k, const float *alpha, const void *const *A,
+                                const int64_t *lda, const void *const *B, const int64_t *ldb,
+                                const float *beta, void *const *C, const int64_t *ldc) {
+    if (count < 0) return OZC_STATUS_INVALID_VALUE;
+    if (count > 0 && (!alpha || !beta)) return OZC_STATUS_INVALID_VALUE;
+    std::vector<double> al((size_t)2 * (count > 0 ? count : 0)), be(al.size());
+    for (size_t i = 0; i < al.size(); ++i) {
+        al[i] = (double)alpha[i];
+        be[i] = (double)beta[i];
+    }
+    return run_vbatched(h, true, count, transa, transb, m, n, k, al.data(), A, lda, B, ldb,
+                        be.data(), C, ldc);
+}
+
+ozc_status_t ozc_set_batch_policy(ozc_handle_t h, const ozc_batch_policy_t *policy) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!policy || policy->tile_threshold < 0 || policy->moduli_group < 1)
+        return OZC_STATUS_INVALID_VALUE;
+    BatchState *bs = state_of(h);
+    if (!bs) return OZC_STATUS_ALLOC_FAILED;
+    bs->policy = *policy;
+    if (bs->policy.tile_threshold == 0) bs->policy.tile_threshold = 1024;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_get_batch_policy(ozc_handle_t h, ozc_batch_policy_t *policy) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!policy) return OZC_STATUS_INVALID_VALUE;
+    BatchState *bs = state_of(h);
+    if (!bs) return OZC_STATUS_ALLOC_FAILED;
+    *policy = bs->policy;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_batch_tune(ozc_handle_t h, int single, int count, const ozc_op_t *transa,
+                            const ozc_op_t *transb, const int64_t *m, const int64_t *n,
+                            const int64_t *k, const void *const *A, const int64_t *lda,
+                            const void *const *B, const int64_t *ldb, ozc_batch_policy_t *chosen) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (h->mode != OZC_MODE_FAST) return OZC_STATUS_NOT_SUPPORTED;
+    std::vector<Problem> probs;
+    ozc_status_t st = gather(count, transa, transb, m, n, k, nullptr, A, lda, B, ldb, nullptr,
+                             nullptr, nullptr, false, probs);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    OZC_TRY(hipSetDevice(h->device));
+    BatchState *bs = state_of(h);
+    if (!bs) return OZC_STATUS_ALLOC_FAILED;
+    st = grid_sizes(h, bs);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    ozc_batch_policy_t best = bs->policy;
+    float best_ms = -1.f;
+    const int thresholds[] = {256, 512, 1024, 2048, 1 << 30};
+    const int groups[] = {1, 2, 4, h->nmod};
+    for (int thr : thresholds) {
+        ozc_batch_policy_t pol = bs->policy;
+        pol.tile_threshold = thr;
+        pol.moduli_group = 1;
+        BatchPlan P;
+        st = plan_batch(h, single != 0, pol, probs, P);
+        if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, P.ws_bytes);
+        if (st == OZC_STATUS_SUCCESS) st = bind(h, P, bs->ws);
+        if (st == OZC_STATUS_SUCCESS) st = launch_batch(h, bs, P, bs->ws, h->stream, PH_PREP, 1);
+        for (int g : groups) {
+            if (st != OZC_STATUS_SUCCESS) break;
+            if (g < 1 || g > h->nmod) continue;
+            float ms = 0.f;
+            st = time_gemm(h, bs, P, g, 3, &ms);
+            if (st == OZC_STATUS_SUCCESS && (best_ms < 0.f || ms < best_ms)) {
+                best_ms = ms;
+                best = pol;
+                best.moduli_group = g;
+            }
+        }
+        if (hipStreamSynchronize(h->stream) != hipSuccess && st == OZC_STATUS_SUCCESS)
+            st = OZC_STATUS_HIP_ERROR;
+        P.release();
+        if (st != OZC_STATUS_SUCCESS) return st;
+    }
+    bs->policy = best;
+    if (chosen) *chosen = best;
+    return OZC_STATUS_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Handle state shared by the host runtime files (api.cpp, batched.cpp).
+#pragma once
+
+#include <array>
+#include <vector>
+
+#include "../../include/ozc.h"
+#include "internal.h"
+
+namespace ozc {
+struct BatchState;  // batched-call plans and tuning (batched.cpp)
+}
+
+struct ozc_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int nmod = 14;
+    ozc_mode_t mode = OZC_MODE_FAST;
+    ozc_algo_t algo = OZC_ALGO_KARATSUBA;
+    void *ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    void *ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    ozc::NTable *tab_dev = nullptr;          // kMaxModuli tables, index N - 1
+    std::vector<ozc::NTable> tab_host;
+    uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
+    ozc_info_t last{};
+    bool profiling = false;
+    // verification
+    bool verify = false;
+    bool escalate = true;
+    double verify_rel = 0.0;
+    uint64_t verify_seed = 0x5eed;
+    void *vws = nullptr;
+    size_t vws_bytes = 0;
+    int fault = 0;
+    int attempt = 0;
+    std::vector<std::array<hipEvent_t, 5>> prof_pending;  // per call: phase boundaries
+    std::vector<hipEvent_t> event_pool;
+    ozc::BatchState *batch = nullptr;
+};
+
+
+#define OZC_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return OZC_STATUS_HIP_ERROR; \
+    } while (0)
+
+namespace ozc {
+constexpr size_t kAlign = 256;
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+OperandView view_A(const void *A, ozc_op_t ta, int64_t m, int64_t k, int64_t lda);
+OperandView view_B(const void *B, ozc_op_t tb, int64_t n, int64_t k, int64_t ldb);
+ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k, const void *A,
+                        int64_t lda, const void *B, int64_t ldb, const void *C, int64_t ldc,
+                        bool c_optional);
+void batch_release(ozc_context *h);
+}  // namespace ozc

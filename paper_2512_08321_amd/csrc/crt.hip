@@ -140,11 +140,12 @@ __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double 
     else reinterpret_cast<double2 *>(C)[idx] = make_double2(re, im);
 }
 
-// One thread: 4 consecutive rows i of one column j.
+// One thread: 4 consecutive rows i of one column j; block bx covers threads
+// 256 bx ... 256 bx + 255 of the (m_pad / 4) x n grid.
 template <int L, bool SINGLE>
-__global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
+__device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     const int64_t m4 = a.m_pad >> 2;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t t = bx * 256 + threadIdx.x;
     const int64_t i4 = t % m4, j = t / m4;
     const int64_t ib = i4 * 4;
     if (j >= a.n || ib >= a.m) return;
@@ -206,6 +207,31 @@ __global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
     }
 }
 
+template <int L, bool SINGLE>
+__global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
+    crt_output_body<L, SINGLE>(a, blockIdx.x);
+}
+
+template <int L, bool SINGLE>
+__global__ __launch_bounds__(256) void batch_crt_kernel(const BatchCrt *probs, int nprob) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nprob - 1;  // last problem whose first block is <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    crt_output_body<L, SINGLE>(probs[lo].a, b - probs[lo].blk0);
+}
+
+template <int L>
+hipError_t launch_batch_L(const BatchCrt *probs, int nprob, int64_t blocks, bool single, hipStream_t s) {
+    dim3 grid((unsigned)blocks);
+    if (single) hipLaunchKernelGGL((batch_crt_kernel<L, true>), grid, dim3(256), 0, s, probs, nprob);
+    else hipLaunchKernelGGL((batch_crt_kernel<L, false>), grid, dim3(256), 0, s, probs, nprob);
+    return hipGetLastError();
+}
+
 // C := alpha * 0 + beta * C (alpha == 0 or k == 0), with the same operation order.
 template <bool SINGLE>
 __global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, double ar, double ai,
@@ -258,6 +284,27 @@ hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool singl
     if (single) hipLaunchKernelGGL(scale_c_kernel<true>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
     else hipLaunchKernelGGL(scale_c_kernel<false>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
     return hipGetLastError();
+}
+
+int64_t batch_crt_blocks(int64_t m_pad, int64_t n) { return ((m_pad / 4) * n + 255) / 256; }
+
+hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
+                            bool single, hipStream_t s) {
+    if (blocks <= 0 || nprob <= 0) return hipSuccess;
+    switch (nlimbs) {
+        case 1: return launch_batch_L<1>(probs, nprob, blocks, single, s);
+        case 2: return launch_batch_L<2>(probs, nprob, blocks, single, s);
+        case 3: return launch_batch_L<3>(probs, nprob, blocks, single, s);
+        case 4: return launch_batch_L<4>(probs, nprob, blocks, single, s);
+        case 5: return launch_batch_L<5>(probs, nprob, blocks, single, s);
+        case 6: return launch_batch_L<6>(probs, nprob, blocks, single, s);
+        case 7: return launch_batch_L<7>(probs, nprob, blocks, single, s);
+        case 8: return launch_batch_L<8>(probs, nprob, blocks, single, s);
+        case 9: return launch_batch_L<9>(probs, nprob, blocks, single, s);
+        case 10: return launch_batch_L<10>(probs, nprob, blocks, single, s);
+        case 11: return launch_batch_L<11>(probs, nprob, blocks, single, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ozc

@@ -169,8 +169,11 @@ __device__ __forceinline__ void vmcnt_wait() {
 }
 __device__ __forceinline__ void block_barrier() { __builtin_amdgcn_s_barrier(); }
 
+// One output tile (ti, tj) of modulus l: all products of the plan and their epilogues.
+// Ends with a block barrier, so a caller may run the next tile right away.
 template <int KIND, typename C, bool DUMP>
-__global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, BoundArgs b) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b, int l, int64_t ti,
+                                          int64_t tj) {
     using P = Plan<KIND>;
     constexpr int TM = C::TM, TN = C::TN, BM = C::BM, BN = C::BN, KS = C::KS;
     constexpr int WTM = BM * 32, WTN = BN * 32;  // wave tile
@@ -183,11 +186,6 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
     const int64_t m_pad = bound ? b.m_pad : a.m_pad;
     const int64_t n_pad = bound ? b.n_pad : a.n_pad;
     const int64_t k_pad = bound ? b.k_pad : a.k_pad;
-    const int64_t TR = m_pad / TM, TC = n_pad / TN;
-    const int nmod = bound ? 1 : a.nmod;
-    int l;
-    int64_t ti, tj;
-    map_tile((int64_t)blockIdx.x, TR, TC, (int64_t)nmod * TR * TC, l, ti, tj);
     const int64_t i0 = ti * TM, j0 = tj * TN;
 
     // planes are slab-major: k-slab s (64 wide) of a plane is m_pad x 64 bytes at s * slabA
@@ -455,6 +453,67 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
     }
 }
 
+template <int KIND, typename C, bool DUMP>
+__global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, BoundArgs b) {
+    const bool bound = KIND == KIND_BOUND;
+    const int64_t TR = (bound ? b.m_pad : a.m_pad) / C::TM, TC = (bound ? b.n_pad : a.n_pad) / C::TN;
+    const int nmod = bound ? 1 : a.nmod;
+    int l;
+    int64_t ti, tj;
+    map_tile((int64_t)blockIdx.x, TR, TC, (int64_t)nmod * TR * TC, l, ti, tj);
+    gemm_tile<KIND, C, DUMP>(a, b, l, ti, tj);
+}
+
+// Persistent kernel over the work queue of a batch: each block takes the next
+// item from the counter until the queue is empty.  Items of one problem are
+// numbered (modulus group, tile row, tile column); problems are ordered by the
+// host (largest k first).
+template <int KIND, typename C>
+__global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm *probs, int nprob,
+                                                                int64_t items, int group, int nmod,
+                                                                const NTable *tab,
+                                                                uint32_t *counter) {
+    __shared__ int64_t item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t w = item_s;
+        __syncthreads();
+        if (w >= items) break;
+        int lo = 0, hi = nprob - 1;  // last problem whose first item is <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].item0 <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchGemm &pb = probs[lo];
+        const int64_t T = (int64_t)pb.TR * pb.TC, local = w - pb.item0;
+        const int lg = (int)(local / T);
+        const int64_t t = local - (int64_t)lg * T;
+        const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
+        GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, nmod, KIND == KIND_4M ? 1 : 0, tab,
+                   pb.eprime, nullptr, C::TM};
+        const int l1 = min(nmod, (lg + 1) * group);
+        for (int l = lg * group; l < l1; ++l) gemm_tile<KIND, C, false>(a, BoundArgs{}, l, ti, tj);
+    }
+}
+
+template <int KIND, typename C>
+void launch_batch_kind(const BatchGemm *probs, int nprob, int64_t items, int group, int nmod,
+                       const NTable *tab, uint32_t *counter, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((batch_gemm_kernel<KIND, C>), dim3((unsigned)grid), dim3(C::THREADS), 0, s,
+                       probs, nprob, items, group, nmod, tab, counter);
+}
+
+template <int KIND, typename C>
+int blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_gemm_kernel<KIND, C>, C::THREADS, 0) !=
+        hipSuccess)
+        n = 1;
+    return n > 0 ? n : 1;
+}
+
 template <int KIND, typename C>
 void launch_kind(const GemmArgs &a, const BoundArgs &b, bool dump, int64_t blocks, hipStream_t s) {
     if (dump) hipLaunchKernelGGL((residue_gemm_kernel<KIND, C, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a, b);
@@ -493,6 +552,33 @@ hipError_t launch_bound_gemm(const BoundArgs &b, hipStream_t s) {
     const int64_t blocks = (b.m_pad / tile) * (b.n_pad / tile);
     GemmArgs none{};
     launch_kind<KIND_BOUND, CfgSmall>(none, b, false, blocks, s);
+    return hipGetLastError();
+}
+
+int batch_gemm_blocks_per_cu(int tile) {
+    return tile == 256 ? blocks_per_cu<KIND_KARATSUBA, CfgLarge>() : blocks_per_cu<KIND_KARATSUBA, CfgSmall>();
+}
+
+hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile, int group,
+                             int nmod, int algo, const NTable *tab, uint32_t *counter,
+                             int grid_blocks, hipStream_t s) {
+    if (items <= 0 || nprob <= 0) return hipSuccess;
+    if ((tile != 128 && tile != 256) || group < 1 || nmod < 1) return hipErrorInvalidValue;
+    if (grid_blocks <= 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        grid_blocks = cus * batch_gemm_blocks_per_cu(tile);
+    }
+    if ((int64_t)grid_blocks > items) grid_blocks = (int)items;
+    if (tile == 256) {
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLarge>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgLarge>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+    } else {
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+    }
     return hipGetLastError();
 }
 

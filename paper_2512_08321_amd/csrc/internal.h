@@ -74,8 +74,8 @@ hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, co
                         int64_t k_pad, hipStream_t s);
 
 struct GemmArgs {
-    const int8_t *A;      // [N][planes][m_pad][k_pad]
-    const int8_t *B;      // [N][planes][n_pad][k_pad]
+    const int8_t *A;      // [N][planes][k_pad/64][m_pad][64] (slab-major planes)
+    const int8_t *B;      // [N][planes][k_pad/64][n_pad][64]
     int64_t m_pad, n_pad, k_pad;
     int nmod;
     int algo;             // 0 Karatsuba, 1 expanded (4 products)
@@ -115,6 +115,56 @@ struct CrtArgs {
 hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s);
 hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
                           double ai, double br, double bi, hipStream_t s);
+
+// ---------------------------------------------------------------- batched problems
+// Many independent problems share one launch per phase: every block of a
+// batched launch first finds its problem (segments are sorted by their first
+// block) and then runs the same code as the single-problem kernel.
+struct BatchOperand {       // op(A) rows or op(B) columns of one problem
+    OperandView v;
+    uint64_t *maxbits, *sigma;  // rows_pad entries each, zeroed before the scan
+    int16_t *mu;                // rows_pad
+    int8_t *res;                // residue planes, slab-major, rows_pad x k_pad each
+    int64_t rows_pad, k_pad;
+    int64_t blk_scan, blk_exp, blk_split;  // first block in each phase's grid
+};
+// Blocks an operand needs in each phase (the host builds the prefix sums with these).
+int64_t batch_scan_blocks(const OperandView &v);
+int64_t batch_exp_blocks(int64_t rows_pad);
+int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad);
+hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                             bool sigma, hipStream_t s);
+hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
+                                       const NTable *tab, uint32_t *status, hipStream_t s);
+hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                              const NTable *tab, int nmod, int nplanes, int nchunks,
+                              hipStream_t s);
+
+struct BatchGemm {          // one problem of a batched product launch
+    const int8_t *A, *B;
+    int8_t *eprime;
+    int64_t m_pad, n_pad, k_pad;
+    int64_t item0;          // first work item; items run (modulus group, tile row, tile column)
+    int32_t TR, TC;         // tiles per column and per row of the output
+};
+// Persistent product kernel over a work queue of (problem, modulus group, tile)
+// items, handed out by an atomic counter that must be zero at launch.  `group`
+// moduli are computed one after another per item.  grid_blocks <= 0 picks one
+// wave of resident blocks.
+hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile,
+                             int group, int nmod, int algo, const NTable *tab, uint32_t *counter,
+                             int grid_blocks, hipStream_t s);
+// Resident blocks of the persistent product kernel per compute unit, for a tile edge.
+int batch_gemm_blocks_per_cu(int tile);
+
+struct BatchCrt {
+    CrtArgs a;
+    int64_t blk0;
+};
+int64_t batch_crt_blocks(int64_t m_pad, int64_t n);
+hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
+                            bool single, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 // Verification (Freivalds) and test hooks.
 hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t cols, int64_t ld,

@@ -90,12 +90,15 @@ __global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t v) {
 
 // ---------------------------------------------------------------- row max |x|
 
+// Block (bx, by) of the scan grids: contig rows take 4 rows x kHChunk elements
+// (a wave per row), strided rows 256 rows x kHChunk / 8 elements.
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t *maxbits) {
+__device__ __forceinline__ void maxabs_contig_body(const OperandView &v, uint64_t *maxbits,
+                                                   int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t r = bx * 4 + wave;
     if (r >= v.rows) return;
-    const int64_t h0 = (int64_t)blockIdx.y * kHChunk;
+    const int64_t h0 = by * kHChunk;
     const int64_t h1 = min(v.k, h0 + kHChunk);
     uint64_t m = 0;
     for (int64_t h = h0 + lane; h < h1; h += 64) {
@@ -109,10 +112,11 @@ __global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t
 }
 
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void maxabs_strided_body(const OperandView &v, uint64_t *maxbits,
+                                                    int64_t bx, int64_t by) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= v.rows) return;
-    const int64_t h0 = (int64_t)blockIdx.y * (kHChunk / 8);
+    const int64_t h0 = by * (kHChunk / 8);
     const int64_t h1 = min(v.k, h0 + kHChunk / 8);
     uint64_t m = 0;
     for (int64_t h = h0; h < h1; ++h) {
@@ -128,15 +132,15 @@ __global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_
 // an integer upper bound of 2^(2F) ||row / 2^e_r||_2^2, independent of summation order.
 
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uint64_t *maxbits,
-                                                        uint64_t *sigma) {
+__device__ __forceinline__ void sigma_contig_body(const OperandView &v, const uint64_t *maxbits,
+                                                  uint64_t *sigma, int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t r = bx * 4 + wave;
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
     if (mb == 0 || mb >= kInfBits) return;
     const int sh = kSigmaFracBits - ilogb_bits(mb);
-    const int64_t h0 = (int64_t)blockIdx.y * kHChunk;
+    const int64_t h0 = by * kHChunk;
     const int64_t h1 = min(v.k, h0 + kHChunk);
     uint64_t s = 0;
     for (int64_t h = h0 + lane; h < h1; h += 64) {
@@ -150,14 +154,14 @@ __global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uin
 }
 
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const uint64_t *maxbits,
-                                                         uint64_t *sigma) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void sigma_strided_body(const OperandView &v, const uint64_t *maxbits,
+                                                   uint64_t *sigma, int64_t bx, int64_t by) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
     if (mb == 0 || mb >= kInfBits) return;
     const int sh = kSigmaFracBits - ilogb_bits(mb);
-    const int64_t h0 = (int64_t)blockIdx.y * (kHChunk / 8);
+    const int64_t h0 = by * (kHChunk / 8);
     const int64_t h1 = min(v.k, h0 + kHChunk / 8);
     uint64_t s = 0;
     for (int64_t h = h0; h < h1; ++h) {
@@ -175,10 +179,11 @@ __global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const ui
 // exact integer form).  Accurate mode: mu_r = (5 - e_r) + t with t the largest
 // integer such that 2 X_r 4^t <= P - 1, X_r the row maximum of the bound product.
 
-__global__ void fast_exponents_kernel(const uint64_t *maxbits, const uint64_t *sigma,
-                                      int64_t rows, int64_t rows_pad, const NTable *tab,
-                                      int16_t *mu, uint32_t *status) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fast_exponents_body(const uint64_t *maxbits, const uint64_t *sigma,
+                                                    int64_t rows, int64_t rows_pad,
+                                                    const NTable *tab, int16_t *mu,
+                                                    uint32_t *status, int64_t bx) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= rows_pad) return;
     int16_t out = kExpZero;
     if (r < rows) {
@@ -282,14 +287,14 @@ __device__ __forceinline__ int sum_residue(int a, int b, const ModConst &mc) {
 }
 
 template <bool SINGLE, bool CONTIG_H, int NPLANES, int NCHUNK, bool CEIL7>
-__global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *mu,
-                                                    const uint64_t *maxbits, const NTable *tab,
-                                                    int nmod, int8_t *dst, int64_t rows_pad,
-                                                    int64_t k_pad) {
+__device__ __forceinline__ void split_body(const OperandView &v, const int16_t *mu,
+                                           const uint64_t *maxbits, const NTable *tab, int nmod,
+                                           int8_t *dst, int64_t rows_pad, int64_t k_pad,
+                                           int64_t bx, int64_t by) {
     __shared__ __align__(16) int8_t lds[NPLANES][kTileR][kLdsPitch];
     const int tid = threadIdx.x;
-    const int64_t h0 = (int64_t)blockIdx.x * kTileH;
-    const int64_t r0 = (int64_t)blockIdx.y * kTileR;
+    const int64_t h0 = bx * kTileH;
+    const int64_t r0 = by * kTileR;
     const int64_t plane_pitch = rows_pad * k_pad;
 
     // element coordinates of this thread (8 elements)
@@ -370,11 +375,138 @@ __global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t
             const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
             const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
             int8_t *out = dst + ((int64_t)l * NPLANES + pl) * plane_pitch +
-                          ((int64_t)blockIdx.x * rows_pad + r0 + row) * kTileH + seg * 16;
+                          (bx * rows_pad + r0 + row) * kTileH + seg * 16;
             *reinterpret_cast<uint4 *>(out) = val;
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------- kernels (one problem)
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t *maxbits) {
+    maxabs_contig_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y);
+}
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits) {
+    maxabs_strided_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y);
+}
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uint64_t *maxbits,
+                                                        uint64_t *sigma) {
+    sigma_contig_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y);
+}
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const uint64_t *maxbits,
+                                                         uint64_t *sigma) {
+    sigma_strided_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *maxbits,
+                                                             const uint64_t *sigma, int64_t rows,
+                                                             int64_t rows_pad, const NTable *tab,
+                                                             int16_t *mu, uint32_t *status) {
+    fast_exponents_body(maxbits, sigma, rows, rows_pad, tab, mu, status, blockIdx.x);
+}
+template <bool SINGLE, bool CONTIG_H, int NPLANES, int NCHUNK, bool CEIL7>
+__global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *mu,
+                                                    const uint64_t *maxbits, const NTable *tab,
+                                                    int nmod, int8_t *dst, int64_t rows_pad,
+                                                    int64_t k_pad) {
+    split_body<SINGLE, CONTIG_H, NPLANES, NCHUNK, CEIL7>(v, mu, maxbits, tab, nmod, dst, rows_pad,
+                                                         k_pad, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- kernels (batched)
+
+// Last segment whose first block is <= b (first blocks ascending).
+template <typename F>
+__device__ __forceinline__ int find_seg(int n, int64_t b, F first) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__host__ __device__ __forceinline__ int64_t scan_grid_x(const OperandView &v) {
+    return v.contig_h ? (v.rows + 3) / 4 : (v.rows + 255) / 256;
+}
+__host__ __device__ __forceinline__ int64_t scan_grid_y(const OperandView &v) {
+    const int64_t hc = v.contig_h ? kHChunk : kHChunk / 8;
+    return (v.k + hc - 1) / hc;
+}
+
+template <bool SINGLE, bool SIGMA>
+__global__ __launch_bounds__(256) void batch_scan_kernel(const BatchOperand *ops, int nops) {
+    const int64_t b = blockIdx.x;
+    const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_scan; });
+    const OperandView v = ops[o].v;
+    const int64_t lb = b - ops[o].blk_scan, gx = scan_grid_x(v);
+    const int64_t bx = lb % gx, by = lb / gx;
+    if (v.contig_h) {
+        if constexpr (SIGMA) sigma_contig_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by);
+        else maxabs_contig_body<SINGLE>(v, ops[o].maxbits, bx, by);
+    } else {
+        if constexpr (SIGMA) sigma_strided_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by);
+        else maxabs_strided_body<SINGLE>(v, ops[o].maxbits, bx, by);
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_fast_exponents_kernel(const BatchOperand *ops, int nops,
+                                                                   const NTable *tab,
+                                                                   uint32_t *status) {
+    const int64_t b = blockIdx.x;
+    const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_exp; });
+    const BatchOperand &op = ops[o];
+    fast_exponents_body(op.maxbits, op.sigma, op.v.rows, op.rows_pad, tab, op.mu, status,
+                        b - op.blk_exp);
+}
+
+template <bool SINGLE, int NPLANES, int NCHUNK>
+__global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops,
+                                                          const NTable *tab, int nmod) {
+    const int64_t b = blockIdx.x;
+    const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_split; });
+    const BatchOperand &op = ops[o];
+    const int64_t lb = b - op.blk_split, gx = op.k_pad / kTileH;
+    const int64_t bx = lb % gx, by = lb / gx;
+    if (op.v.contig_h)
+        split_body<SINGLE, true, NPLANES, NCHUNK, false>(op.v, op.mu, nullptr, tab, nmod, op.res,
+                                                         op.rows_pad, op.k_pad, bx, by);
+    else
+        split_body<SINGLE, false, NPLANES, NCHUNK, false>(op.v, op.mu, nullptr, tab, nmod, op.res,
+                                                          op.rows_pad, op.k_pad, bx, by);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <bool SINGLE, int NPLANES>
+hipError_t batch_split_chunks(const BatchOperand *ops, int nops, int64_t blocks, const NTable *tab,
+                              int nmod, int nchunks, hipStream_t s) {
+    dim3 grid((unsigned)blocks);
+#define OZC_BSPLIT_CASE(NC)                                                                  \
+    case NC:                                                                                 \
+        hipLaunchKernelGGL((batch_split_kernel<SINGLE, NPLANES, NC>), grid, dim3(256), 0, s, \
+                           ops, nops, tab, nmod);                                            \
+        break;
+    switch (nchunks) {
+        OZC_BSPLIT_CASE(1)
+        OZC_BSPLIT_CASE(2)
+        OZC_BSPLIT_CASE(3)
+        OZC_BSPLIT_CASE(4)
+        OZC_BSPLIT_CASE(5)
+        OZC_BSPLIT_CASE(6)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef OZC_BSPLIT_CASE
+    return hipGetLastError();
 }
 
 template <bool SINGLE, bool CONTIG_H, int NPLANES, bool CEIL7>
@@ -487,6 +619,54 @@ hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbi
     return v.contig_h ? split_dispatch_chunks<false, true, 3, true>(OZC_C7_ARGS)
                       : split_dispatch_chunks<false, false, 3, true>(OZC_C7_ARGS);
 #undef OZC_C7_ARGS
+}
+
+int64_t batch_scan_blocks(const OperandView &v) {
+    if (v.rows <= 0 || v.k <= 0) return 0;
+    return scan_grid_x(v) * scan_grid_y(v);
+}
+int64_t batch_exp_blocks(int64_t rows_pad) { return (rows_pad + 255) / 256; }
+int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad) {
+    return (k_pad / kTileH) * (rows_pad / kTileR);
+}
+
+hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                             bool sigma, hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    dim3 grid((unsigned)blocks);
+    if (single) {
+        if (sigma) hipLaunchKernelGGL((batch_scan_kernel<true, true>), grid, dim3(256), 0, s, ops, nops);
+        else hipLaunchKernelGGL((batch_scan_kernel<true, false>), grid, dim3(256), 0, s, ops, nops);
+    } else {
+        if (sigma) hipLaunchKernelGGL((batch_scan_kernel<false, true>), grid, dim3(256), 0, s, ops, nops);
+        else hipLaunchKernelGGL((batch_scan_kernel<false, false>), grid, dim3(256), 0, s, ops, nops);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
+                                       const NTable *tab, uint32_t *status, hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_fast_exponents_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops,
+                       tab, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                              const NTable *tab, int nmod, int nplanes, int nchunks,
+                              hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    if (single)
+        return nplanes == 3 ? batch_split_chunks<true, 3>(ops, nops, blocks, tab, nmod, nchunks, s)
+                            : batch_split_chunks<true, 2>(ops, nops, blocks, tab, nmod, nchunks, s);
+    return nplanes == 3 ? batch_split_chunks<false, 3>(ops, nops, blocks, tab, nmod, nchunks, s)
+                        : batch_split_chunks<false, 2>(ops, nops, blocks, tab, nmod, nchunks, s);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
 }
 
 }  // namespace ozc
