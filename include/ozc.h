@@ -95,7 +95,9 @@ ozc_status_t ozc_set_stream(ozc_handle_t handle, void *stream);
  * N; moduli are the first N of 256, 255, 253, 251, 247, 241, ... , the
  * greedy descending pairwise-coprime integers <= 256), scaling mode and
  * product algorithm for the following calls.  Default: N = 14, fast,
- * Karatsuba.  Errors: INVALID_VALUE. */
+ * Karatsuba.  num_moduli == 0 selects the learned choice (see "moduli-count
+ * predictor" below) for ozc_zgemm; ozc_cgemm then uses N = 9.  Batched calls
+ * and ozc_inspect keep the last fixed N.  Errors: INVALID_VALUE. */
 ozc_status_t ozc_set_config(ozc_handle_t handle, int num_moduli, ozc_mode_t mode,
                             ozc_algo_t algo);
 
@@ -173,7 +175,9 @@ typedef struct {
  *   accepted iff for every row i
  *   |w_i - alpha z_i - beta v_i| <= rel (|alpha| (|A||B||x|)_i + |beta| (|C_in||x|)_i)
  *                                    + g (|C||x| + |alpha| |A||B||x| + |beta| |C_in||x|)_i
- * with g = 4 (n + k + 4) 2^-53 covering the double-precision evaluation.  rel <= 0
+ * with the three products accumulated in double-double arithmetic and
+ * g = 4 (n + k + 4) 2^-104 covering that evaluation, so that tolerances well
+ * below double precision (e.g. a 1e-15 target) can be checked.  rel <= 0
  * selects 4 k 2^-53 for ZGEMM and 4 k 2^-24 for CGEMM.  On failure, with
  * escalate != 0, the call reruns with N + 2 moduli (at most OZC_MAX_MODULI;
  * C_in is saved first when beta != 0) and finally returns
@@ -263,6 +267,71 @@ ozc_status_t ozc_batch_tune(ozc_handle_t handle, int single, int count, const oz
                             const int64_t *k, const void *const *A, const int64_t *lda,
                             const void *const *B, const int64_t *ldb,
                             ozc_batch_policy_t *chosen);
+
+/* ------------------------------------------------------------------ moduli-count predictor
+ * (an addition of this library; the paper fixes N by hand).  A perceptron
+ * OZC_MLP_FEATURES -> OZC_MLP_HIDDEN -> OZC_MLP_HIDDEN -> OZC_MLP_CLASSES (ReLU,
+ * FP32) maps cheap statistics of op(A) and op(B) to a class c, N = OZC_MLP_MIN_N
+ * + c (the last class stands for "more than 24" and gives 24).  With N = 0
+ * configured, every ozc_zgemm call computes the statistics, predicts N (this
+ * synchronises the stream), adds the margin and runs with it; with the
+ * Freivalds check enabled, a failure escalates N as usual.  Until parameters
+ * are set or trained, the fixed fallback count is used.
+ *
+ * Parameter vector (OZC_MLP_PARAMS floats): W1 (H x F, row-major), b1 (H), W2
+ * (H x H), b2 (H), W3 (C x H), b3 (C), mu (F), sd (F); inputs are standardised
+ * as (x - mu) / sd before the first layer. */
+#define OZC_MLP_FEATURES 20
+#define OZC_MLP_HIDDEN 64
+#define OZC_MLP_CLASSES 20
+#define OZC_MLP_MIN_N 6
+#define OZC_MLP_PARAMS (OZC_MLP_HIDDEN * OZC_MLP_FEATURES + OZC_MLP_HIDDEN + \
+                        OZC_MLP_HIDDEN * OZC_MLP_HIDDEN + OZC_MLP_HIDDEN + \
+                        OZC_MLP_CLASSES * OZC_MLP_HIDDEN + OZC_MLP_CLASSES + 2 * OZC_MLP_FEATURES)
+
+/* Statistics of op(A) (m x k) and op(B) (k x n) into `features` (device, 20
+ * floats): log2 m, log2 n, log2 k; min, max, mean, std over the nonzero rows
+ * of op(A) of l2 = 0.5 log2 sum (|x| 2^-e)^2 and of l1 = log2 sum |x| 2^-e
+ * (the 2k reals of a row, e = floor(log2 max |x|), as in the scaling step of
+ * Section III-B); the same over the columns of op(B); the fraction of zero
+ * reals.  m, n, k >= 1.  Asynchronous. */
+ozc_status_t ozc_features(ozc_handle_t handle, int single, ozc_op_t transa, ozc_op_t transb,
+                          int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                          const void *B, int64_t ldb, float *features);
+
+/* Host copies of the parameter vector (count must be OZC_MLP_PARAMS; every
+ * sd entry > 0).  get fails with INVALID_VALUE before parameters exist. */
+ozc_status_t ozc_mlp_set_params(ozc_handle_t handle, const float *params, int count);
+ozc_status_t ozc_mlp_get_params(ozc_handle_t handle, float *params, int count);
+
+/* Logits (device, rows x OZC_MLP_CLASSES) for feature rows X (device, rows x
+ * OZC_MLP_FEATURES).  Asynchronous. */
+ozc_status_t ozc_mlp_forward(ozc_handle_t handle, const float *X, int rows, float *logits);
+
+/* Gradient (device, OZC_MLP_PARAMS floats; zero for mu, sd) of the mean softmax
+ * cross-entropy over rows X with labels y (device int, classes) at the current
+ * parameters; *loss (host, may be NULL) receives the loss (synchronises). */
+ozc_status_t ozc_mlp_grad(ozc_handle_t handle, const float *X, const int *y, int rows,
+                          float *grad, float *loss);
+
+/* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) for `epochs`
+ * passes over (X, y) (device) in mini-batches of `batch` rows, shuffled per
+ * epoch with SplitMix64(seed) draws (a batch >= rows keeps the row order).
+ * init != 0 (or no parameters yet): mu, sd from the data, He-uniform weights
+ * from SplitMix64(seed), zero biases.  epoch_loss (host, epochs floats, may be
+ * NULL) receives the mean batch loss per epoch.  Synchronises. */
+ozc_status_t ozc_mlp_train(ozc_handle_t handle, const float *X, const int *y, int rows,
+                           int epochs, int batch, float lr, uint64_t seed, int init,
+                           float *epoch_loss);
+
+/* Fallback N (used without parameters; default 18) and a margin added to every
+ * prediction (default 0, at most 8). */
+ozc_status_t ozc_set_auto_moduli(ozc_handle_t handle, int fallback, int margin);
+
+/* The N the predictor would choose for this product (synchronises). */
+ozc_status_t ozc_predict_moduli(ozc_handle_t handle, int single, ozc_op_t transa,
+                                ozc_op_t transb, int64_t m, int64_t n, int64_t k, const void *A,
+                                int64_t lda, const void *B, int64_t ldb, int *num_moduli);
 
 /* Synchronises the handle's stream and reports on the last call.  Returns
  * NONFINITE when the last call met inf/NaN input (info still filled). */

@@ -86,8 +86,21 @@ EXPORTS = {
     "ozc_get_batch_policy": [_VP, ctypes.POINTER(BatchPolicy)],
     "ozc_batch_tune": [_VP, _INT, _INT, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                        ctypes.POINTER(BatchPolicy)],
+    "ozc_features": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP],
+    "ozc_mlp_set_params": [_VP, _VP, _INT],
+    "ozc_mlp_get_params": [_VP, _VP, _INT],
+    "ozc_mlp_forward": [_VP, _VP, _INT, _VP],
+    "ozc_mlp_grad": [_VP, _VP, _VP, _INT, _VP, _VP],
+    "ozc_mlp_train": [_VP, _VP, _VP, _INT, _INT, _INT, ctypes.c_float, ctypes.c_uint64, _INT, _VP],
+    "ozc_set_auto_moduli": [_VP, _INT, _INT],
+    "ozc_predict_moduli": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64,
+                           ctypes.POINTER(_INT)],
     "ozc_status_string": [_INT],
 }
+
+MLP_FEATURES, MLP_HIDDEN, MLP_CLASSES, MLP_MIN_N = 20, 64, 20, 6
+MLP_PARAMS = (MLP_HIDDEN * MLP_FEATURES + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN
+              + MLP_CLASSES * MLP_HIDDEN + MLP_CLASSES + 2 * MLP_FEATURES)
 
 
 def lib():
@@ -142,6 +155,7 @@ class Handle:
             pass
 
     def set_config(self, num_moduli: int, mode: str = "fast", algo: str = "karatsuba"):
+        """num_moduli = 0 selects the learned per-call choice (ozc_zgemm)."""
         _check(lib().ozc_set_config(self._h, int(num_moduli), MODE[mode], ALGO[algo]), "ozc_set_config")
         self.num_moduli, self.mode, self.algo = int(num_moduli), mode, algo
 
@@ -218,6 +232,59 @@ class Handle:
         _check(lib().ozc_batch_tune(self._h, int(bool(single)), b.count, b.ta, b.tb, b.m, b.n, b.k,
                                     b.A, b.lda, b.B, b.ldb, ctypes.byref(p)), "ozc_batch_tune")
         return _policy_dict(p)
+
+    # ---------------------------------------------------------- moduli-count predictor
+    def features(self, transa, transb, m, n, k, A, lda, B, ldb, out, single=False, stream=None):
+        """ozc_features into ``out`` (device float32 tensor of MLP_FEATURES entries)."""
+        self.set_stream(stream)
+        _check(lib().ozc_features(self._h, int(bool(single)), OP[transa], OP[transb], m, n, k,
+                                  _ptr(A), lda, _ptr(B), ldb, _ptr(out)), "ozc_features")
+
+    def mlp_set_params(self, params):
+        import numpy as np
+
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().ozc_mlp_set_params(self._h, p.ctypes.data, p.size), "ozc_mlp_set_params")
+
+    def mlp_get_params(self):
+        import numpy as np
+
+        p = np.zeros(MLP_PARAMS, np.float32)
+        _check(lib().ozc_mlp_get_params(self._h, p.ctypes.data, p.size), "ozc_mlp_get_params")
+        return p
+
+    def mlp_forward(self, X, rows, logits, stream=None):
+        self.set_stream(stream)
+        _check(lib().ozc_mlp_forward(self._h, _ptr(X), int(rows), _ptr(logits)), "ozc_mlp_forward")
+
+    def mlp_grad(self, X, y, rows, grad, stream=None) -> float:
+        self.set_stream(stream)
+        loss = ctypes.c_float()
+        _check(lib().ozc_mlp_grad(self._h, _ptr(X), _ptr(y), int(rows), _ptr(grad),
+                                  ctypes.byref(loss)), "ozc_mlp_grad")
+        return loss.value
+
+    def mlp_train(self, X, y, rows, epochs, batch=256, lr=1e-3, seed=1, init=True, stream=None):
+        import numpy as np
+
+        self.set_stream(stream)
+        losses = np.zeros(max(1, epochs), np.float32)
+        _check(lib().ozc_mlp_train(self._h, _ptr(X), _ptr(y), int(rows), int(epochs), int(batch),
+                                   float(lr), int(seed), int(bool(init)), losses.ctypes.data),
+               "ozc_mlp_train")
+        return losses[:epochs]
+
+    def set_auto_moduli(self, fallback=18, margin=0):
+        _check(lib().ozc_set_auto_moduli(self._h, int(fallback), int(margin)), "ozc_set_auto_moduli")
+
+    def predict_moduli(self, transa, transb, m, n, k, A, lda, B, ldb, single=False,
+                       stream=None) -> int:
+        self.set_stream(stream)
+        N = _INT()
+        _check(lib().ozc_predict_moduli(self._h, int(bool(single)), OP[transa], OP[transb], m, n, k,
+                                        _ptr(A), lda, _ptr(B), ldb, ctypes.byref(N)),
+               "ozc_predict_moduli")
+        return N.value
 
     def set_profiling(self, enable: bool):
         _check(lib().ozc_set_profiling(self._h, int(bool(enable))), "ozc_set_profiling")

@@ -1,0 +1,163 @@
+"""Training data, training and evaluation of the moduli-count predictor.
+
+Instances follow the paper's generator (Section IV-A: entries (u - 0.5)
+exp(phi g), u uniform, g standard normal) with uneven shapes, phi up to 8 and
+power-of-two skews along k (skews of whole rows or columns do not change the
+required N, since the exponent rules of Section III-B absorb them).  The label
+of an instance is the smallest N in [6, 24] whose result meets the target
+max_ij |C_N - C_ref|_ij / (|A||B|)_ij <= target, with C_ref the N = 24 result
+and |A||B| the product of the moduli (both computed by the library itself);
+instances that need more than 24 get the extra class.  Everything runs
+through the C-ABI (statistics, emulation, training, prediction).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import Handle, MLP_CLASSES, MLP_FEATURES, MLP_MIN_N
+
+MAX_N = 24
+
+
+def draw_instance(rng, lo=64, hi=512, klo=64, khi=4096, phi_max=8.0, skew_max=40, device="cuda"):
+    """One instance (A, B) as column-major device tensors (op = N) plus its parameters."""
+    import torch
+
+    m = n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    k = int(round(math.exp(rng.uniform(math.log(klo), math.log(khi)))))
+    phi = float(rng.uniform(0.0, phi_max))
+    sigma = int(rng.integers(0, skew_max + 1))
+    seed = int(rng.integers(0, 2 ** 62))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+
+    def mat(rows, cols):
+        x = torch.rand((2, cols, rows), dtype=torch.float64, device=device, generator=gen) - 0.5
+        g = torch.randn((2, cols, rows), dtype=torch.float64, device=device, generator=gen)
+        x = x * torch.exp(phi * g)
+        return torch.complex(x[0], x[1])  # (cols, rows): column-major rows x cols
+
+    A = mat(m, k)
+    B = mat(k, n)
+    if sigma > 0:  # power-of-two skew along k (columns of A, rows of B), exact scaling
+        ea = torch.from_numpy(rng.integers(0, sigma + 1, k).astype(np.float64)).to(device)
+        eb = torch.from_numpy(rng.integers(0, sigma + 1, k).astype(np.float64)).to(device)
+        A = A * torch.exp2(-ea)[:, None]
+        B = B * torch.exp2(-eb)[None, :]
+    return dict(m=m, n=n, k=k, phi=phi, sigma=sigma, A=A.contiguous(), B=B.contiguous())
+
+
+def _emulate(h, inst, N, C):
+    h.set_config(N, "fast", "karatsuba")
+    m, n, k = inst["m"], inst["n"], inst["k"]
+    h.zgemm("N", "N", m, n, k, 1.0, inst["A"], m, inst["B"], k, 0.0, C, m)
+
+
+def error_profile(h, inst, Ns):
+    """max relative error (against |A||B|) of the N-moduli results, N in Ns."""
+    import torch
+
+    m, n, k = inst["m"], inst["n"], inst["k"]
+    Cref = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+    _emulate(h, inst, MAX_N, Cref)
+    absA = torch.complex(inst["A"].abs(), torch.zeros_like(inst["A"].real))
+    absB = torch.complex(inst["B"].abs(), torch.zeros_like(inst["B"].real))
+    absAB = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+    h.set_config(16, "fast", "karatsuba")
+    h.zgemm("N", "N", m, n, k, 1.0, absA, m, absB, k, 0.0, absAB, m)
+    den = absAB.real.clamp_min(torch.finfo(torch.float64).tiny)
+    C = torch.empty_like(Cref)
+    out = {}
+    for N in Ns:
+        _emulate(h, inst, N, C)
+        out[N] = float(((C - Cref).abs() / den).max())
+    return out
+
+
+def label(h, inst, target):
+    """Smallest N in [6, 24] meeting the target, by bisection (error falls with N);
+    MAX_N + 1 if even 24 misses it."""
+    lo, hi = MLP_MIN_N, MAX_N
+    cache = {}
+
+    def ok(N):
+        if N not in cache:
+            cache.update(error_profile(h, inst, [N]))
+        return cache[N] <= target
+
+    if not ok(hi):
+        return MAX_N + 1
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if ok(mid):
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo
+
+
+def features(h, inst):
+    import torch
+
+    out = torch.empty(MLP_FEATURES, dtype=torch.float32, device="cuda")
+    m, n, k = inst["m"], inst["n"], inst["k"]
+    h.features("N", "N", m, n, k, inst["A"], m, inst["B"], k, out)
+    return out
+
+
+def generate(h, count, seed, target=1e-15, log=None, **kw):
+    """Features (count x F, float32, device) and labels (count, int32 classes, device)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    X = torch.empty((count, MLP_FEATURES), dtype=torch.float32, device="cuda")
+    y = torch.empty(count, dtype=torch.int32, device="cuda")
+    meta = []
+    t0 = time.perf_counter()
+    for i in range(count):
+        inst = draw_instance(rng, **kw)
+        X[i] = features(h, inst)
+        N = label(h, inst, target)
+        y[i] = N - MLP_MIN_N
+        meta.append((inst["m"], inst["k"], inst["phi"], inst["sigma"], N))
+        if log and (i + 1) % max(1, count // 10) == 0:
+            log(f"[autoN] {i + 1}/{count} instances labelled ({time.perf_counter() - t0:.1f} s)")
+    return X, y, meta
+
+
+def fixed_rule(labels_N, quantile=0.999):
+    """The conservative fixed count: smallest N meeting the target on the given share
+    of the training instances (at most 24)."""
+    Ns = np.sort(np.asarray(labels_N))
+    idx = min(len(Ns) - 1, int(math.ceil(quantile * len(Ns))) - 1)
+    return int(min(MAX_N, Ns[idx]))
+
+
+def evaluate(h, insts, target, margin=0):
+    """Run every instance with the learned N (Freivalds check at the target, escalation
+    by 2): returns per-instance (predicted N, N used, escalations, error)."""
+    import torch
+
+    res = []
+    h.set_auto_moduli(fallback=MAX_N, margin=margin)
+    for inst in insts:
+        m, n, k = inst["m"], inst["n"], inst["k"]
+        N_hat = h.predict_moduli("N", "N", m, n, k, inst["A"], m, inst["B"], k)
+        C = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+        h.set_config(0, "fast", "karatsuba")
+        h.set_verify(True, rel=target, escalate=True)
+        try:
+            h.zgemm("N", "N", m, n, k, 1.0, inst["A"], m, inst["B"], k, 0.0, C, m)
+            status = 0
+        except Exception as e:  # verification failure at 24 moduli
+            status = getattr(e, "status", -1)
+        info = h.last_info()
+        h.set_verify(False)
+        prof = error_profile(h, inst, [info["num_moduli"]])
+        res.append(dict(N_hat=N_hat, N_used=info["num_moduli"], esc=info["escalations"],
+                        err=prof[info["num_moduli"]], status=status))
+    h.set_config(14, "fast", "karatsuba")
+    return res

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libozc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["tables.cpp", "api.cpp", "batched.cpp", "prep.hip", "gemm.hip", "crt.hip", "verify.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "batched.cpp", "autoN.cpp", "prep.hip", "gemm.hip", "crt.hip",
+           "verify.hip", "mlp.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -360,6 +360,22 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
                           int64_t lda, const void *B, int64_t ldb, const double beta[2], void *C,
                           int64_t ldc) {
     h->attempt = 0;
+    struct RestoreN0 {
+        ozc_context *h;
+        int n0;
+        ~RestoreN0() { h->nmod = n0; }
+    } restore0{h, h->nmod};
+    if (h->auto_n) {
+        ozc_status_t sa = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
+        if (sa != OZC_STATUS_SUCCESS) return sa;
+        int N = 9;  // complex64: the fixed count (single-precision level)
+        if (!single) {
+            OZC_TRY(hipSetDevice(h->device));
+            sa = predict_moduli(h, single, ta, tb, m, n, k, A, lda, B, ldb, &N);
+            if (sa != OZC_STATUS_SUCCESS) return sa;
+        }
+        h->nmod = N;
+    }
     if (!h->verify) return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
     ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
     if (st != OZC_STATUS_SUCCESS) return st;
@@ -378,10 +394,11 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
         off = align_up(off + b);
         return o;
     };
-    const size_t o_y = take(16 * vk), o_ya = take(8 * vk);
-    const size_t o_z = take(16 * vm), o_za = take(8 * vm);
-    const size_t o_w = take(16 * vm), o_wa = take(8 * vm);
-    const size_t o_v = take(16 * vm), o_va = take(8 * vm);
+    // double-double vectors: high parts, low parts, absolute sums
+    const size_t o_y = take(16 * vk), o_yl = take(16 * vk), o_ya = take(8 * vk);
+    const size_t o_z = take(16 * vm), o_zl = take(16 * vm), o_za = take(8 * vm);
+    const size_t o_w = take(16 * vm), o_wl = take(16 * vm), o_wa = take(8 * vm);
+    const size_t o_v = take(16 * vm), o_vl = take(16 * vm), o_va = take(8 * vm);
     size_t scr = gemv_scratch_bytes(m, n);
     if (ta == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(m, k));
     if (tb == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(k, n));
@@ -393,6 +410,8 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
     char *vw = (char *)h->vws;
     double2 *y = (double2 *)(vw + o_y), *z = (double2 *)(vw + o_z), *w = (double2 *)(vw + o_w),
             *v = (double2 *)(vw + o_v);
+    double2 *yl = (double2 *)(vw + o_yl), *zl = (double2 *)(vw + o_zl),
+            *wl = (double2 *)(vw + o_wl), *vl = (double2 *)(vw + o_vl);
     double *ya = (double *)(vw + o_ya), *za = (double *)(vw + o_za), *wa = (double *)(vw + o_wa),
            *va = (double *)(vw + o_va);
     void *scratch = vw + o_scr;
@@ -401,10 +420,12 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
     const uint64_t seed = h->verify_seed;
     const double rel = h->verify_rel > 0.0 ? h->verify_rel
                                             : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
-    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-53;
+    // rounding of the double-double evaluation itself
+    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-104;
     if (!beta_zero) {
         OZC_TRY(hipMemcpy2DAsync(cin, es * m, C, es * ldc, es * m, n, hipMemcpyDeviceToDevice, s));
-        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, seed, v, va, scratch, s));
+        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, v, vl, va,
+                            scratch, s));
     }
     struct RestoreN {
         ozc_context *h;
@@ -419,13 +440,15 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
         st = run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
         if (st != OZC_STATUS_SUCCESS) break;
         // y = op(B) x (k), z = op(A) y (m), w = C x (m)
-        if (tb == OZC_OP_N) OZC_TRY(launch_gemv(B, single, 0, k, n, ldb, nullptr, nullptr, seed, y, ya, scratch, s));
-        else OZC_TRY(launch_gemv(B, single, (int)tb, n, k, ldb, nullptr, nullptr, seed, y, ya, scratch, s));
-        if (ta == OZC_OP_N) OZC_TRY(launch_gemv(A, single, 0, m, k, lda, y, ya, 0, z, za, scratch, s));
-        else OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, y, ya, 0, z, za, scratch, s));
-        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, seed, w, wa, scratch, s));
-        OZC_TRY(launch_freivalds_rows(w, wa, z, za, beta_zero ? nullptr : v, va, m, alpha, beta, rel,
-                                      gam, word, s));
+        if (tb == OZC_OP_N)
+            OZC_TRY(launch_gemv(B, single, 0, k, n, ldb, nullptr, nullptr, nullptr, seed, y, yl, ya, scratch, s));
+        else
+            OZC_TRY(launch_gemv(B, single, (int)tb, n, k, ldb, nullptr, nullptr, nullptr, seed, y, yl, ya, scratch, s));
+        if (ta == OZC_OP_N) OZC_TRY(launch_gemv(A, single, 0, m, k, lda, y, yl, ya, 0, z, zl, za, scratch, s));
+        else OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, y, yl, ya, 0, z, zl, za, scratch, s));
+        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, w, wl, wa, scratch, s));
+        OZC_TRY(launch_freivalds_rows(w, wl, wa, z, zl, za, beta_zero ? nullptr : v, vl, va, m, alpha,
+                                      beta, rel, gam, word, s));
         unsigned long long host[2] = {0, 0};
         OZC_TRY(hipMemcpyAsync(host, word, sizeof(host), hipMemcpyDeviceToHost, s));
         OZC_TRY(hipStreamSynchronize(s));
@@ -507,6 +530,7 @@ ozc_status_t ozc_destroy(ozc_handle_t h) {
     if (h->ws_own) (void)hipFree(h->ws_own);
     if (h->vws) (void)hipFree(h->vws);
     batch_release(h);
+    mlp_release(h);
     (void)hipFree(h->tab_dev);
     (void)hipFree(h->status_dev);
     delete h;
@@ -521,10 +545,12 @@ ozc_status_t ozc_set_stream(ozc_handle_t h, void *stream) {
 
 ozc_status_t ozc_set_config(ozc_handle_t h, int num_moduli, ozc_mode_t mode, ozc_algo_t algo) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
-    if (num_moduli < OZC_MIN_MODULI || num_moduli > OZC_MAX_MODULI) return OZC_STATUS_INVALID_VALUE;
+    if (num_moduli != 0 && (num_moduli < OZC_MIN_MODULI || num_moduli > OZC_MAX_MODULI))
+        return OZC_STATUS_INVALID_VALUE;
     if (mode != OZC_MODE_FAST && mode != OZC_MODE_ACCURATE) return OZC_STATUS_INVALID_VALUE;
     if (algo != OZC_ALGO_KARATSUBA && algo != OZC_ALGO_4M) return OZC_STATUS_INVALID_VALUE;
-    h->nmod = num_moduli;
+    h->auto_n = num_moduli == 0;
+    if (num_moduli != 0) h->nmod = num_moduli;
     h->mode = mode;
     h->algo = algo;
     return OZC_STATUS_SUCCESS;

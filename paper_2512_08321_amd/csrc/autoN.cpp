@@ -1,0 +1,365 @@
+// Learned choice of the moduli count (include/ozc.h, "moduli-count predictor"):
+// input statistics, the perceptron's buffers, its training loop, and the
+// per-call prediction used when the handle is configured with N = 0.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "context.h"
+
+namespace ozc {
+
+constexpr MlpDims kDims{OZC_MLP_FEATURES, OZC_MLP_HIDDEN, OZC_MLP_CLASSES};
+
+struct MlpState {
+    float *params = nullptr;  // device, mlp_offsets(kDims).total floats
+    float *m = nullptr, *v = nullptr, *grad = nullptr;
+    float *loss_acc = nullptr;
+    int *pred = nullptr;
+    bool have_params = false;
+    // activations, sized for `rows_cap` rows
+    int rows_cap = 0;
+    float *acts = nullptr;
+    MlpActs a{};
+    int *idx = nullptr;
+    int idx_cap = 0;
+    // statistics scratch for one operand pair
+    int64_t stat_rows = 0;
+    char *stat = nullptr;
+    float *feat = nullptr;  // 1 x F
+    int n_fix = 18;         // fallback moduli count
+    int margin = 0;         // added to the predicted count
+
+    void release() {
+        for (void *p : {(void *)params, (void *)m, (void *)v, (void *)grad, (void *)loss_acc,
+                        (void *)pred, (void *)acts, (void *)idx, (void *)stat, (void *)feat})
+            if (p) (void)hipFree(p);
+    }
+};
+
+void mlp_release(ozc_context *h) {
+    if (!h->mlp) return;
+    h->mlp->release();
+    delete h->mlp;
+    h->mlp = nullptr;
+}
+
+namespace {
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+MlpState *mlp_state(ozc_context *h) {
+    if (h->mlp) return h->mlp;
+    MlpState *st = new (std::nothrow) MlpState();
+    if (!st) return nullptr;
+    const int P = mlp_offsets(kDims).total;
+    if (dev_alloc(&st->params, P) != hipSuccess || dev_alloc(&st->m, P) != hipSuccess ||
+        dev_alloc(&st->v, P) != hipSuccess || dev_alloc(&st->grad, P) != hipSuccess ||
+        dev_alloc(&st->loss_acc, 1) != hipSuccess || dev_alloc(&st->pred, 1) != hipSuccess ||
+        dev_alloc(&st->feat, kDims.F) != hipSuccess) {
+        st->release();
+        delete st;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    h->mlp = st;
+    return st;
+}
+
+ozc_status_t ensure_acts(MlpState *st, int rows) {
+    if (rows <= st->rows_cap) return OZC_STATUS_SUCCESS;
+    if (st->acts) (void)hipFree(st->acts);
+    st->acts = nullptr;
+    st->rows_cap = 0;
+    const size_t H = kDims.H, C = kDims.C, F = kDims.F, R = (size_t)rows;
+    const size_t total = R * (6 * H + 2 * C + 1 + F);
+    if (dev_alloc(&st->acts, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    float *p = st->acts;
+    auto take = [&](size_t n) {
+        float *q = p;
+        p += n;
+        return q;
+    };
+    st->a.a1 = take(R * H);
+    st->a.h1 = take(R * H);
+    st->a.a2 = take(R * H);
+    st->a.h2 = take(R * H);
+    st->a.d2 = take(R * H);
+    st->a.d1 = take(R * H);
+    st->a.z = take(R * C);
+    st->a.dz = take(R * C);
+    st->a.loss_r = take(R);
+    st->a.xs = take(R * F);
+    st->rows_cap = rows;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ensure_stats(MlpState *st, int64_t rows) {
+    if (rows <= st->stat_rows) return OZC_STATUS_SUCCESS;
+    if (st->stat) (void)hipFree(st->stat);
+    st->stat = nullptr;
+    st->stat_rows = 0;
+    // per row: maxbits (8), s1 (8), s2 (8); plus one zero counter
+    if (dev_alloc(&st->stat, (size_t)rows * 24 + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    st->stat_rows = rows;
+    return OZC_STATUS_SUCCESS;
+}
+
+uint64_t splitmix64(uint64_t state, uint64_t i) {
+    uint64_t z = state + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t seed, uint64_t i) { return (double)(splitmix64(seed, i) >> 11) * 0x1p-53; }
+
+}  // namespace
+
+// Statistics of op(A) (m x k) and op(B) (k x n) into st->feat (device, F floats).
+ozc_status_t compute_features(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                              int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                              int64_t ldb, float *out) {
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    ozc_status_t s = ensure_stats(st, m + n);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    hipStream_t str = h->stream;
+    uint64_t *mb = (uint64_t *)st->stat;
+    double *s1 = (double *)(st->stat + 8 * (size_t)(m + n));
+    double *s2 = (double *)(st->stat + 16 * (size_t)(m + n));
+    unsigned long long *zeros = (unsigned long long *)(st->stat + 24 * (size_t)(m + n));
+    OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, s1, s2 (0.0), zeros
+    const OperandView vA = view_A(A, ta, m, k, lda), vB = view_B(B, tb, n, k, ldb);
+    OZC_TRY(launch_row_maxabs(vA, single, mb, str));
+    OZC_TRY(launch_row_maxabs(vB, single, mb + m, str));
+    OZC_TRY(launch_feat_sums(vA, single, mb, s1, s2, zeros, str));
+    OZC_TRY(launch_feat_sums(vB, single, mb + m, s1 + m, s2 + m, zeros, str));
+    OZC_TRY(launch_feat_reduce(s1, s2, m, s1 + m, s2 + m, n, zeros, m, n, k, out, str));
+    return OZC_STATUS_SUCCESS;
+}
+
+// Predicted N for one product (synchronises the stream).  Without parameters:
+// the fixed fallback count.
+ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                            int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                            int64_t ldb, int *N) {
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    if (!st->have_params || m == 0 || n == 0 || k == 0) {
+        *N = st->n_fix;
+        return OZC_STATUS_SUCCESS;
+    }
+    ozc_status_t s = compute_features(h, single, ta, tb, m, n, k, A, lda, B, ldb, st->feat);
+    if (s == OZC_STATUS_SUCCESS) s = ensure_acts(st, 1);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    OZC_TRY(launch_mlp_forward(kDims, st->params, st->feat, nullptr, 1, st->a, h->stream));
+    OZC_TRY(launch_argmax(st->a.z, 1, kDims.C, st->pred, h->stream));
+    int cls = 0;
+    OZC_TRY(hipMemcpyAsync(&cls, st->pred, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    OZC_TRY(hipStreamSynchronize(h->stream));
+    *N = std::min(OZC_MAX_MODULI, std::max(OZC_MIN_MODULI, OZC_MLP_MIN_N + cls + st->margin));
+    return OZC_STATUS_SUCCESS;
+}
+
+}  // namespace ozc
+
+using namespace ozc;
+
+extern "C" {
+
+ozc_status_t ozc_features(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                          int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                          int64_t ldb, float *features) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    ozc_status_t s = check_args(ta, tb, m, n, k, A, lda, B, ldb, nullptr, m > 1 ? m : 1, true);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    if (m == 0 || n == 0 || k == 0 || !features) return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipSetDevice(h->device));
+    return compute_features(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, features);
+}
+
+ozc_status_t ozc_mlp_set_params(ozc_handle_t h, const float *params, int count) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!params || count != mlp_offsets(kDims).total) return OZC_STATUS_INVALID_VALUE;
+    const MlpOffsets o = mlp_offsets(kDims);
+    for (int i = 0; i < kDims.F; ++i)
+        if (!(params[o.sd + i] > 0.f)) return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipSetDevice(h->device));
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    OZC_TRY(hipMemcpy(st->params, params, sizeof(float) * count, hipMemcpyHostToDevice));
+    st->have_params = true;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_mlp_get_params(ozc_handle_t h, float *params, int count) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!params || count != mlp_offsets(kDims).total) return OZC_STATUS_INVALID_VALUE;
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    if (!st->have_params) return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipStreamSynchronize(h->stream));
+    OZC_TRY(hipMemcpy(params, st->params, sizeof(float) * count, hipMemcpyDeviceToHost));
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_mlp_forward(ozc_handle_t h, const float *X, int rows, float *logits) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (rows < 0 || (rows > 0 && (!X || !logits))) return OZC_STATUS_INVALID_VALUE;
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    if (!st->have_params) return OZC_STATUS_INVALID_VALUE;
+    if (rows == 0) return OZC_STATUS_SUCCESS;
+    OZC_TRY(hipSetDevice(h->device));
+    ozc_status_t s = ensure_acts(st, rows);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    MlpActs a = st->a;
+    a.z = logits;
+    OZC_TRY(launch_mlp_forward(kDims, st->params, X, nullptr, rows, a, h->stream));
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_mlp_grad(ozc_handle_t h, const float *X, const int *y, int rows, float *grad,
+                          float *loss) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (rows <= 0 || !X || !y || !grad) return OZC_STATUS_INVALID_VALUE;
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    if (!st->have_params) return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipSetDevice(h->device));
+    ozc_status_t s = ensure_acts(st, rows);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    OZC_TRY(launch_fill_f32(st->loss_acc, 1, 0.f, h->stream));
+    OZC_TRY(launch_mlp_grad(kDims, st->params, X, y, nullptr, rows, st->a, grad, st->loss_acc,
+                            h->stream));
+    if (loss) {
+        OZC_TRY(hipMemcpyAsync(loss, st->loss_acc, sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        OZC_TRY(hipStreamSynchronize(h->stream));
+    }
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_mlp_train(ozc_handle_t h, const float *X, const int *y, int rows, int epochs,
+                           int batch, float lr, uint64_t seed, int init, float *epoch_loss) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (rows <= 0 || epochs < 0 || batch <= 0 || !(lr > 0.f) || !X || !y)
+        return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipSetDevice(h->device));
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    const MlpOffsets o = mlp_offsets(kDims);
+    hipStream_t s = h->stream;
+    if (init || !st->have_params) {
+        // standardisation from the data, He-uniform weights, zero biases
+        std::vector<float> hx((size_t)rows * kDims.F);
+        OZC_TRY(hipStreamSynchronize(s));
+        OZC_TRY(hipMemcpy(hx.data(), X, hx.size() * sizeof(float), hipMemcpyDeviceToHost));
+        std::vector<float> p((size_t)o.total, 0.f);
+        for (int f = 0; f < kDims.F; ++f) {
+            double mean = 0.0, sq = 0.0;
+            for (int r = 0; r < rows; ++r) mean += hx[(size_t)r * kDims.F + f];
+            mean /= rows;
+            for (int r = 0; r < rows; ++r) {
+                const double d = hx[(size_t)r * kDims.F + f] - mean;
+                sq += d * d;
+            }
+            const double sd = sqrt(sq / rows);
+            p[(size_t)o.mu + f] = (float)mean;
+            p[(size_t)o.sd + f] = (float)(sd > 1e-6 ? sd : 1.0);
+        }
+        uint64_t ctr = 0;
+        auto fill = [&](int off, int fan_in, int count) {
+            const double lim = sqrt(6.0 / fan_in);
+            for (int i = 0; i < count; ++i) p[(size_t)off + i] = (float)((2.0 * uniform01(seed, ctr++) - 1.0) * lim);
+        };
+        fill(o.W1, kDims.F, kDims.H * kDims.F);
+        fill(o.W2, kDims.H, kDims.H * kDims.H);
+        fill(o.W3, kDims.H, kDims.C * kDims.H);
+        OZC_TRY(hipMemcpy(st->params, p.data(), sizeof(float) * o.total, hipMemcpyHostToDevice));
+        st->have_params = true;
+    }
+    OZC_TRY(launch_fill_f32(st->m, o.total, 0.f, s));
+    OZC_TRY(launch_fill_f32(st->v, o.total, 0.f, s));
+    const int B = std::min(batch, rows);
+    ozc_status_t r = ensure_acts(st, B);
+    if (r != OZC_STATUS_SUCCESS) return r;
+    if (rows > st->idx_cap) {
+        if (st->idx) (void)hipFree(st->idx);
+        st->idx = nullptr;
+        st->idx_cap = 0;
+        if (dev_alloc(&st->idx, (size_t)rows) != hipSuccess) {
+            (void)hipGetLastError();
+            return OZC_STATUS_ALLOC_FAILED;
+        }
+        st->idx_cap = rows;
+    }
+    std::vector<int> perm((size_t)rows);
+    const int steps = (rows + B - 1) / B;
+    int t = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = 0; i < rows; ++i) perm[(size_t)i] = i;
+        if (B < rows)  // Fisher-Yates with SplitMix64 draws; a full batch keeps the row order
+            for (int i = rows - 1; i > 0; --i) {
+                const int j = (int)(splitmix64(seed ^ 0xA5A5A5A5ull, (uint64_t)ep * rows + i) % (uint64_t)(i + 1));
+                std::swap(perm[(size_t)i], perm[(size_t)j]);
+            }
+        OZC_TRY(hipStreamSynchronize(s));  // perm is read by the copy below
+        OZC_TRY(hipMemcpy(st->idx, perm.data(), sizeof(int) * rows, hipMemcpyHostToDevice));
+        OZC_TRY(launch_fill_f32(st->loss_acc, 1, 0.f, s));
+        for (int b = 0; b < steps; ++b) {
+            const int r0 = b * B, nb = std::min(B, rows - r0);
+            OZC_TRY(launch_mlp_grad(kDims, st->params, X, y, st->idx + r0, nb, st->a, st->grad,
+                                    st->loss_acc, s));
+            OZC_TRY(launch_adam(st->params, st->grad, st->m, st->v, o.trainable, lr, 0.9f, 0.999f,
+                                1e-8f, ++t, s));
+        }
+        if (epoch_loss) {
+            float acc = 0.f;
+            OZC_TRY(hipMemcpyAsync(&acc, st->loss_acc, sizeof(float), hipMemcpyDeviceToHost, s));
+            OZC_TRY(hipStreamSynchronize(s));
+            epoch_loss[ep] = acc / (float)steps;
+        }
+    }
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_set_auto_moduli(ozc_handle_t h, int fallback, int margin) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (fallback < OZC_MIN_MODULI || fallback > OZC_MAX_MODULI || margin < 0 || margin > 8)
+        return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipSetDevice(h->device));
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    st->n_fix = fallback;
+    st->margin = margin;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_predict_moduli(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                                int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                                int64_t ldb, int *num_moduli) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!num_moduli) return OZC_STATUS_INVALID_VALUE;
+    ozc_status_t s = check_args(ta, tb, m, n, k, A, lda, B, ldb, nullptr, m > 1 ? m : 1, true);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    OZC_TRY(hipSetDevice(h->device));
+    return predict_moduli(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, num_moduli);
+}
+
+}  // extern "C"

@@ -9,6 +9,7 @@
 
 namespace ozc {
 struct BatchState;  // batched-call plans and tuning (batched.cpp)
+struct MlpState;    // moduli-count predictor (autoN.cpp)
 }
 
 struct ozc_context {
@@ -38,6 +39,8 @@ struct ozc_context {
     std::vector<std::array<hipEvent_t, 5>> prof_pending;  // per call: phase boundaries
     std::vector<hipEvent_t> event_pool;
     ozc::BatchState *batch = nullptr;
+    ozc::MlpState *mlp = nullptr;
+    bool auto_n = false;  // choose N per ozc_zgemm call
 };
 
 
@@ -57,4 +60,8 @@ ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t 
                         int64_t lda, const void *B, int64_t ldb, const void *C, int64_t ldc,
                         bool c_optional);
 void batch_release(ozc_context *h);
+void mlp_release(ozc_context *h);
+ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                            int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                            int64_t ldb, int *N);
 }  // namespace ozc

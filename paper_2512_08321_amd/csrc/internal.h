@@ -166,13 +166,53 @@ hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, in
                             bool single, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
+// ---------------------------------------------------------------- moduli-count predictor
+struct MlpDims {
+    int F, H, C;
+};
+struct MlpOffsets {
+    int W1, b1, W2, b2, W3, b3, mu, sd, total, trainable;
+};
+inline MlpOffsets mlp_offsets(const MlpDims &d) {
+    MlpOffsets o{};
+    o.W1 = 0;
+    o.b1 = o.W1 + d.H * d.F;
+    o.W2 = o.b1 + d.H;
+    o.b2 = o.W2 + d.H * d.H;
+    o.W3 = o.b2 + d.H;
+    o.b3 = o.W3 + d.C * d.H;
+    o.mu = o.b3 + d.C;
+    o.sd = o.mu + d.F;
+    o.total = o.sd + d.F;
+    o.trainable = o.mu;
+    return o;
+}
+struct MlpActs {  // device buffers for `rows` rows
+    float *a1, *h1, *a2, *h2, *z, *dz, *loss_r, *d2, *d1, *xs;
+};
+hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits, double *s1,
+                            double *s2, unsigned long long *zeros, hipStream_t s);
+hipError_t launch_feat_reduce(const double *s1a, const double *s2a, int64_t ra, const double *s1b,
+                              const double *s2b, int64_t rb, const unsigned long long *zeros,
+                              int64_t m, int64_t n, int64_t k, float *out, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpDims &d, const float *params, const float *X, const int *idx,
+                              int rows, MlpActs &a, hipStream_t s);
+hipError_t launch_mlp_grad(const MlpDims &d, const float *params, const float *X, const int *y,
+                           const int *idx, int rows, MlpActs &a, float *grad, float *loss_acc,
+                           hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t s);
+hipError_t launch_argmax(const float *z, int rows, int C, int *out, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int n, float v, hipStream_t s);
+
 // Verification (Freivalds) and test hooks.
 hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t cols, int64_t ld,
-                       const double2 *xv, const double *xa, uint64_t seed, double2 *y, double *ya,
-                       void *scratch, hipStream_t s);
+                       const double2 *xv, const double2 *xlo, const double *xa, uint64_t seed,
+                       double2 *y, double2 *ylo, double *ya, void *scratch, hipStream_t s);
 size_t gemv_scratch_bytes(int64_t rows, int64_t cols);
-hipError_t launch_freivalds_rows(const double2 *w, const double *wa, const double2 *z,
-                                 const double *za, const double2 *v, const double *va, int64_t m,
+hipError_t launch_freivalds_rows(const double2 *w, const double2 *wl, const double *wa,
+                                 const double2 *z, const double2 *zl, const double *za,
+                                 const double2 *v, const double2 *vl, const double *va, int64_t m,
                                  const double alpha[2], const double beta[2], double rel,
                                  double gam, unsigned long long *worst, hipStream_t s);
 hipError_t launch_debug_xor_byte(int8_t *p, hipStream_t s);

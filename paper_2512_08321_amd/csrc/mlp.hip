@@ -1,0 +1,350 @@
+// Moduli-count predictor: input statistics and a small FP32 perceptron with its
+// training step (forward, softmax cross-entropy, backward, Adam).  Not part of
+// the paper; it chooses N before the emulation runs (the scheme's accuracy grows
+// by about 2^-7.8 per added modulus, Section II).
+//
+// Statistics: per row of op(A) / column of op(B) (2k reals), with e = floor(log2
+// max|x|), l2 = 0.5 log2 sum (|x| 2^-e)^2 and l1 = log2 sum |x| 2^-e; the feature
+// vector holds log2 m, log2 n, log2 k, min/max/mean/std of l2 and l1 over the
+// nonzero rows of each operand, and the fraction of zero reals.
+//
+// Network (parameter layout shared with the C-ABI): xs = (x - mu) / sd,
+// h1 = relu(W1 xs + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3; W row-major
+// (out x in).  Every reduction runs in a fixed order, so training is
+// reproducible run to run.
+#include <math.h>
+
+#include "internal.h"
+
+namespace ozc {
+namespace {
+
+constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
+
+template <bool SINGLE>
+__device__ __forceinline__ void load2(const void *base, int64_t idx, double &re, double &im) {
+    if constexpr (SINGLE) {
+        const float2 v = reinterpret_cast<const float2 *>(base)[idx];
+        re = v.x;
+        im = v.y;
+    } else {
+        const double2 v = reinterpret_cast<const double2 *>(base)[idx];
+        re = v.x;
+        im = v.y;
+    }
+}
+
+// 2^-e for the row whose largest magnitude has the bit pattern mb (0 < mb < inf)
+__device__ __forceinline__ double inv_pow2_of(uint64_t mb) {
+    const int ef = (int)(mb >> 52);
+    const int e = ef == 0 ? -1074 + 63 - __clzll((long long)mb) : ef - 1023;
+    return ldexp(1.0, -e);
+}
+
+constexpr int kFeatChunk = 2048;
+
+// Sums s1 = sum |x| 2^-e, s2 = sum (|x| 2^-e)^2 and the zero count of one row,
+// one block per (row group, k chunk); rows with k contiguous take a wave per row.
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uint64_t *maxbits,
+                                                        double *s1, double *s2,
+                                                        unsigned long long *zeros) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t r, h0, h1, step;
+    if (v.contig_h) {
+        r = (int64_t)blockIdx.x * 4 + wave;
+        h0 = (int64_t)blockIdx.y * kFeatChunk + lane;
+        step = 64;
+    } else {
+        r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        h0 = (int64_t)blockIdx.y * (kFeatChunk / 8);
+        step = 1;
+    }
+    h1 = min(v.k, (int64_t)(v.contig_h ? (int64_t)blockIdx.y * kFeatChunk + kFeatChunk
+                                       : (int64_t)blockIdx.y * (kFeatChunk / 8) + kFeatChunk / 8));
+    if (r >= v.rows) return;
+    const uint64_t mb = maxbits[r];
+    const double sc = (mb != 0 && mb < 0x7ff0000000000000ull) ? inv_pow2_of(mb) : 0.0;
+    double a1 = 0.0, a2 = 0.0;
+    unsigned long long z = 0;
+    for (int64_t h = h0; h < h1; h += step) {
+        double re, im;
+        load2<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
+        const double x = fabs(re) * sc, y = fabs(im) * sc;
+        a1 += x + y;
+        a2 = fma(x, x, fma(y, y, a2));
+        z += (re == 0.0) + (im == 0.0);
+    }
+    if (v.contig_h) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a1 += __shfl_xor(a1, off, 64);
+            a2 += __shfl_xor(a2, off, 64);
+            z += __shfl_xor(z, off, 64);
+        }
+        if (lane != 0) return;
+    }
+    atomicAdd(&s1[r], a1);
+    atomicAdd(&s2[r], a2);
+    if (z) atomicAdd(&zeros[0], z);
+}
+
+// One block: statistics of l2 and l1 over the nonzero rows of both operands.
+__global__ __launch_bounds__(256) void feat_reduce_kernel(const double *s1a, const double *s2a,
+                                                          int64_t ra, const double *s1b,
+                                                          const double *s2b, int64_t rb,
+                                                          const unsigned long long *zeros,
+                                                          double m, double n, double k,
+                                                          float *out) {
+    __shared__ double red[256][5];
+    const int t = threadIdx.x;
+    float res[16];
+    for (int op = 0; op < 2; ++op) {
+        const double *s1 = op ? s1b : s1a, *s2 = op ? s2b : s2a;
+        const int64_t rows = op ? rb : ra;
+        for (int q = 0; q < 2; ++q) {  // q = 0: l2, 1: l1
+            double mn = INFINITY, mx = -INFINITY, sum = 0.0, sq = 0.0, cnt = 0.0;
+            for (int64_t r = t; r < rows; r += 256) {
+                if (!(s2[r] > 0.0)) continue;
+                const double x = q == 0 ? 0.5 * log2(s2[r]) : log2(s1[r]);
+                mn = fmin(mn, x);
+                mx = fmax(mx, x);
+                sum += x;
+                sq += x * x;
+                cnt += 1.0;
+            }
+            red[t][0] = mn;
+            red[t][1] = mx;
+            red[t][2] = sum;
+            red[t][3] = sq;
+            red[t][4] = cnt;
+            __syncthreads();
+            for (int w = 128; w >= 1; w >>= 1) {
+                if (t < w) {
+                    red[t][0] = fmin(red[t][0], red[t + w][0]);
+                    red[t][1] = fmax(red[t][1], red[t + w][1]);
+                    red[t][2] += red[t + w][2];
+                    red[t][3] += red[t + w][3];
+                    red[t][4] += red[t + w][4];
+                }
+                __syncthreads();
+            }
+            const double c = red[0][4];
+            const double mean = c > 0 ? red[0][2] / c : 0.0;
+            const double var = c > 0 ? fmax(0.0, red[0][3] / c - mean * mean) : 0.0;
+            float *o = res + op * 8 + q * 4;
+            o[0] = c > 0 ? (float)red[0][0] : 0.f;
+            o[1] = c > 0 ? (float)red[0][1] : 0.f;
+            o[2] = (float)mean;
+            o[3] = (float)sqrt(var);
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        out[0] = (float)log2(m);
+        out[1] = (float)log2(n);
+        out[2] = (float)log2(k);
+        for (int i = 0; i < 16; ++i) out[3 + i] = res[i];
+        out[19] = (float)((double)zeros[0] / (2.0 * (m + n) * k));
+    }
+}
+
+// ---------------------------------------------------------------- network
+
+// out[r][o] = act(sum_i W[o][i] in[idx(r)][i] + b[o]); pre keeps the pre-activation.
+// With `standardize`, the input is (x - mu) / sd first.
+__global__ void dense_fwd_kernel(const float *in, const int *idx, int rows, int din, int dout,
+                                 const float *W, const float *b, const float *mu, const float *sd,
+                                 int relu, float *pre, float *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * dout) return;
+    const int r = t / dout, o = t % dout;
+    const int src = idx ? idx[r] : r;
+    const float *x = in + (int64_t)src * din;
+    float acc = b[o];
+    for (int i = 0; i < din; ++i) {
+        const float xi = mu ? (x[i] - mu[i]) / sd[i] : x[i];
+        acc = fmaf(W[o * din + i], xi, acc);
+    }
+    if (pre) pre[(int64_t)r * dout + o] = acc;
+    out[(int64_t)r * dout + o] = relu ? fmaxf(acc, 0.f) : acc;
+}
+
+// standardised copy of the gathered batch (input of the first layer's weight gradient)
+__global__ void standardize_kernel(const float *in, const int *idx, int rows, int din,
+                                   const float *mu, const float *sd, float *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * din) return;
+    const int r = t / din, i = t % din;
+    const int src = idx ? idx[r] : r;
+    out[t] = (in[(int64_t)src * din + i] - mu[i]) / sd[i];
+}
+
+// dz = (softmax(z) - onehot(y)) / rows, loss_r = logsumexp(z) - z[y]
+__global__ void softmax_ce_kernel(const float *z, const int *y, const int *idx, int rows, int C,
+                                  float *dz, float *loss_r) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const float *zr = z + (int64_t)r * C;
+    float mx = zr[0];
+    for (int c = 1; c < C; ++c) mx = fmaxf(mx, zr[c]);
+    float s = 0.f;
+    for (int c = 0; c < C; ++c) s += expf(zr[c] - mx);
+    const int yr = y[idx ? idx[r] : r];
+    for (int c = 0; c < C; ++c) {
+        const float p = expf(zr[c] - mx) / s;
+        dz[(int64_t)r * C + c] = (p - (c == yr ? 1.f : 0.f)) / (float)rows;
+    }
+    loss_r[r] = (mx + logf(s)) - zr[yr];
+}
+
+// gW[o][i] = sum_r dout[r][o] in[r][i], gb[o] = sum_r dout[r][o] (rows in order)
+__global__ void dense_bwd_w_kernel(const float *dout, const float *in, int rows, int din, int dimo,
+                                   float *gW, float *gb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < dimo * din) {
+        const int o = t / din, i = t % din;
+        float acc = 0.f;
+        for (int r = 0; r < rows; ++r) acc = fmaf(dout[(int64_t)r * dimo + o], in[(int64_t)r * din + i], acc);
+        gW[t] = acc;
+    } else if (t < dimo * din + dimo) {
+        const int o = t - dimo * din;
+        float acc = 0.f;
+        for (int r = 0; r < rows; ++r) acc += dout[(int64_t)r * dimo + o];
+        gb[o] = acc;
+    }
+}
+
+// din_grad[r][i] = (sum_o dout[r][o] W[o][i]) * [pre[r][i] > 0]
+__global__ void dense_bwd_x_kernel(const float *dout, const float *W, const float *pre, int rows,
+                                   int din, int dimo, float *dx) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * din) return;
+    const int r = t / din, i = t % din;
+    float acc = 0.f;
+    for (int o = 0; o < dimo; ++o) acc = fmaf(dout[(int64_t)r * dimo + o], W[o * din + i], acc);
+    dx[t] = pre[t] > 0.f ? acc : 0.f;
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
+                            float b2, float eps, float bc1, float bc2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// one block: sum of the per-row losses in row order (thread 0), accumulated into *acc
+__global__ void loss_sum_kernel(const float *loss_r, int rows, float *acc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += loss_r[r];
+    *acc += s / (float)rows;
+}
+
+__global__ void fill_f32_kernel(float *p, int n, float v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void argmax_kernel(const float *z, int rows, int C, int *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    int best = 0;
+    for (int c = 1; c < C; ++c)
+        if (z[(int64_t)r * C + c] > z[(int64_t)r * C + best]) best = c;
+    out[r] = best;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits, double *s1,
+                            double *s2, unsigned long long *zeros, hipStream_t s) {
+    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+    dim3 grid;
+    if (v.contig_h) grid = dim3((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kFeatChunk - 1) / kFeatChunk));
+    else grid = dim3((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + kFeatChunk / 8 - 1) / (kFeatChunk / 8)));
+    if (single) hipLaunchKernelGGL(feat_sums_kernel<true>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
+    else hipLaunchKernelGGL(feat_sums_kernel<false>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
+    return hipGetLastError();
+}
+
+hipError_t launch_feat_reduce(const double *s1a, const double *s2a, int64_t ra, const double *s1b,
+                              const double *s2b, int64_t rb, const unsigned long long *zeros,
+                              int64_t m, int64_t n, int64_t k, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(feat_reduce_kernel, dim3(1), dim3(256), 0, s, s1a, s2a, ra, s1b, s2b, rb, zeros,
+                       (double)m, (double)n, (double)k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpDims &d, const float *params, const float *X, const int *idx,
+                              int rows, MlpActs &a, hipStream_t s) {
+    const MlpOffsets o = mlp_offsets(d);
+    const float *W1 = params + o.W1, *b1 = params + o.b1, *W2 = params + o.W2, *b2 = params + o.b2,
+                *W3 = params + o.W3, *b3 = params + o.b3, *mu = params + o.mu, *sd = params + o.sd;
+    hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks_for((int64_t)rows * d.H)), dim3(256), 0, s, X, idx,
+                       rows, d.F, d.H, W1, b1, mu, sd, 1, a.a1, a.h1);
+    hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks_for((int64_t)rows * d.H)), dim3(256), 0, s, a.h1,
+                       nullptr, rows, d.H, d.H, W2, b2, nullptr, nullptr, 1, a.a2, a.h2);
+    hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks_for((int64_t)rows * d.C)), dim3(256), 0, s, a.h2,
+                       nullptr, rows, d.H, d.C, W3, b3, nullptr, nullptr, 0, nullptr, a.z);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const MlpDims &d, const float *params, const float *X, const int *y,
+                           const int *idx, int rows, MlpActs &a, float *grad, float *loss_acc,
+                           hipStream_t s) {
+    hipError_t e = launch_mlp_forward(d, params, X, idx, rows, a, s);
+    if (e != hipSuccess) return e;
+    const MlpOffsets o = mlp_offsets(d);
+    const float *W2 = params + o.W2, *W3 = params + o.W3, *mu = params + o.mu, *sd = params + o.sd;
+    hipLaunchKernelGGL(softmax_ce_kernel, dim3(blocks_for(rows)), dim3(256), 0, s, a.z, y, idx, rows, d.C,
+                       a.dz, a.loss_r);
+    if (loss_acc) hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, s, a.loss_r, rows, loss_acc);
+    // layer 3
+    hipLaunchKernelGGL(dense_bwd_w_kernel, dim3(blocks_for((int64_t)d.C * d.H + d.C)), dim3(256), 0, s,
+                       a.dz, a.h2, rows, d.H, d.C, grad + o.W3, grad + o.b3);
+    hipLaunchKernelGGL(dense_bwd_x_kernel, dim3(blocks_for((int64_t)rows * d.H)), dim3(256), 0, s, a.dz,
+                       W3, a.a2, rows, d.H, d.C, a.d2);
+    // layer 2
+    hipLaunchKernelGGL(dense_bwd_w_kernel, dim3(blocks_for((int64_t)d.H * d.H + d.H)), dim3(256), 0, s,
+                       a.d2, a.h1, rows, d.H, d.H, grad + o.W2, grad + o.b2);
+    hipLaunchKernelGGL(dense_bwd_x_kernel, dim3(blocks_for((int64_t)rows * d.H)), dim3(256), 0, s, a.d2,
+                       W2, a.a1, rows, d.H, d.H, a.d1);
+    // layer 1 (input: the standardised features)
+    hipLaunchKernelGGL(standardize_kernel, dim3(blocks_for((int64_t)rows * d.F)), dim3(256), 0, s, X, idx,
+                       rows, d.F, mu, sd, a.xs);
+    hipLaunchKernelGGL(dense_bwd_w_kernel, dim3(blocks_for((int64_t)d.H * d.F + d.H)), dim3(256), 0, s,
+                       a.d1, a.xs, rows, d.F, d.H, grad + o.W1, grad + o.b1);
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(2 * d.F)), dim3(256), 0, s, grad + o.mu, 2 * d.F,
+                       0.f);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t s) {
+    const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps,
+                       bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmax(const float *z, int rows, int C, int *out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(argmax_kernel, dim3(blocks_for(rows)), dim3(256), 0, s, z, rows, C, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace ozc

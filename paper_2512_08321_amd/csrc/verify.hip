@@ -3,10 +3,13 @@
 // the result is accepted when, for every row i,
 //   |w_i - alpha z_i - beta v_i| <= tol_i,
 //   tol_i = rel (|alpha| (|A| (|B| |x|))_i + |beta| (|C_in| |x|)_i) + eval_i,
-// where eval_i bounds the double-precision rounding of the three products
-// themselves (Higham's gamma_n applied to the same absolute sums).  A wrong
-// entry c_ij moves w_i by |c_ij - c*_ij| (|x_j| = 1), so an error larger than
-// the tolerance in any row is caught with probability >= 1/2 per vector.
+// where eval_i bounds the rounding of the check itself.  The three products
+// are accumulated in double-double arithmetic (error-free sums and products,
+// Dekker / Knuth; products via fused multiply-add), so eval_i is of order
+// (n + k) 2^-104 of the same absolute sums and the check can resolve
+// tolerances far below double precision.  A wrong entry c_ij moves w_i by
+// |c_ij - c*_ij| (|x_j| = 1), so an error larger than the tolerance in any row
+// is caught with probability >= 1/2 per vector.
 //
 // x_j = +1 or -1 from bit 0 of SplitMix64(seed, j) (Steele, Lea, Flood 2014).
 // All reductions run in a fixed order, so the verdict is reproducible.
@@ -26,6 +29,29 @@ __device__ __forceinline__ double sign_of(uint64_t seed, int64_t j) {
     return (splitmix64(seed, (uint64_t)j) & 1ull) ? -1.0 : 1.0;
 }
 
+// ---- double-double: value hi + lo with |lo| <= ulp(hi) / 2
+struct dd {
+    double hi, lo;
+};
+__device__ __forceinline__ dd two_sum(double a, double b) {
+    const double s = a + b, bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {  // |a| >= |b|
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+// acc += a * b
+__device__ __forceinline__ void dd_fma(dd &acc, double a, double b) {
+    const double p = a * b, pe = fma(a, b, -p);
+    const dd s = two_sum(acc.hi, p);
+    acc = fast_two_sum(s.hi, s.lo + (acc.lo + pe));
+}
+__device__ __forceinline__ void dd_add(dd &acc, dd x) {
+    const dd s = two_sum(acc.hi, x.hi);
+    acc = fast_two_sum(s.hi, s.lo + (acc.lo + x.lo));
+}
+
 template <bool SINGLE>
 __device__ __forceinline__ double2 load_c(const void *p, int64_t idx) {
     if constexpr (SINGLE) {
@@ -36,21 +62,32 @@ __device__ __forceinline__ double2 load_c(const void *p, int64_t idx) {
     }
 }
 
-// Vector source: either the sign vector (vec == nullptr) or a complex vector
-// with its absolute companion.
+// Vector source: the sign vector (v == nullptr) or a double-double complex
+// vector (v: high parts, vlo: low parts) with its absolute companion va.
 struct VecIn {
-    const double2 *v;   // nullptr: x_j = sign_of(seed, j), |x_j| = 1
+    const double2 *v, *vlo;
     const double *va;
     uint64_t seed;
 };
 
-__device__ __forceinline__ void vec_at(const VecIn &x, int64_t j, double2 &v, double &va) {
+// acc += m * x_j (complex), abs += |m| |x_j|
+__device__ __forceinline__ void accum(const VecIn &x, int64_t j, double2 m, dd &re, dd &im,
+                                      double &ab) {
     if (x.v) {
-        v = x.v[j];
-        va = x.va[j];
+        const double2 h = x.v[j], l = x.vlo[j];
+        dd_fma(re, m.x, h.x);
+        dd_fma(re, -m.y, h.y);
+        dd_fma(im, m.x, h.y);
+        dd_fma(im, m.y, h.x);
+        // low parts: contributions 2^-53 below the high ones, plain double is enough
+        re.lo = fma(m.x, l.x, fma(-m.y, l.y, re.lo));
+        im.lo = fma(m.x, l.y, fma(m.y, l.x, im.lo));
+        ab = fma(hypot(m.x, m.y), x.va[j], ab);
     } else {
-        v = make_double2(sign_of(x.seed, j), 0.0);
-        va = 1.0;
+        const double s = sign_of(x.seed, j);
+        dd_fma(re, m.x, s);
+        dd_fma(im, m.y, s);
+        ab += hypot(m.x, m.y);
     }
 }
 
@@ -58,94 +95,107 @@ constexpr int kChunk = 1024;  // columns per partial sum (N case)
 
 // y = op(M) x for M stored column-major (rows x cols, ld) with op = N:
 // y_r = sum_c M[r + c ld] x_c.  Thread per row, block column chunks write
-// partials[chunk][r] (value and absolute sum), reduced in order afterwards.
+// partials[chunk][r], reduced in order afterwards.
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void gemv_n_partial(const void *M, int64_t rows, int64_t cols,
-                                                      int64_t ld, VecIn x, double2 *part,
-                                                      double *part_abs) {
+                                                      int64_t ld, VecIn x, double2 *part_hi,
+                                                      double2 *part_lo, double *part_abs) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
     const int64_t c0 = (int64_t)blockIdx.y * kChunk, c1 = min(cols, c0 + kChunk);
-    double sr = 0.0, si = 0.0, sa = 0.0;
-    for (int64_t c = c0; c < c1; ++c) {
-        const double2 m = load_c<SINGLE>(M, r + c * ld);
-        double2 v;
-        double va;
-        vec_at(x, c, v, va);
-        sr = fma(m.x, v.x, fma(-m.y, v.y, sr));
-        si = fma(m.x, v.y, fma(m.y, v.x, si));
-        sa = fma(hypot(m.x, m.y), va, sa);
-    }
-    part[blockIdx.y * rows + r] = make_double2(sr, si);
-    part_abs[blockIdx.y * rows + r] = sa;
+    dd re{0.0, 0.0}, im{0.0, 0.0};
+    double ab = 0.0;
+    for (int64_t c = c0; c < c1; ++c) accum(x, c, load_c<SINGLE>(M, r + c * ld), re, im, ab);
+    const int64_t o = blockIdx.y * rows + r;
+    part_hi[o] = make_double2(re.hi, im.hi);
+    part_lo[o] = make_double2(re.lo, im.lo);
+    part_abs[o] = ab;
 }
 
-__global__ void reduce_partials(const double2 *part, const double *part_abs, int64_t rows,
-                                int nchunk, double2 *y, double *ya) {
+__global__ void reduce_partials(const double2 *part_hi, const double2 *part_lo,
+                                const double *part_abs, int64_t rows, int nchunk, double2 *y,
+                                double2 *ylo, double *ya) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
-    double sr = 0.0, si = 0.0, sa = 0.0;
+    dd re{0.0, 0.0}, im{0.0, 0.0};
+    double ab = 0.0;
     for (int c = 0; c < nchunk; ++c) {
-        sr += part[c * rows + r].x;
-        si += part[c * rows + r].y;
-        sa += part_abs[c * rows + r];
+        const double2 h = part_hi[c * rows + r], l = part_lo[c * rows + r];
+        dd_add(re, {h.x, l.x});
+        dd_add(im, {h.y, l.y});
+        ab += part_abs[c * rows + r];
     }
-    y[r] = make_double2(sr, si);
-    ya[r] = sa;
+    y[r] = make_double2(re.hi, im.hi);
+    ylo[r] = make_double2(re.lo, im.lo);
+    ya[r] = ab;
 }
 
-// y = op(M) x for op = T or C: y_c = sum_r op(M)[c][r] x_r = sum_r M[r + c ld]^(*) x_r.
-// One wave per output entry c, lanes over r, fixed-order butterfly reduction.
+// y = op(M) x for op = T or C: y_c = sum_r M[r + c ld]^(*) x_r.  One wave per
+// output entry, lanes over r, fixed-order butterfly reduction in double-double.
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void gemv_t(const void *M, int64_t rows, int64_t cols, int64_t ld,
-                                              int conj, VecIn x, double2 *y, double *ya) {
+                                              int conj, VecIn x, double2 *y, double2 *ylo,
+                                              double *ya) {
     const int lane = threadIdx.x & 63;
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= cols) return;
-    double sr = 0.0, si = 0.0, sa = 0.0;
+    dd re{0.0, 0.0}, im{0.0, 0.0};
+    double ab = 0.0;
     for (int64_t r = lane; r < rows; r += 64) {
         double2 m = load_c<SINGLE>(M, r + c * ld);
         if (conj) m.y = -m.y;
-        double2 v;
-        double va;
-        vec_at(x, r, v, va);
-        sr = fma(m.x, v.x, fma(-m.y, v.y, sr));
-        si = fma(m.x, v.y, fma(m.y, v.x, si));
-        sa = fma(hypot(m.x, m.y), va, sa);
+        accum(x, r, m, re, im, ab);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-        sr += __shfl_xor(sr, off, 64);
-        si += __shfl_xor(si, off, 64);
-        sa += __shfl_xor(sa, off, 64);
+        dd_add(re, {__shfl_xor(re.hi, off, 64), __shfl_xor(re.lo, off, 64)});
+        dd_add(im, {__shfl_xor(im.hi, off, 64), __shfl_xor(im.lo, off, 64)});
+        ab += __shfl_xor(ab, off, 64);
     }
     if (lane == 0) {
-        y[c] = make_double2(sr, si);
-        ya[c] = sa;
+        y[c] = make_double2(re.hi, im.hi);
+        ylo[c] = make_double2(re.lo, im.lo);
+        ya[c] = ab;
     }
+}
+
+// (a_r + i a_i) * (z_hi + z_lo) for a double complex a and a double-double complex z
+__device__ __forceinline__ void cmul_dd(double ar, double ai, double2 zh, double2 zl, dd &re, dd &im) {
+    re = {0.0, 0.0};
+    im = {0.0, 0.0};
+    dd_fma(re, ar, zh.x);
+    dd_fma(re, -ai, zh.y);
+    dd_fma(im, ar, zh.y);
+    dd_fma(im, ai, zh.x);
+    re.lo = fma(ar, zl.x, fma(-ai, zl.y, re.lo));
+    im.lo = fma(ar, zl.y, fma(ai, zl.x, im.lo));
 }
 
 // Per-row residual test.  worst[0] receives max_i |res_i| / tol_i as the bit
 // pattern of a non-negative double (order-preserving), worst[1] the number of
 // failing rows.
-__global__ void freivalds_rows(const double2 *w, const double *wa, const double2 *z,
-                               const double *za, const double2 *v, const double *va, int64_t m,
-                               double ar, double ai, double br, double bi, double rel,
-                               double gam, unsigned long long *worst) {
+__global__ void freivalds_rows(const double2 *w, const double2 *wl, const double *wa,
+                               const double2 *z, const double2 *zl, const double *za,
+                               const double2 *v, const double2 *vl, const double *va, int64_t m,
+                               double ar, double ai, double br, double bi, double rel, double gam,
+                               unsigned long long *worst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    double er = w[i].x - (ar * z[i].x - ai * z[i].y);
-    double ei = w[i].y - (ar * z[i].y + ai * z[i].x);
+    dd er{w[i].x, wl[i].x}, ei{w[i].y, wl[i].y}, tr, ti;
+    cmul_dd(-ar, -ai, z[i], zl[i], tr, ti);
+    dd_add(er, tr);
+    dd_add(ei, ti);
     double bound = rel * hypot(ar, ai) * za[i];
     double evals = wa[i] + hypot(ar, ai) * za[i];
     if (v) {
-        er -= br * v[i].x - bi * v[i].y;
-        ei -= br * v[i].y + bi * v[i].x;
+        cmul_dd(-br, -bi, v[i], vl[i], tr, ti);
+        dd_add(er, tr);
+        dd_add(ei, ti);
         bound += rel * hypot(br, bi) * va[i];
         evals += hypot(br, bi) * va[i];
     }
     const double tol = bound + gam * evals;
-    const double res = hypot(er, ei);
+    const double res = hypot(er.hi + er.lo, ei.hi + ei.lo);
     double ratio = tol > 0.0 ? res / tol : (res > 0.0 ? INFINITY : 0.0);
     if (!(ratio == ratio) || !(res == res) || !(tol == tol)) ratio = INFINITY;  // NaN fails
     atomicMax(&worst[0], (unsigned long long)__double_as_longlong(ratio));
@@ -174,46 +224,48 @@ hipError_t launch_debug_add_exp(int16_t *mu, int delta, hipStream_t s) {
     return hipGetLastError();
 }
 
-// y = op(M) x, ya = |op(M)| |x|.  M column-major rows x cols (ld); op: 0 N, 1 T, 2 C.
-// scratch: (ceil(cols / 1024)) * rows * 24 bytes for op = N.
+// y = op(M) x (double-double: y, ylo), ya = |op(M)| |x|.  M column-major rows x
+// cols (ld); op: 0 N, 1 T, 2 C.  scratch: gemv_scratch_bytes(rows, cols) for op = N.
 hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t cols, int64_t ld,
-                       const double2 *xv, const double *xa, uint64_t seed, double2 *y, double *ya,
-                       void *scratch, hipStream_t s) {
-    VecIn x{xv, xa, seed};
+                       const double2 *xv, const double2 *xlo, const double *xa, uint64_t seed,
+                       double2 *y, double2 *ylo, double *ya, void *scratch, hipStream_t s) {
+    VecIn x{xv, xlo, xa, seed};
     if (op == 0) {
         if (rows <= 0) return hipSuccess;
         const int nchunk = (int)((cols + kChunk - 1) / kChunk);
-        double2 *part = (double2 *)scratch;
-        double *part_abs = (double *)(part + (size_t)nchunk * rows);
+        double2 *ph = (double2 *)scratch;
+        double2 *pl = ph + (size_t)nchunk * rows;
+        double *pa = (double *)(pl + (size_t)nchunk * rows);
         if (nchunk > 0) {
             dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nchunk);
-            if (single) hipLaunchKernelGGL(gemv_n_partial<true>, grid, dim3(256), 0, s, M, rows, cols, ld, x, part, part_abs);
-            else hipLaunchKernelGGL(gemv_n_partial<false>, grid, dim3(256), 0, s, M, rows, cols, ld, x, part, part_abs);
+            if (single) hipLaunchKernelGGL(gemv_n_partial<true>, grid, dim3(256), 0, s, M, rows, cols, ld, x, ph, pl, pa);
+            else hipLaunchKernelGGL(gemv_n_partial<false>, grid, dim3(256), 0, s, M, rows, cols, ld, x, ph, pl, pa);
         }
-        hipLaunchKernelGGL(reduce_partials, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, part,
-                           part_abs, rows, nchunk, y, ya);
+        hipLaunchKernelGGL(reduce_partials, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, ph, pl,
+                           pa, rows, nchunk, y, ylo, ya);
     } else {
         if (cols <= 0) return hipSuccess;
         dim3 grid((unsigned)((cols + 3) / 4));
-        if (single) hipLaunchKernelGGL(gemv_t<true>, grid, dim3(256), 0, s, M, rows, cols, ld, op == 2 ? 1 : 0, x, y, ya);
-        else hipLaunchKernelGGL(gemv_t<false>, grid, dim3(256), 0, s, M, rows, cols, ld, op == 2 ? 1 : 0, x, y, ya);
+        if (single) hipLaunchKernelGGL(gemv_t<true>, grid, dim3(256), 0, s, M, rows, cols, ld, op == 2 ? 1 : 0, x, y, ylo, ya);
+        else hipLaunchKernelGGL(gemv_t<false>, grid, dim3(256), 0, s, M, rows, cols, ld, op == 2 ? 1 : 0, x, y, ylo, ya);
     }
     return hipGetLastError();
 }
 
 size_t gemv_scratch_bytes(int64_t rows, int64_t cols) {
     const int64_t nchunk = (cols + kChunk - 1) / kChunk;
-    return (size_t)(nchunk > 0 ? nchunk : 1) * (size_t)(rows > 0 ? rows : 1) * 24;
+    return (size_t)(nchunk > 0 ? nchunk : 1) * (size_t)(rows > 0 ? rows : 1) * 40;
 }
 
-hipError_t launch_freivalds_rows(const double2 *w, const double *wa, const double2 *z,
-                                 const double *za, const double2 *v, const double *va, int64_t m,
+hipError_t launch_freivalds_rows(const double2 *w, const double2 *wl, const double *wa,
+                                 const double2 *z, const double2 *zl, const double *za,
+                                 const double2 *v, const double2 *vl, const double *va, int64_t m,
                                  const double alpha[2], const double beta[2], double rel,
                                  double gam, unsigned long long *worst, hipStream_t s) {
     hipLaunchKernelGGL(fill_words, dim3(1), dim3(64), 0, s, worst, 2);
     if (m <= 0) return hipGetLastError();
-    hipLaunchKernelGGL(freivalds_rows, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w, wa, z,
-                       za, v, va, m, alpha[0], alpha[1], beta[0], beta[1], rel, gam, worst);
+    hipLaunchKernelGGL(freivalds_rows, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w, wl, wa, z,
+                       zl, za, v, vl, va, m, alpha[0], alpha[1], beta[0], beta[1], rel, gam, worst);
     return hipGetLastError();
 }
 

@@ -1,0 +1,200 @@
+"""Moduli-count predictor on the GPU (through the C-ABI) against the CPU FP64 reference.
+
+Bar (FP32 kernels against FP64 references): statistics to 1e-5 relative;
+logits, gradients and one Adam step to 1e-4 relative to the largest entry.
+The learned choice runs the emulation with the predicted N, bit-exact with
+the oracle at that N; a small end-to-end run shows the trained network using
+fewer moduli than the fixed rule at the same verified accuracy.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import from_device, stored, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import torch
+
+    import paper_2512_08321_amd as ozc
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    h = ozc.Handle(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+def _rand_params(seed):
+    from oracle import mlp
+
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.3, mlp.n_params()).astype(np.float32)
+    n = mlp.n_params()
+    p[n - 2 * mlp.F:n - mlp.F] = rng.normal(0, 1, mlp.F)
+    p[n - mlp.F:] = rng.uniform(0.5, 2.0, mlp.F)
+    return p
+
+
+@pytest.mark.parametrize("case", ["NN", "TC", "zeros", "single", "skewed"])
+def test_features_match_oracle(handle, case):
+    import torch
+
+    from oracle import features as ft
+
+    print(f"features {case}", flush=True)
+    single = case == "single"
+    dt = np.complex64 if single else np.complex128
+    A = workloads.complex_matrix(70, 3000, 2.0, 101, dtype=dt)
+    B = workloads.complex_matrix(3000, 45, 2.0, 102, dtype=dt)
+    ta, tb = ("T", "C") if case == "TC" else ("N", "N")
+    if case == "zeros":
+        A[3] = 0
+        A[:, 5] = 0
+        B[:, 7] = 0
+    if case == "skewed":
+        rng = np.random.default_rng(103)
+        A = workloads.skewed(A, col_exp=rng.integers(-40, 1, 3000))
+    As, Bs = stored(A, ta), stored(B, tb)
+    dA, lda = to_device(As)
+    dB, ldb = to_device(Bs)
+    out = torch.empty(20, dtype=torch.float32, device="cuda")
+    handle.features(ta, tb, 70, 45, 3000, dA, lda, dB, ldb, out, single=single)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = ft.features(A, B)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-5), np.c_[got, ref]
+
+
+def test_forward_and_gradient_match_oracle(handle):
+    import torch
+
+    from oracle import mlp
+
+    p = _rand_params(7)
+    handle.mlp_set_params(p)
+    assert np.array_equal(handle.mlp_get_params(), p)
+    rng = np.random.default_rng(8)
+    X = rng.normal(0, 2, (37, mlp.F)).astype(np.float32)
+    y = rng.integers(0, mlp.C, 37).astype(np.int32)
+    dX, dy = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    z = torch.empty((37, mlp.C), dtype=torch.float32, device="cuda")
+    handle.mlp_forward(dX, 37, z)
+    zr, _ = mlp.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(z.cpu().numpy(), zr, rtol=1e-4, atol=1e-4 * np.abs(zr).max())
+    g = torch.empty(mlp.n_params(), dtype=torch.float32, device="cuda")
+    loss = handle.mlp_grad(dX, dy, 37, g)
+    gr = mlp.grad(p.astype(np.float64), X.astype(np.float64), y)
+    assert loss == pytest.approx(mlp.loss(p.astype(np.float64), X.astype(np.float64), y), rel=1e-4)
+    assert np.allclose(g.cpu().numpy(), gr, rtol=0, atol=1e-4 * np.abs(gr).max())
+
+
+def test_one_adam_step_matches_oracle(handle):
+    import torch
+
+    from oracle import mlp
+
+    p = _rand_params(9)
+    handle.mlp_set_params(p)
+    rng = np.random.default_rng(10)
+    X = rng.normal(0, 1, (50, mlp.F)).astype(np.float32)
+    y = rng.integers(0, mlp.C, 50).astype(np.int32)
+    handle.mlp_train(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), 50, epochs=1,
+                     batch=64, lr=1e-3, init=False)
+    got = handle.mlp_get_params()
+    pd = p.astype(np.float64)
+    g = mlp.grad(pd, X.astype(np.float64), y)
+    n_train = mlp.n_params() - 2 * mlp.F
+    want, _, _ = mlp.adam(pd, g, np.zeros_like(pd), np.zeros_like(pd), 1, lr=1e-3, n_train=n_train)
+    # the first step moves every trainable entry by about lr sign(g): compare the moves
+    assert np.allclose(got - p, want - pd, rtol=0, atol=2e-5)
+
+
+def test_training_learns_a_separable_rule(handle):
+    import torch
+
+    from oracle import mlp
+
+    rng = np.random.default_rng(11)
+    X = rng.normal(0, 1, (4000, mlp.F)).astype(np.float32)
+    W = rng.normal(0, 1, (mlp.C, mlp.F))
+    y = np.argmax(X @ W.T, axis=1).astype(np.int32)
+    dX, dy = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    losses = handle.mlp_train(dX, dy, 4000, epochs=30, batch=128, lr=3e-3, seed=5)
+    assert losses[-1] < 0.5 * losses[0]
+    z = torch.empty((4000, mlp.C), dtype=torch.float32, device="cuda")
+    handle.mlp_forward(dX, 4000, z)
+    acc = float((z.argmax(dim=1).cpu().numpy() == y).mean())
+    ref_pred = mlp.predict(handle.mlp_get_params().astype(np.float64), X.astype(np.float64))
+    assert acc > 0.8
+    assert float((ref_pred == z.argmax(dim=1).cpu().numpy()).mean()) > 0.99
+
+
+def test_auto_moduli_runs_the_predicted_count(handle):
+    """N = 0: the call runs with the predicted N (bit-exact with the oracle at that N);
+    without parameters it uses the fallback."""
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    from oracle import core
+
+    A = workloads.complex_matrix(96, 200, 1.0, 121)
+    B = workloads.complex_matrix(200, 64, 1.0, 122)
+    dA, lda = to_device(A)
+    dB, ldb = to_device(B)
+    dC, ldc = to_device(np.zeros((96, 64), complex))
+    h2 = ozc.Handle(0)
+    try:
+        h2.set_auto_moduli(fallback=15, margin=0)
+        h2.set_config(0, "fast", "karatsuba")
+        h2.zgemm("N", "N", 96, 64, 200, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc)
+        torch.cuda.synchronize()
+        assert h2.last_info()["num_moduli"] == 15
+        p = _rand_params(12)
+        h2.mlp_set_params(p)
+        N = h2.predict_moduli("N", "N", 96, 64, 200, dA, lda, dB, ldb)
+        assert 6 <= N <= 24
+        h2.zgemm("N", "N", 96, 64, 200, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc)
+        torch.cuda.synchronize()
+        assert h2.last_info()["num_moduli"] == N
+        got = from_device(dC, 96, 64, ldc)
+        assert np.array_equal(got, core.emulate(A, B, N)["out"])
+    finally:
+        h2.close()
+
+
+def test_trained_predictor_beats_fixed_rule(handle):
+    """Small end-to-end run: label instances by the emulation itself, train, and run
+    held-out instances with the learned N (plus a margin of 1) and the Freivalds check
+    at the target (escalation by 2 on failure).  Every call ends accepted by the
+    check, the per-entry target holds on most instances, and the mean N stays below
+    the fixed rule's."""
+    import paper_2512_08321_amd as ozc
+    from paper_2512_08321_amd import autoN
+
+    h2 = ozc.Handle(0)
+    try:
+        target = 1e-15
+        kw = dict(lo=48, hi=192, klo=64, khi=2048, phi_max=8.0, skew_max=40)
+        print("labelling training instances", flush=True)
+        X, y, meta = autoN.generate(h2, 360, seed=2024, target=target, **kw)
+        N_train = [r[-1] for r in meta]
+        n_fix = autoN.fixed_rule(N_train)
+        h2.mlp_train(X, y, len(meta), epochs=150, batch=64, lr=3e-3, seed=7)
+        rng = np.random.default_rng(99)
+        insts = [autoN.draw_instance(rng, **kw) for _ in range(40)]
+        print("evaluating held-out instances", flush=True)
+        res = autoN.evaluate(h2, insts, target, margin=1)
+        used = np.array([r["N_used"] for r in res])
+        ok = [r for r in res if r["status"] == 0]
+        print(f"fixed rule N={n_fix}; learned mean N={used.mean():.2f}; "
+              f"escalated {sum(r['esc'] > 0 for r in res)}/{len(res)}", flush=True)
+        met = np.mean([r["err"] <= target for r in res])
+        print(f"per-entry target met on {met:.2%} of the held-out instances", flush=True)
+        assert len(ok) == len(res)
+        assert met >= 0.9
+        assert used.mean() < n_fix
+    finally:
+        h2.close()
