@@ -73,8 +73,11 @@ def main():
     ap.add_argument("--sample-rows", type=int, default=512)
     ap.add_argument("--sample-cols", type=int, default=1536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="zgemm", choices=["zgemm", "batch"],
-                    help="zgemm: one large product (default); batch: 512 uneven products")
+    ap.add_argument("--workload", default="zgemm", choices=["zgemm", "batch", "batch-auto"],
+                    help="zgemm: one large product (default); batch: 512 uneven products; "
+                         "batch-auto: the same with the learned moduli count")
+    ap.add_argument("--train-count", type=int, default=400, help="batch-auto: training instances")
+    ap.add_argument("--target", type=float, default=1e-15, help="batch-auto: accuracy target")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--tune", action="store_true", help="batch: run the schedule autotuner first")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -89,6 +92,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "batch-auto":
+        return bench_batch_auto(args)
 
     import numpy as np
     import torch
@@ -308,6 +313,137 @@ def bench_batch(args):
         "speedup_vs_loop": round(loop_ms / batch_ms, 3),
         "bit_identical_to_single_calls": bool(same),
         "int8_mfma_util_end_to_end": round(ops / (batch_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+def uneven_batch(count, seed_base):
+    """The 512-problem workload: m, n, k log-uniform in [64, 2048], phi uniform in [0, 4]."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads
+
+    rng = np.random.default_rng(seed_base)
+    probs, flops = [], 0.0
+    for p in range(count):
+        m, n, k = (int(round(math.exp(rng.uniform(math.log(64), math.log(2048))))) for _ in range(3))
+        phi = float(rng.uniform(0.0, 4.0))
+        A = workloads.complex_matrix_torch(m, k, phi, seed_base * 1000 + 2 * p)
+        B = workloads.complex_matrix_torch(k, n, phi, seed_base * 1000 + 2 * p + 1)
+        C = torch.zeros((n, m), dtype=torch.complex128, device="cuda")
+        probs.append(dict(transa="N", transb="N", m=m, n=n, k=k, alpha=1.0, beta=0.0, A=A, lda=m,
+                          B=B, ldb=k, C=C, ldc=m))
+        flops += 8.0 * m * n * k
+    torch.cuda.synchronize()
+    return probs, flops
+
+
+def bench_batch_auto(args):
+    """Learned moduli count plus batching against the plain fixed-count path on the
+    512-problem uneven batch: training instances from the same distribution are
+    labelled by the emulation itself (smallest N meeting the target), the fixed
+    count is the 99.9% quantile of those labels, and every output's error against
+    the 24-moduli result is measured."""
+    import numpy as np
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    import workloads
+    from paper_2512_08321_amd import autoN
+
+    torch.cuda.set_device(0)
+    h = ozc.Handle(0)
+    target = args.target
+    kw = dict(lo=64, hi=2048, klo=64, khi=2048, phi_max=4.0, skew_max=0, square=False)
+    log(f"[bench] labelling {args.train_count} training instances (target {target:g})")
+    t0 = time.perf_counter()
+    X, y, meta = autoN.generate(h, args.train_count, seed=workloads.seed_for(4, 0, "A"),
+                                target=target, log=log, **kw)
+    labels = [r[-1] for r in meta]
+    n_fix = autoN.fixed_rule(labels)
+    losses = h.mlp_train(X, y, len(meta), epochs=200, batch=64, lr=3e-3, seed=7)
+    log(f"[bench] labels N: mean {np.mean(labels):.2f}, fixed rule N={n_fix}; training loss "
+        f"{losses[0]:.3f} -> {losses[-1]:.3f} ({time.perf_counter() - t0:.1f} s)")
+    probs, flops = uneven_batch(args.batch_count, workloads.seed_for(3, 0, "A"))
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3 / steps
+
+    def loop():
+        for q in probs:
+            h.zgemm("N", "N", q["m"], q["n"], q["k"], 1.0, q["A"], q["lda"], q["B"], q["ldb"], 0.0,
+                    q["C"], q["ldc"])
+
+    h.set_config(n_fix, "fast", "karatsuba")
+    loop_ms = timed(loop, max(1, args.steps // 2), 1)
+    fixed_batch_ms = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
+    out_fixed = [q["C"].clone() for q in probs]
+    h.set_auto_moduli(fallback=n_fix, margin=1)
+    h.set_config(0, "fast", "karatsuba")
+    auto_ms = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
+    out_auto = [q["C"].clone() for q in probs]
+    Ns = []
+    for q in probs:
+        Ns.append(h.predict_moduli("N", "N", q["m"], q["n"], q["k"], q["A"], q["lda"], q["B"],
+                                   q["ldb"]))
+    log("[bench] measuring errors against the 24-moduli results")
+    met_fixed = met_auto = 0
+    worst_auto = 0.0
+    for q, cf, ca in zip(probs, out_fixed, out_auto):
+        inst = dict(m=q["m"], n=q["n"], k=q["k"], A=q["A"], B=q["B"])
+        ref = torch.empty_like(cf)
+        autoN._emulate(h, inst, autoN.MAX_N, ref)
+        absA = torch.complex(q["A"].abs(), torch.zeros_like(q["A"].real))
+        absB = torch.complex(q["B"].abs(), torch.zeros_like(q["B"].real))
+        den = torch.empty_like(cf)
+        h.set_config(16, "fast", "karatsuba")
+        h.zgemm("N", "N", q["m"], q["n"], q["k"], 1.0, absA, q["m"], absB, q["k"], 0.0, den, q["m"])
+        d = den.real.clamp_min(torch.finfo(torch.float64).tiny)
+        ef = float(((cf - ref).abs() / d).max())
+        ea = float(((ca - ref).abs() / d).max())
+        met_fixed += ef <= target
+        met_auto += ea <= target
+        worst_auto = max(worst_auto, ea)
+    P = len(probs)
+    value = flops / (auto_ms * 1e-3) / 1e12
+    log(f"[bench] loop N={n_fix}: {loop_ms:.2f} ms; batched N={n_fix}: {fixed_batch_ms:.2f} ms; "
+        f"batched learned N (mean {np.mean(Ns):.2f}): {auto_ms:.2f} ms; target met "
+        f"{met_fixed}/{P} fixed, {met_auto}/{P} learned")
+    out = {
+        "metric": "emulated batched ZGEMM eff. TFLOPS (sum 8mnk / t), learned moduli count",
+        "value": round(value, 3),
+        "unit": "TFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(auto_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"{P} uneven ZGEMMs, m, n, k log-uniform in [64, 2048], phi uniform "
+                               f"in [0, 4]; predictor trained on {args.train_count} instances of the "
+                               f"same distribution labelled at max err/(|A||B|) <= {target:g}"},
+        "fixed_rule_N": n_fix,
+        "learned_mean_N": round(float(np.mean(Ns)), 3),
+        "loop_fixed_ms": round(loop_ms, 4),
+        "batched_fixed_ms": round(fixed_batch_ms, 4),
+        "speedup_vs_loop_fixed": round(loop_ms / auto_ms, 3),
+        "speedup_vs_batched_fixed": round(fixed_batch_ms / auto_ms, 3),
+        "target_met": {"fixed": met_fixed, "learned": met_auto, "of": P},
+        "worst_err_learned": worst_auto,
     }
     print(json.dumps(out), flush=True)
     h.close()

@@ -96,8 +96,9 @@ ozc_status_t ozc_set_stream(ozc_handle_t handle, void *stream);
  * greedy descending pairwise-coprime integers <= 256), scaling mode and
  * product algorithm for the following calls.  Default: N = 14, fast,
  * Karatsuba.  num_moduli == 0 selects the learned choice (see "moduli-count
- * predictor" below) for ozc_zgemm; ozc_cgemm then uses N = 9.  Batched calls
- * and ozc_inspect keep the last fixed N.  Errors: INVALID_VALUE. */
+ * predictor" below) for ozc_zgemm and ozc_zgemm_vbatched; complex64 calls then
+ * use N = 9.  ozc_inspect and ozc_workspace_size keep the last fixed N.
+ * Errors: INVALID_VALUE. */
 ozc_status_t ozc_set_config(ozc_handle_t handle, int num_moduli, ozc_mode_t mode,
                             ozc_algo_t algo);
 
@@ -231,8 +232,11 @@ ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
  * into a HIP graph per distinct argument list (pointers included) and
  * replayed when the same list comes again.  The batch owns a workspace of its
  * own (kept until the handle is destroyed or a larger batch needs more).
- * Fast mode only: NOT_SUPPORTED in accurate mode.  Problems must not overlap
- * in C.  Asynchronous on the handle's stream; non-finite inputs are
+ * With the learned moduli count configured (N = 0), one statistics pass over
+ * all problems and one forward pass of the predictor choose N per problem (one
+ * synchronisation), and the batch runs as one launch sequence per distinct N
+ * (up to 8 recorded sequences are kept).  Fast mode only: NOT_SUPPORTED in
+ * accurate mode.  Problems must not overlap in C.  Asynchronous on the handle's stream; non-finite inputs are
  * reported by ozc_last_info as for a single call. */
 ozc_status_t ozc_zgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,
                                 const ozc_op_t *transb, const int64_t *m, const int64_t *n,

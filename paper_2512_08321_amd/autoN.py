@@ -22,11 +22,13 @@ from . import Handle, MLP_CLASSES, MLP_FEATURES, MLP_MIN_N
 MAX_N = 24
 
 
-def draw_instance(rng, lo=64, hi=512, klo=64, khi=4096, phi_max=8.0, skew_max=40, device="cuda"):
+def draw_instance(rng, lo=64, hi=512, klo=64, khi=4096, phi_max=8.0, skew_max=40, square=True,
+                  device="cuda"):
     """One instance (A, B) as column-major device tensors (op = N) plus its parameters."""
     import torch
 
-    m = n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    m = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    n = m if square else int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
     k = int(round(math.exp(rng.uniform(math.log(klo), math.log(khi)))))
     phi = float(rng.uniform(0.0, phi_max))
     sigma = int(rng.integers(0, skew_max + 1))

@@ -32,10 +32,13 @@ struct MlpState {
     float *feat = nullptr;  // 1 x F
     int n_fix = 18;         // fallback moduli count
     int margin = 0;         // added to the predicted count
+    char *many = nullptr;   // scratch of the many-product prediction
+    size_t many_bytes = 0;
 
     void release() {
         for (void *p : {(void *)params, (void *)m, (void *)v, (void *)grad, (void *)loss_acc,
-                        (void *)pred, (void *)acts, (void *)idx, (void *)stat, (void *)feat})
+                        (void *)pred, (void *)acts, (void *)idx, (void *)stat, (void *)feat,
+                        (void *)many})
             if (p) (void)hipFree(p);
     }
 };
@@ -174,6 +177,103 @@ ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t t
     OZC_TRY(hipMemcpyAsync(&cls, st->pred, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     OZC_TRY(hipStreamSynchronize(h->stream));
     *N = std::min(OZC_MAX_MODULI, std::max(OZC_MIN_MODULI, OZC_MLP_MIN_N + cls + st->margin));
+    return OZC_STATUS_SUCCESS;
+}
+
+// Predicted N for many products at once: one statistics pass over all
+// operands (batched launches), one forward pass, one synchronisation.
+ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<OperandView> &va,
+                                 const std::vector<OperandView> &vb, std::vector<int> &N) {
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    const size_t P = va.size();
+    N.assign(P, st->n_fix);
+    if (!st->have_params || P == 0) return OZC_STATUS_SUCCESS;
+    hipStream_t s = h->stream;
+    int64_t rows = 0;
+    for (size_t p = 0; p < P; ++p) rows += va[p].rows + vb[p].rows;
+    // device scratch: maxbits, s1, s2 per row; zero counters; features; descriptors
+    std::vector<BatchOperand> scan(2 * P);
+    std::vector<FeatOperand> fops(2 * P);
+    std::vector<FeatProblem> fprob(P);
+    const size_t b_rows = align_up(24 * (size_t)rows), b_zero = align_up(8 * P),
+                 b_feat = align_up(4 * P * kDims.F), b_scan = align_up(sizeof(BatchOperand) * 2 * P),
+                 b_fops = align_up(sizeof(FeatOperand) * 2 * P),
+                 b_fprob = align_up(sizeof(FeatProblem) * P), b_pred = align_up(4 * P);
+    const size_t total = b_rows + b_zero + b_feat + b_scan + b_fops + b_fprob + b_pred;
+    if (total > st->many_bytes) {
+        OZC_TRY(hipStreamSynchronize(s));
+        if (st->many) (void)hipFree(st->many);
+        st->many = nullptr;
+        st->many_bytes = 0;
+        if (hipMalloc(&st->many, total) != hipSuccess) {
+            st->many = nullptr;
+            (void)hipGetLastError();
+            return OZC_STATUS_ALLOC_FAILED;
+        }
+        st->many_bytes = total;
+    }
+    char *buf = st->many;
+    uint64_t *mb = (uint64_t *)buf;
+    double *s1 = (double *)(buf + 8 * (size_t)rows), *s2 = (double *)(buf + 16 * (size_t)rows);
+    unsigned long long *zeros = (unsigned long long *)(buf + b_rows);
+    float *feat = (float *)(buf + b_rows + b_zero);
+    char *d = buf + b_rows + b_zero + b_feat;
+    BatchOperand *scan_dev = (BatchOperand *)d;
+    FeatOperand *fops_dev = (FeatOperand *)(d + b_scan);
+    FeatProblem *fprob_dev = (FeatProblem *)(d + b_scan + b_fops);
+    int *pred = (int *)(d + b_scan + b_fops + b_fprob);
+    int64_t r0 = 0, blk_scan = 0, blk_feat = 0;
+    for (size_t p = 0; p < P; ++p) {
+        const OperandView *v2[2] = {&va[p], &vb[p]};
+        const int64_t rbase[2] = {r0, r0 + va[p].rows};
+        for (int q = 0; q < 2; ++q) {
+            BatchOperand &b = scan[2 * p + q];
+            b = BatchOperand{};
+            b.v = *v2[q];
+            b.maxbits = mb + rbase[q];
+            b.blk_scan = blk_scan;
+            blk_scan += batch_scan_blocks(b.v);
+            FeatOperand &f = fops[2 * p + q];
+            f.v = *v2[q];
+            f.maxbits = mb + rbase[q];
+            f.s1 = s1 + rbase[q];
+            f.s2 = s2 + rbase[q];
+            f.zeros = zeros + p;
+            f.blk = blk_feat;
+            blk_feat += batch_feat_blocks(f.v);
+        }
+        FeatProblem &fp = fprob[p];
+        fp.s1a = s1 + rbase[0];
+        fp.s2a = s2 + rbase[0];
+        fp.ra = va[p].rows;
+        fp.s1b = s1 + rbase[1];
+        fp.s2b = s2 + rbase[1];
+        fp.rb = vb[p].rows;
+        fp.zeros = zeros + p;
+        fp.m = (double)va[p].rows;
+        fp.n = (double)vb[p].rows;
+        fp.k = (double)va[p].k;
+        fp.out = feat + p * kDims.F;
+        r0 += va[p].rows + vb[p].rows;
+    }
+    OZC_TRY(hipMemcpyAsync(scan_dev, scan.data(), sizeof(BatchOperand) * 2 * P, hipMemcpyHostToDevice, s));
+    OZC_TRY(hipMemcpyAsync(fops_dev, fops.data(), sizeof(FeatOperand) * 2 * P, hipMemcpyHostToDevice, s));
+    OZC_TRY(hipMemcpyAsync(fprob_dev, fprob.data(), sizeof(FeatProblem) * P, hipMemcpyHostToDevice, s));
+    OZC_TRY(launch_fill_u64(mb, 3 * rows, 0, s));
+    OZC_TRY(launch_fill_u64((uint64_t *)zeros, (int64_t)P, 0, s));
+    OZC_TRY(launch_batch_scan(scan_dev, (int)(2 * P), blk_scan, single, false, s));
+    OZC_TRY(launch_batch_feat_sums(fops_dev, (int)(2 * P), blk_feat, single, s));
+    OZC_TRY(launch_batch_feat_reduce(fprob_dev, (int)P, s));
+    ozc_status_t r = ensure_acts(st, (int)P);
+    if (r != OZC_STATUS_SUCCESS) return r;
+    OZC_TRY(launch_mlp_forward(kDims, st->params, feat, nullptr, (int)P, st->a, s));
+    OZC_TRY(launch_argmax(st->a.z, (int)P, kDims.C, pred, s));
+    std::vector<int> cls(P);
+    OZC_TRY(hipMemcpyAsync(cls.data(), pred, sizeof(int) * P, hipMemcpyDeviceToHost, s));
+    OZC_TRY(hipStreamSynchronize(s));
+    for (size_t p = 0; p < P; ++p)
+        N[p] = std::min(OZC_MAX_MODULI, std::max(OZC_MIN_MODULI, OZC_MLP_MIN_N + cls[p] + st->margin));
     return OZC_STATUS_SUCCESS;
 }
 

@@ -55,9 +55,9 @@ struct BatchPlan {
 };
 
 struct BatchState {
+    static constexpr size_t kMaxPlans = 8;
     ozc_batch_policy_t policy{1024, 1, 1};
-    BatchPlan plan;
-    bool have_plan = false;
+    std::vector<BatchPlan *> plans;  // most recently used last
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
@@ -67,7 +67,11 @@ struct BatchState {
 void batch_release(ozc_context *h) {
     if (!h->batch) return;
     BatchState *bs = h->batch;
-    bs->plan.release();
+    for (BatchPlan *p : bs->plans) {
+        p->release();
+        delete p;
+    }
+    bs->plans.clear();
     if (bs->ws) (void)hipFree(bs->ws);
     if (bs->cap) (void)hipStreamDestroy(bs->cap);
     delete bs;
@@ -349,10 +353,11 @@ ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
 ozc_status_t ensure_batch_ws(ozc_context *h, BatchState *bs, size_t bytes) {
     if (bytes <= bs->ws_bytes) return OZC_STATUS_SUCCESS;
     OZC_TRY(hipStreamSynchronize(h->stream));
-    if (bs->have_plan) {  // its graph points into the old workspace
-        bs->plan.release();
-        bs->have_plan = false;
+    for (BatchPlan *p : bs->plans) {  // their graphs point into the old workspace
+        p->release();
+        delete p;
     }
+    bs->plans.clear();
     if (bs->ws) (void)hipFree(bs->ws);
     bs->ws = nullptr;
     bs->ws_bytes = 0;
@@ -425,6 +430,54 @@ ozc_status_t record_graph(ozc_context *h, BatchState *bs, BatchPlan &P) {
     return st;
 }
 
+// One batch with the handle's current N: plan lookup (or build and record), launch.
+ozc_status_t run_group(ozc_context *h, BatchState *bs, bool single,
+                       const std::vector<Problem> &probs) {
+    const ozc_batch_policy_t pol = bs->policy;
+    std::vector<uint64_t> key = make_key(h, single, pol, probs);
+    BatchPlan *P = nullptr;
+    for (size_t i = 0; i < bs->plans.size(); ++i)
+        if (bs->plans[i]->key == key) {
+            P = bs->plans[i];
+            bs->plans.erase(bs->plans.begin() + (long)i);
+            bs->plans.push_back(P);
+            break;
+        }
+    if (!P) {
+        BatchPlan *Q = new (std::nothrow) BatchPlan();
+        if (!Q) return OZC_STATUS_ALLOC_FAILED;
+        ozc_status_t st = plan_batch(h, single, pol, probs, *Q);
+        if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, Q->ws_bytes);
+        if (st == OZC_STATUS_SUCCESS) st = bind(h, *Q, bs->ws);
+        if (st == OZC_STATUS_SUCCESS && pol.use_graph) st = record_graph(h, bs, *Q);
+        if (st != OZC_STATUS_SUCCESS) {
+            Q->release();
+            delete Q;
+            return st;
+        }
+        Q->key = std::move(key);
+        if (bs->plans.size() >= BatchState::kMaxPlans) {  // evict the least recently used
+            OZC_TRY(hipStreamSynchronize(h->stream));
+            bs->plans.front()->release();
+            delete bs->plans.front();
+            bs->plans.erase(bs->plans.begin());
+        }
+        bs->plans.push_back(Q);
+        P = Q;
+    }
+    if (P->exec) OZC_TRY(hipGraphLaunch(P->exec, h->stream));
+    else {
+        ozc_status_t st = launch_batch(h, bs, *P, bs->ws, h->stream, PH_ALL, P->group);
+        if (st != OZC_STATUS_SUCCESS) return st;
+    }
+    h->last.m += P->sum_m;
+    h->last.n += P->sum_n;
+    h->last.k += P->sum_k;
+    h->last.workspace = std::max(h->last.workspace, P->ws_bytes);
+    h->last.int8_ops += P->int8_ops;
+    return OZC_STATUS_SUCCESS;
+}
+
 ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t *ta,
                           const ozc_op_t *tb, const int64_t *m, const int64_t *n,
                           const int64_t *k, const double *alpha, const void *const *A,
@@ -446,39 +499,42 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
     if (probs.empty()) return OZC_STATUS_SUCCESS;
     st = grid_sizes(h, bs);
     if (st != OZC_STATUS_SUCCESS) return st;
+    if (!h->auto_n) return run_group(h, bs, single, probs);
 
-    const ozc_batch_policy_t pol = bs->policy;
-    std::vector<uint64_t> key = make_key(h, single, pol, probs);
-    if (!(bs->have_plan && bs->plan.key == key)) {
-        if (bs->have_plan) {
-            OZC_TRY(hipStreamSynchronize(h->stream));  // the old graph may still run
-            bs->plan.release();
-            bs->have_plan = false;
+    // Learned N per problem (complex64: the fixed count), then one batch per N.
+    std::vector<int> Ns(probs.size(), 9);
+    if (!single) {
+        std::vector<OperandView> va, vb;
+        std::vector<size_t> which;
+        for (size_t p = 0; p < probs.size(); ++p) {
+            const Problem &q = probs[p];
+            if (q.m == 0 || q.n == 0 || is_degenerate(q)) continue;
+            va.push_back(view_A(q.A, q.ta, q.m, q.k, q.lda));
+            vb.push_back(view_B(q.B, q.tb, q.n, q.k, q.ldb));
+            which.push_back(p);
         }
-        bs->plan = BatchPlan{};
-        BatchPlan &P = bs->plan;
-        st = plan_batch(h, single, pol, probs, P);
-        if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, P.ws_bytes);
-        if (st == OZC_STATUS_SUCCESS) st = bind(h, P, bs->ws);
-        if (st == OZC_STATUS_SUCCESS && pol.use_graph) st = record_graph(h, bs, P);
-        if (st != OZC_STATUS_SUCCESS) {
-            P.release();
-            return st;
-        }
-        P.key = std::move(key);
-        bs->have_plan = true;
+        std::vector<int> pred;
+        st = predict_moduli_many(h, single, va, vb, pred);
+        if (st != OZC_STATUS_SUCCESS) return st;
+        for (size_t i = 0; i < which.size(); ++i) Ns[which[i]] = pred[i];
     }
-    BatchPlan &P = bs->plan;
-    if (P.exec) OZC_TRY(hipGraphLaunch(P.exec, h->stream));
-    else {
-        st = launch_batch(h, bs, P, bs->ws, h->stream, PH_ALL, P.group);
+    struct RestoreN {
+        ozc_context *h;
+        int n0;
+        ~RestoreN() { h->nmod = n0; }
+    } restore{h, h->nmod};
+    int nmax = 0;
+    for (int N = OZC_MIN_MODULI; N <= OZC_MAX_MODULI; ++N) {
+        std::vector<Problem> group;
+        for (size_t p = 0; p < probs.size(); ++p)
+            if (Ns[p] == N) group.push_back(probs[p]);
+        if (group.empty()) continue;
+        h->nmod = N;
+        nmax = N;
+        st = run_group(h, bs, single, group);
         if (st != OZC_STATUS_SUCCESS) return st;
     }
-    h->last.m = P.sum_m;
-    h->last.n = P.sum_n;
-    h->last.k = P.sum_k;
-    h->last.workspace = P.ws_bytes;
-    h->last.int8_ops = P.int8_ops;
+    h->last.num_moduli = nmax;  // the largest count used
     return OZC_STATUS_SUCCESS;
 }
 

@@ -64,4 +64,6 @@ void mlp_release(ozc_context *h);
 ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                             int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
                             int64_t ldb, int *N);
+ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<OperandView> &va,
+                                 const std::vector<OperandView> &vb, std::vector<int> &N);
 }  // namespace ozc

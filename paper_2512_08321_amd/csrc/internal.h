@@ -190,6 +190,24 @@ inline MlpOffsets mlp_offsets(const MlpDims &d) {
 struct MlpActs {  // device buffers for `rows` rows
     float *a1, *h1, *a2, *h2, *z, *dz, *loss_r, *d2, *d1, *xs;
 };
+struct FeatOperand {  // one operand of a batched statistics pass
+    OperandView v;
+    const uint64_t *maxbits;
+    double *s1, *s2;
+    unsigned long long *zeros;  // the problem's zero counter
+    int64_t blk;                // first block of this operand
+};
+struct FeatProblem {
+    const double *s1a, *s2a, *s1b, *s2b;
+    int64_t ra, rb;
+    const unsigned long long *zeros;
+    double m, n, k;
+    float *out;  // OZC_MLP_FEATURES floats
+};
+int64_t batch_feat_blocks(const OperandView &v);
+hipError_t launch_batch_feat_sums(const FeatOperand *ops, int nops, int64_t blocks, bool single,
+                                  hipStream_t s);
+hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStream_t s);
 hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits, double *s1,
                             double *s2, unsigned long long *zeros, hipStream_t s);
 hipError_t launch_feat_reduce(const double *s1a, const double *s2a, int64_t ra, const double *s1b,

@@ -45,23 +45,30 @@ constexpr int kFeatChunk = 2048;
 
 // Sums s1 = sum |x| 2^-e, s2 = sum (|x| 2^-e)^2 and the zero count of one row,
 // one block per (row group, k chunk); rows with k contiguous take a wave per row.
+__host__ __device__ __forceinline__ int64_t feat_grid_x(const OperandView &v) {
+    return v.contig_h ? (v.rows + 3) / 4 : (v.rows + 255) / 256;
+}
+__host__ __device__ __forceinline__ int64_t feat_grid_y(const OperandView &v) {
+    const int64_t c = v.contig_h ? kFeatChunk : kFeatChunk / 8;
+    return (v.k + c - 1) / c;
+}
+
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uint64_t *maxbits,
-                                                        double *s1, double *s2,
-                                                        unsigned long long *zeros) {
+__device__ __forceinline__ void feat_sums_body(const OperandView &v, const uint64_t *maxbits,
+                                               double *s1, double *s2, unsigned long long *zeros,
+                                               int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t r, h0, h1, step;
     if (v.contig_h) {
-        r = (int64_t)blockIdx.x * 4 + wave;
-        h0 = (int64_t)blockIdx.y * kFeatChunk + lane;
+        r = bx * 4 + wave;
+        h0 = by * kFeatChunk + lane;
         step = 64;
     } else {
-        r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-        h0 = (int64_t)blockIdx.y * (kFeatChunk / 8);
+        r = bx * 256 + threadIdx.x;
+        h0 = by * (kFeatChunk / 8);
         step = 1;
     }
-    h1 = min(v.k, (int64_t)(v.contig_h ? (int64_t)blockIdx.y * kFeatChunk + kFeatChunk
-                                       : (int64_t)blockIdx.y * (kFeatChunk / 8) + kFeatChunk / 8));
+    h1 = min(v.k, v.contig_h ? by * kFeatChunk + kFeatChunk : by * (kFeatChunk / 8) + kFeatChunk / 8);
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
     const double sc = (mb != 0 && mb < 0x7ff0000000000000ull) ? inv_pow2_of(mb) : 0.0;
@@ -89,13 +96,32 @@ __global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uin
     if (z) atomicAdd(&zeros[0], z);
 }
 
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uint64_t *maxbits,
+                                                        double *s1, double *s2,
+                                                        unsigned long long *zeros) {
+    feat_sums_body<SINGLE>(v, maxbits, s1, s2, zeros, blockIdx.x, blockIdx.y);
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void batch_feat_sums_kernel(const FeatOperand *ops, int nops) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nops - 1;  // last operand whose first block is <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ops[mid].blk <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const FeatOperand &o = ops[lo];
+    const int64_t lb = b - o.blk, gx = feat_grid_x(o.v);
+    feat_sums_body<SINGLE>(o.v, o.maxbits, o.s1, o.s2, o.zeros, lb % gx, lb / gx);
+}
+
 // One block: statistics of l2 and l1 over the nonzero rows of both operands.
-__global__ __launch_bounds__(256) void feat_reduce_kernel(const double *s1a, const double *s2a,
-                                                          int64_t ra, const double *s1b,
-                                                          const double *s2b, int64_t rb,
-                                                          const unsigned long long *zeros,
-                                                          double m, double n, double k,
-                                                          float *out) {
+__device__ __forceinline__ void feat_reduce_body(const double *s1a, const double *s2a, int64_t ra,
+                                                 const double *s1b, const double *s2b, int64_t rb,
+                                                 const unsigned long long *zeros, double m,
+                                                 double n, double k, float *out) {
     __shared__ double red[256][5];
     const int t = threadIdx.x;
     float res[16];
@@ -147,6 +173,20 @@ __global__ __launch_bounds__(256) void feat_reduce_kernel(const double *s1a, con
         for (int i = 0; i < 16; ++i) out[3 + i] = res[i];
         out[19] = (float)((double)zeros[0] / (2.0 * (m + n) * k));
     }
+}
+
+__global__ __launch_bounds__(256) void feat_reduce_kernel(const double *s1a, const double *s2a,
+                                                          int64_t ra, const double *s1b,
+                                                          const double *s2b, int64_t rb,
+                                                          const unsigned long long *zeros,
+                                                          double m, double n, double k,
+                                                          float *out) {
+    feat_reduce_body(s1a, s2a, ra, s1b, s2b, rb, zeros, m, n, k, out);
+}
+
+__global__ __launch_bounds__(256) void batch_feat_reduce_kernel(const FeatProblem *probs) {
+    const FeatProblem &p = probs[blockIdx.x];
+    feat_reduce_body(p.s1a, p.s2a, p.ra, p.s1b, p.s2b, p.rb, p.zeros, p.m, p.n, p.k, p.out);
 }
 
 // ---------------------------------------------------------------- network
@@ -272,6 +312,25 @@ hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *m
     else grid = dim3((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + kFeatChunk / 8 - 1) / (kFeatChunk / 8)));
     if (single) hipLaunchKernelGGL(feat_sums_kernel<true>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
     else hipLaunchKernelGGL(feat_sums_kernel<false>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
+    return hipGetLastError();
+}
+
+int64_t batch_feat_blocks(const OperandView &v) {
+    if (v.rows <= 0 || v.k <= 0) return 0;
+    return feat_grid_x(v) * feat_grid_y(v);
+}
+
+hipError_t launch_batch_feat_sums(const FeatOperand *ops, int nops, int64_t blocks, bool single,
+                                  hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    if (single) hipLaunchKernelGGL(batch_feat_sums_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
+    else hipLaunchKernelGGL(batch_feat_sums_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_feat_reduce_kernel, dim3((unsigned)nprob), dim3(256), 0, s, probs);
     return hipGetLastError();
 }
 

@@ -269,3 +269,41 @@ def test_uneven_batch_full_sizes_against_single_calls(handle):
     torch.cuda.synchronize()
     for p, d in enumerate(dev):
         assert torch.equal(torch.view_as_real(got[p]), torch.view_as_real(d["C"])), p
+
+
+def test_learned_moduli_batch_matches_single_calls(handle):
+    """N = 0 in a batch: each problem runs with its own predicted N, bit-identical to a
+    single call at that N."""
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    from oracle import mlp
+
+    h2 = ozc.Handle(0)
+    try:
+        rng = np.random.default_rng(13)
+        p = rng.normal(0, 0.5, mlp.n_params()).astype(np.float32)
+        n = mlp.n_params()
+        p[n - 2 * mlp.F:n - mlp.F] = rng.normal(0, 3, mlp.F)
+        p[n - mlp.F:] = rng.uniform(0.5, 2.0, mlp.F)
+        h2.mlp_set_params(p)
+        h2.set_batch_policy(1024, 1, True)
+        probs = _make_batch(81, 12, 16, 300, phi_max=6.0)
+        dev = _upload(probs)
+        Ns = [h2.predict_moduli(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["A"],
+                                d["lda"], d["B"], d["ldb"]) for d in dev]
+        print(f"predicted N {Ns}", flush=True)
+        h2.set_config(0, "fast", "karatsuba")
+        h2.gemm_vbatched(dev)
+        got = _download(dev)
+        ref_dev = _upload(probs)
+        for d, N in zip(ref_dev, Ns):
+            h2.set_config(N, "fast", "karatsuba")
+            h2.zgemm(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["alpha"], d["A"], d["lda"],
+                     d["B"], d["ldb"], d["beta"], d["C"], d["ldc"])
+        ref = _download(ref_dev)
+        assert all(_same(a, b) for a, b in zip(got, ref))
+        assert h2.last_info()["num_moduli"] == Ns[-1]
+        torch.cuda.synchronize()
+    finally:
+        h2.close()
