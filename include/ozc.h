@@ -51,7 +51,7 @@ typedef struct ozc_context *ozc_handle_t;
 typedef enum {
     OZC_STATUS_SUCCESS = 0,
     OZC_STATUS_INVALID_VALUE = 1,   /* an argument is out of range (BLAS-style checks)   */
-    OZC_STATUS_NOT_SUPPORTED = 2,   /* e.g. k above OZC_MAX_K                              */
+    OZC_STATUS_NOT_SUPPORTED = 2,   /* e.g. k above OZC_MAX_K in ozc_inspect or a batch    */
     OZC_STATUS_ALLOC_FAILED = 3,    /* device allocation of the workspace failed          */
     OZC_STATUS_HIP_ERROR = 4,       /* a HIP runtime call or kernel launch failed          */
     OZC_STATUS_NONFINITE = 5,       /* reported by ozc_last_info: an input was inf or NaN  */
@@ -115,8 +115,11 @@ ozc_status_t ozc_set_workspace(ozc_handle_t handle, void *ptr, size_t bytes);
 
 /* C := alpha op(A) op(B) + beta C, complex128 (double2) elements.
  * A: lda >= max(1, m) if transa == N, else >= max(1, k); B: ldb >= max(1, k)
- * if transb == N, else >= max(1, n); ldc >= max(1, m).  m, n, k >= 0,
- * k <= OZC_MAX_K (else NOT_SUPPORTED).  m == 0 or n == 0: no work.
+ * if transb == N, else >= max(1, n); ldc >= max(1, m).  m, n, k >= 0.
+ * The INT32 accumulation of the products is exact for k <= OZC_MAX_K; a
+ * larger k is split into ceil(k / OZC_MAX_K) near-equal chunks, each
+ * emulated with its own scaling exponents and accumulated into C (beta = 1
+ * after the first chunk).  m == 0 or n == 0: no work.
  * alpha == 0 or k == 0: C := beta C without reading A or B.  beta == 0: C
  * is not read.  Rows of op(A) / columns of op(B) holding inf or NaN give NaN
  * output entries and set the status that ozc_last_info reports.

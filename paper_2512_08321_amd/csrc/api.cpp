@@ -135,7 +135,6 @@ ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t 
     if (ldc < (m > 1 ? m : 1)) return OZC_STATUS_INVALID_VALUE;
     if (m > 0 && n > 0 && C == nullptr && !c_optional) return OZC_STATUS_INVALID_VALUE;
     if (m > 0 && n > 0 && k > 0 && (A == nullptr || B == nullptr)) return OZC_STATUS_INVALID_VALUE;
-    if (k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
     if (m > ((int64_t)1 << 31) || n > ((int64_t)1 << 31)) return OZC_STATUS_NOT_SUPPORTED;
     return OZC_STATUS_SUCCESS;
 }
@@ -185,6 +184,29 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     if (!h) return OZC_STATUS_INVALID_HANDLE;
     ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, ins != nullptr);
     if (st != OZC_STATUS_SUCCESS) return st;
+    if (k > OZC_MAX_K) {
+        // INT32 accumulation is exact only up to OZC_MAX_K terms (127^2 per term):
+        // split k into near-equal chunks, each an emulated product of its own
+        // (own exponents), accumulated in C with beta = 1 after the first.
+        if (ins) return OZC_STATUS_NOT_SUPPORTED;
+        if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
+        const int64_t nc = (k + OZC_MAX_K - 1) / OZC_MAX_K;
+        const size_t es = single ? 8 : 16;
+        const double one[2] = {1.0, 0.0};
+        double ops = 0.0;
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t h0 = k * c / nc, h1 = k * (c + 1) / nc;
+            const char *Ac = (const char *)A + es * (size_t)(ta == OZC_OP_N ? h0 * lda : h0);
+            const char *Bc = (const char *)B + es * (size_t)(tb == OZC_OP_N ? h0 : h0 * ldb);
+            st = run(h, single, ta, tb, m, n, h1 - h0, alpha, Ac, lda, Bc, ldb, c == 0 ? beta : one,
+                     C, ldc, nullptr);
+            if (st != OZC_STATUS_SUCCESS) return st;
+            ops += h->last.int8_ops;
+        }
+        h->last.k = k;
+        h->last.int8_ops = ops;
+        return OZC_STATUS_SUCCESS;
+    }
     hipStream_t s = h->stream;
     OZC_TRY(hipSetDevice(h->device));
     h->last = ozc_info_t{};
@@ -561,8 +583,10 @@ ozc_status_t ozc_workspace_size(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_
     if (!h) return OZC_STATUS_INVALID_HANDLE;
     if (!bytes || !valid_op(ta) || !valid_op(tb) || m < 0 || n < 0 || k < 0)
         return OZC_STATUS_INVALID_VALUE;
-    if (k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
-    *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(h, m, n, k, false).total;
+    const int64_t kc = k > OZC_MAX_K ? (k + (k + OZC_MAX_K - 1) / OZC_MAX_K - 1) /
+                                           ((k + OZC_MAX_K - 1) / OZC_MAX_K)
+                                     : k;  // largest k chunk
+    *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(h, m, n, kc, false).total;
     return OZC_STATUS_SUCCESS;
 }
 

@@ -115,6 +115,7 @@ ozc_status_t gather(int count, const ozc_op_t *ta, const ozc_op_t *tb, const int
         ozc_status_t st = check_args(q.ta, q.tb, q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C,
                                      q.ldc, !need_c);
         if (st != OZC_STATUS_SUCCESS) return st;
+        if (q.k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
     }
     return OZC_STATUS_SUCCESS;
 }

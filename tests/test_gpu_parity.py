@@ -205,12 +205,36 @@ def test_argument_errors(handle):
     with pytest.raises(ozc.OzcError) as e:
         handle.zgemm("N", "N", 4, 4, 4, 1.0, 1, 3, 1, 4, 0.0, 1, 4)  # lda < m
     assert e.value.status == 1
+    with pytest.raises(ozc.OzcError) as e:  # checked before any work: no memory is touched
+        handle.inspect(False, "N", "N", 4, 4, ozc.MAX_K + 1, 1, 4, 1, ozc.MAX_K + 1, ldc=4)
+    assert e.value.status == 2
     with pytest.raises(ozc.OzcError) as e:
-        handle.zgemm("N", "N", 4, 4, ozc.MAX_K + 1, 1.0, 1, 4, 1, ozc.MAX_K + 1, 0.0, 1, 4)
+        handle.gemm_vbatched([dict(transa="N", transb="N", m=4, n=4, k=ozc.MAX_K + 1, alpha=1.0,
+                                   beta=0.0, A=1, lda=4, B=1, ldb=ozc.MAX_K + 1, C=1, ldc=4)])
     assert e.value.status == 2
     with pytest.raises(ozc.OzcError):
         handle.set_config(25)
     handle.set_config(14)
+
+
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "T")])
+def test_k_above_int32_limit_is_chunked(handle, orc, ta, tb):
+    """k > 2^17: near-equal k chunks, each emulated on its own, accumulated with beta = 1;
+    bit-exact with the oracle doing the same chunking."""
+    import paper_2512_08321_amd as ozc
+
+    k = ozc.MAX_K + 1000
+    m, n = 6, 5
+    print(f"k-chunk {ta}{tb} k={k}", flush=True)
+    A = workloads.complex_matrix(m, k, 0.5, 141)
+    B = workloads.complex_matrix(k, n, 0.5, 142)
+    C = workloads.complex_matrix(m, n, 1.0, 143)
+    alpha, beta = 0.75 - 0.5j, 0.5 + 1j
+    got = _gemm_call(handle, A, B, C, alpha, beta, 14, ta=ta, tb=tb)
+    half = k // 2
+    ref = orc.emulate(A[:, :half], B[:half], 14, alpha=alpha, beta=beta, C=C)["out"]
+    ref = orc.emulate(A[:, half:], B[half:], 14, alpha=alpha, beta=1.0, C=ref)["out"]
+    assert _same(got, ref)
 
 
 def test_config0_workload_bit_exact(handle, orc):
