@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--sample-rows", type=int, default=512)
     ap.add_argument("--sample-cols", type=int, default=1536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verify", action="store_true",
+                    help="enable the Freivalds check on every call (its cost shows in ms/step)")
     ap.add_argument("--workload", default="zgemm", choices=["zgemm", "batch", "batch-auto"],
                     help="zgemm: one large product (default); batch: 512 uneven products; "
                          "batch-auto: the same with the learned moduli count")
@@ -128,6 +130,8 @@ def main():
 
     h = ozc.Handle(0, num_moduli=N, mode=args.mode, algo=args.algo)
     call = h.cgemm if args.single else h.zgemm
+    if args.verify:
+        h.set_verify(True)
 
     def step():
         call("N", "N", m, n, k, 1.0, A, m, B, k, 0.0, C, m)
@@ -210,7 +214,7 @@ def main():
         "config": {"workload": f"{kind} {m}x{n}x{k} {prec}, {N} moduli, {args.mode} mode, "
                                f"{args.algo} products, phi={args.phi}, alpha=1, beta=0",
                    "m": m, "n": n, "k": k, "moduli": N, "mode": args.mode, "algo": args.algo,
-                   "phi": args.phi, "precision": prec},
+                   "phi": args.phi, "precision": prec, "freivalds_check": bool(args.verify)},
         "int8_mfma_util": {"gemm_kernel": round(achieved / INT8_PEAK_TOPS, 4),
                            "end_to_end": round(util_e2e, 4)},
         "err_nc_sample": err,

@@ -158,6 +158,7 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         for (int q = 0; q < L; ++q) accR[u][q] = accI[u][q] = 0;
 
     const int8_t *E = a.eprime + j * a.m_pad + ib;
+#pragma unroll 4
     for (int l = 0; l < a.nmod; ++l) {
         const uint32_t wr = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l) * planeC);
         const uint32_t wi = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l + 1) * planeC);
