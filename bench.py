@@ -75,9 +75,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", action="store_true",
                     help="enable the Freivalds check on every call (its cost shows in ms/step)")
-    ap.add_argument("--workload", default="zgemm", choices=["zgemm", "batch", "batch-auto"],
+    ap.add_argument("--workload", default="zgemm",
+                    choices=["zgemm", "batch", "batch-auto", "vendor-int8"],
                     help="zgemm: one large product (default); batch: 512 uneven products; "
-                         "batch-auto: the same with the learned moduli count")
+                         "batch-auto: the same with the learned moduli count; vendor-int8: the "
+                         "vendor's INT8 GEMM (torch._int_mm) on size^3 int8 operands, for "
+                         "comparison with one residue product")
     ap.add_argument("--train-count", type=int, default=400, help="batch-auto: training instances")
     ap.add_argument("--target", type=float, default=1e-15, help="batch-auto: accuracy target")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -96,6 +99,8 @@ def main():
         return bench_batch(args)
     if args.workload == "batch-auto":
         return bench_batch_auto(args)
+    if args.workload == "vendor-int8":
+        return bench_vendor_int8(args)
 
     import numpy as np
     import torch
@@ -320,6 +325,35 @@ def bench_batch(args):
     }
     print(json.dumps(out), flush=True)
     h.close()
+
+
+def bench_vendor_int8(args):
+    """The vendor INT8 GEMM (hipBLASLt through torch._int_mm) on one size^3 product, the
+    unit of work of the residue product kernel (which runs 3N such products)."""
+    import torch
+
+    torch.cuda.set_device(0)
+    n = args.size
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    a = torch.randint(-128, 128, (n, n), dtype=torch.int8, device="cuda", generator=gen)
+    b = torch.randint(-128, 128, (n, n), dtype=torch.int8, device="cuda", generator=gen)
+    bt = b.t()
+    for _ in range(args.warmup):
+        torch._int_mm(a, bt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch._int_mm(a, bt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tops = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    log(f"[bench] vendor INT8 GEMM {n}^3: {ms:.3f} ms, {tops:.0f} TOP/s")
+    print(json.dumps({"metric": "vendor INT8 GEMM TOP/s", "value": round(tops, 1), "unit": "TOP/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+                      "config": {"workload": f"int8 GEMM {n}^3 (torch._int_mm)"}}), flush=True)
 
 
 def uneven_batch(count, seed_base):
