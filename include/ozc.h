@@ -331,6 +331,20 @@ ozc_status_t ozc_mlp_train(ozc_handle_t handle, const float *X, const int *y, in
                            int epochs, int batch, float lr, uint64_t seed, int init,
                            float *epoch_loss);
 
+/* Store / restore the predictor's parameters (mu, sd and the weights of the
+ * three layers) in a file at `path` (host string), so that a network trained
+ * once serves later processes.  File layout, little-endian: the 8 bytes
+ * "OZCMLP01"; int32 F, H, C, MIN_N, count (the OZC_MLP_* values and
+ * OZC_MLP_PARAMS); count float32 parameters in the order ozc_mlp_get_params
+ * returns them; the 64-bit FNV-1a hash of those parameter bytes.
+ * save: INVALID_VALUE before parameters exist or when the file cannot be
+ * written (synchronises).  load: INVALID_VALUE when the file cannot be read,
+ * is shorter or longer than that layout, names other dimensions, fails the
+ * hash, or holds an sd entry <= 0; the handle's parameters are replaced only
+ * by a file that passes every check. */
+ozc_status_t ozc_mlp_save(ozc_handle_t handle, const char *path);
+ozc_status_t ozc_mlp_load(ozc_handle_t handle, const char *path);
+
 /* Fallback N (used without parameters; default 18) and a margin added to every
  * prediction (default 0, at most 8). */
 ozc_status_t ozc_set_auto_moduli(ozc_handle_t handle, int fallback, int margin);

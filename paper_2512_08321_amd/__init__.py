@@ -89,6 +89,8 @@ EXPORTS = {
     "ozc_features": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP],
     "ozc_mlp_set_params": [_VP, _VP, _INT],
     "ozc_mlp_get_params": [_VP, _VP, _INT],
+    "ozc_mlp_save": [_VP, ctypes.c_char_p],
+    "ozc_mlp_load": [_VP, ctypes.c_char_p],
     "ozc_mlp_forward": [_VP, _VP, _INT, _VP],
     "ozc_mlp_grad": [_VP, _VP, _VP, _INT, _VP, _VP],
     "ozc_mlp_train": [_VP, _VP, _VP, _INT, _INT, _INT, ctypes.c_float, ctypes.c_uint64, _INT, _VP],
@@ -252,6 +254,12 @@ class Handle:
         p = np.zeros(MLP_PARAMS, np.float32)
         _check(lib().ozc_mlp_get_params(self._h, p.ctypes.data, p.size), "ozc_mlp_get_params")
         return p
+
+    def mlp_save(self, path):
+        _check(lib().ozc_mlp_save(self._h, os.fsencode(path)), "ozc_mlp_save")
+
+    def mlp_load(self, path):
+        _check(lib().ozc_mlp_load(self._h, os.fsencode(path)), "ozc_mlp_load")
 
     def mlp_forward(self, X, rows, logits, stream=None):
         self.set_stream(stream)

@@ -283,8 +283,8 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
 
     // Steps IV, V-i/ii: truncation and residues
     OZC_TRY(pe.mark(1));
-    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, nchunks, resA, L.m_pad, L.k_pad, s));
-    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, nchunks, resB, L.n_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, nchunks, abits, resA, L.m_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, nchunks, abits, resB, L.n_pad, L.k_pad, s));
 
     // Step V-iii/iv: INT8 products and their residues
     OZC_TRY(pe.mark(2));

@@ -2,6 +2,7 @@
 // input statistics, the perceptron's buffers, its training loop, and the
 // per-call prediction used when the handle is configured with N = 0.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -317,6 +318,56 @@ ozc_status_t ozc_mlp_get_params(ozc_handle_t h, float *params, int count) {
     OZC_TRY(hipStreamSynchronize(h->stream));
     OZC_TRY(hipMemcpy(params, st->params, sizeof(float) * count, hipMemcpyDeviceToHost));
     return OZC_STATUS_SUCCESS;
+}
+
+namespace {
+const char kMlpMagic[8] = {'O', 'Z', 'C', 'M', 'L', 'P', '0', '1'};
+
+uint64_t fnv1a64(const void *data, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(data);
+    uint64_t x = 14695981039346656037ull;
+    for (size_t i = 0; i < n; ++i) x = (x ^ b[i]) * 1099511628211ull;
+    return x;
+}
+}  // namespace
+
+ozc_status_t ozc_mlp_save(ozc_handle_t h, const char *path) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!path) return OZC_STATUS_INVALID_VALUE;
+    const int P = mlp_offsets(kDims).total;
+    std::vector<float> p(P);
+    ozc_status_t s = ozc_mlp_get_params(h, p.data(), P);
+    if (s != OZC_STATUS_SUCCESS) return s;
+    const int32_t dims[5] = {kDims.F, kDims.H, kDims.C, OZC_MLP_MIN_N, P};
+    const uint64_t hash = fnv1a64(p.data(), sizeof(float) * P);
+    FILE *f = fopen(path, "wb");
+    if (!f) return OZC_STATUS_INVALID_VALUE;
+    bool ok = fwrite(kMlpMagic, 1, 8, f) == 8 && fwrite(dims, sizeof(int32_t), 5, f) == 5 &&
+              fwrite(p.data(), sizeof(float), P, f) == (size_t)P &&
+              fwrite(&hash, sizeof(hash), 1, f) == 1;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? OZC_STATUS_SUCCESS : OZC_STATUS_INVALID_VALUE;
+}
+
+ozc_status_t ozc_mlp_load(ozc_handle_t h, const char *path) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!path) return OZC_STATUS_INVALID_VALUE;
+    const int P = mlp_offsets(kDims).total;
+    FILE *f = fopen(path, "rb");
+    if (!f) return OZC_STATUS_INVALID_VALUE;
+    char magic[8];
+    int32_t dims[5];
+    std::vector<float> p(P);
+    uint64_t hash = 0;
+    char extra;
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMlpMagic, 8) == 0 &&
+              fread(dims, sizeof(int32_t), 5, f) == 5 && dims[0] == kDims.F &&
+              dims[1] == kDims.H && dims[2] == kDims.C && dims[3] == OZC_MLP_MIN_N &&
+              dims[4] == P && fread(p.data(), sizeof(float), P, f) == (size_t)P &&
+              fread(&hash, sizeof(hash), 1, f) == 1 && fread(&extra, 1, 1, f) == 0;
+    fclose(f);
+    if (!ok || hash != fnv1a64(p.data(), sizeof(float) * P)) return OZC_STATUS_INVALID_VALUE;
+    return ozc_mlp_set_params(h, p.data(), P);  // checks sd > 0 before replacing anything
 }
 
 ozc_status_t ozc_mlp_forward(ozc_handle_t h, const float *X, int rows, float *logits) {

@@ -382,6 +382,138 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
     }
 }
 
+// The same split without LDS staging (residues only).  A block of 256
+// threads covers 32 rows and one 64-wide k-slab; each thread holds 8
+// consecutive k of one row and writes their
+// residues as one 8-byte word per plane and modulus.  Eight consecutive lanes
+// share a row (lane i holds octet i), so each wave writes 8 whole 64-byte rows
+// (512 contiguous bytes) per plane and modulus, and the block writes each
+// plane's 32 x 64-byte block of the slab.  Loads: for rows contiguous with
+// each other a load instruction reads 8 rows at 8 k (128-byte runs); for rows
+// with contiguous k each lane reads its own 128-byte run.
+//
+// Residues in FP32: |a'| is held as NF signed 11-bit chunks c_j (a' =
+// sum_j c_j 2^(11 j)), so x = sum_j c_j w_j with w_j the symmetric residue of
+// 2^(11 j) is an integer with |x| <= 9 * 2047 * 128 < 2^22, exact in FP32.
+// q = rint(x * fl(1/p)) is round(x / p): the computed quotient is within
+// |x / p| 2^-23 (1 + 2^-23) < 1 / (2p) of x / p, and for odd p no x / p lies
+// closer than 1 / (2p) to a half-integer; so s = x - q p (one exact fma) is the
+// symmetric residue.  For p = 256 an exact tie gives s = +128 instead of -128,
+// the same byte.
+constexpr int kDirectRows = 32;
+
+__device__ __forceinline__ uint32_t pack_bytes(int a, int b, int c, int d) {
+    return (uint32_t)(a & 0xff) | ((uint32_t)(b & 0xff) << 8) | ((uint32_t)(c & 0xff) << 16) |
+           ((uint32_t)(d & 0xff) << 24);
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// The 8 residues r[0..7] as one 8-byte store.
+__device__ __forceinline__ void store8(int8_t *p, const int (&r)[8]) {
+    const u32x2 w{pack_bytes(r[0], r[1], r[2], r[3]), pack_bytes(r[4], r[5], r[6], r[7])};
+    *reinterpret_cast<u32x2 *>(p) = w;
+}
+
+// a' = trunc(|x| 2^mu) as NF 11-bit chunks, signed like x, in FP32.
+template <int NF>
+__device__ __forceinline__ void trunc_fchunks(double x, int mu, float (&c)[NF]) {
+    uint64_t M;
+    int E;
+    decompose(x, M, E);
+    const int s = E + mu;
+    uint64_t lo = 0, hi = 0;
+    if (M != 0) {
+        if (s >= 64) {
+            hi = M << (s - 64);
+        } else if (s > 0) {
+            lo = M << s;
+            hi = M >> (64 - s);
+        } else if (s > -64) {
+            lo = M >> (-s);
+        }
+    }
+    constexpr uint64_t mask = (1ull << kFChunkBits) - 1;
+    const bool neg = x < 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const int o = kFChunkBits * j;
+        uint64_t v;
+        if (o + kFChunkBits <= 64) v = lo >> o;
+        else if (o >= 64) v = hi >> (o - 64);
+        else v = (lo >> o) | (hi << (64 - o));
+        const float f = (float)(uint32_t)(v & mask);
+        c[j] = neg ? -f : f;
+    }
+}
+
+__device__ __forceinline__ float smod_f(float x, float p, float ip) {
+    return __builtin_fmaf(-__builtin_rintf(x * ip), p, x);
+}
+
+template <bool SINGLE, bool CONTIG_H, int NPLANES, int NF>
+__global__ __launch_bounds__(256) void split_direct_kernel(OperandView v,
+                                                           const int16_t *__restrict__ mu,
+                                                           const NTable *__restrict__ tab, int nmod,
+                                                           int8_t *__restrict__ dst,
+                                                           int64_t rows_pad, int64_t k_pad) {
+    const int tid = threadIdx.x;
+    const int rl = tid >> 3;
+    const int oc = tid & 7;
+    const int64_t bx = blockIdx.x;
+    const int64_t r = (int64_t)blockIdx.y * kDirectRows + rl;
+    const int64_t h0 = bx * kTileH + 8 * oc;
+    const int64_t plane_pitch = rows_pad * k_pad;
+
+    int ex = kExpZero;
+    if (r < v.rows) ex = mu[r];
+    const bool live = ex != kExpZero && ex != kExpNonfinite;
+    float cR[8][NF], cI[8][NF];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double re = 0.0, im = 0.0;
+        const int64_t h = h0 + j;
+        if (live && h < v.k) {
+            load_elem<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
+            if (v.conj) im = -im;
+        }
+        trunc_fchunks<NF>(re, live ? ex : 0, cR[j]);
+        trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
+    }
+
+    int8_t *out = dst + (bx * rows_pad + r) * kTileH + 8 * oc;
+    for (int l = 0; l < nmod; ++l) {
+        const ModConst &mc = tab->mod[l];
+        const float p = mc.pf, ip = mc.ipf;
+        float w[NF];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) w[c] = mc.wf[c];
+        float fa[8], fb[8];
+        int a[8], b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float xr = cR[j][0] * w[0], xi = cI[j][0] * w[0];
+#pragma unroll
+            for (int c = 1; c < NF; ++c) {
+                xr = __builtin_fmaf(cR[j][c], w[c], xr);
+                xi = __builtin_fmaf(cI[j][c], w[c], xi);
+            }
+            fa[j] = smod_f(xr, p, ip);
+            fb[j] = smod_f(xi, p, ip);
+            a[j] = (int)fa[j];
+            b[j] = (int)fb[j];
+        }
+        int8_t *o = out + (int64_t)l * NPLANES * plane_pitch;
+        store8(o, a);
+        store8(o + plane_pitch, b);
+        if constexpr (NPLANES == 3) {
+            int c[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) c[j] = (int)smod_f(fa[j] + fb[j], p, ip);
+            store8(o + 2 * plane_pitch, c);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- kernels (one problem)
 
 template <bool SINGLE>
@@ -509,6 +641,33 @@ hipError_t batch_split_chunks(const BatchOperand *ops, int nops, int64_t blocks,
     return hipGetLastError();
 }
 
+template <bool SINGLE, bool CONTIG_H, int NPLANES>
+hipError_t split_direct_chunks(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod,
+                               int nf, int8_t *dst, int64_t rows_pad, int64_t k_pad,
+                               hipStream_t s) {
+    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kDirectRows));
+#define OZC_DIRECT_CASE(NF)                                                                  \
+    case NF:                                                                                 \
+        hipLaunchKernelGGL((split_direct_kernel<SINGLE, CONTIG_H, NPLANES, NF>), grid,       \
+                           dim3(256), 0, s, v, mu, tab, nmod, dst, rows_pad, k_pad);         \
+        break;
+    switch (nf) {
+        OZC_DIRECT_CASE(1)
+        OZC_DIRECT_CASE(2)
+        OZC_DIRECT_CASE(3)
+        OZC_DIRECT_CASE(4)
+        OZC_DIRECT_CASE(5)
+        OZC_DIRECT_CASE(6)
+        OZC_DIRECT_CASE(7)
+        OZC_DIRECT_CASE(8)
+        OZC_DIRECT_CASE(9)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef OZC_DIRECT_CASE
+    return hipGetLastError();
+}
+
 template <bool SINGLE, bool CONTIG_H, int NPLANES, bool CEIL7>
 hipError_t split_dispatch_chunks(const OperandView &v, const int16_t *mu, const uint64_t *maxbits,
                                  const NTable *tab, int nmod, int nchunks, int8_t *dst,
@@ -590,10 +749,25 @@ hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int6
     return hipGetLastError();
 }
 
+#define OZC_DIRECT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
 hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
-                        int nmod, int nplanes, int nchunks, int8_t *dst, int64_t rows_pad,
-                        int64_t k_pad, hipStream_t s) {
+                        int nmod, int nplanes, int nchunks, int abits, int8_t *dst,
+                        int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
+    int nf = (abits + kFChunkBits - 1) / kFChunkBits;
+    if (nf < 1) nf = 1;
+    if (rows_pad % kDirectRows == 0 && nf <= kMaxFChunks) {
+        if (single) {
+            if (v.contig_h) return nplanes == 3 ? split_direct_chunks<true, true, 3>(OZC_DIRECT_ARGS)
+                                                : split_direct_chunks<true, true, 2>(OZC_DIRECT_ARGS);
+            return nplanes == 3 ? split_direct_chunks<true, false, 3>(OZC_DIRECT_ARGS)
+                                : split_direct_chunks<true, false, 2>(OZC_DIRECT_ARGS);
+        }
+        if (v.contig_h) return nplanes == 3 ? split_direct_chunks<false, true, 3>(OZC_DIRECT_ARGS)
+                                            : split_direct_chunks<false, true, 2>(OZC_DIRECT_ARGS);
+        return nplanes == 3 ? split_direct_chunks<false, false, 3>(OZC_DIRECT_ARGS)
+                            : split_direct_chunks<false, false, 2>(OZC_DIRECT_ARGS);
+    }
 #define OZC_SPLIT_ARGS v, mu, nullptr, tab, nmod, nchunks, dst, rows_pad, k_pad, s
     if (single) {
         if (v.contig_h) return nplanes == 3 ? split_dispatch_chunks<true, true, 3, false>(OZC_SPLIT_ARGS)
@@ -607,6 +781,7 @@ hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, co
                         : split_dispatch_chunks<false, false, 2, false>(OZC_SPLIT_ARGS);
 #undef OZC_SPLIT_ARGS
 }
+#undef OZC_DIRECT_ARGS
 
 hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits, int8_t *dst,
                         int64_t rows_pad, int64_t k_pad, hipStream_t s) {

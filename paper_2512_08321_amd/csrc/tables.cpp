@@ -166,6 +166,14 @@ void build_tables(NTable *tables) {
                 mc.w[j] = (uint32_t)(pw % p);
                 pw = (pw % p) * ((1ull << kChunkBits) % p);
             }
+            mc.pf = (float)p;
+            mc.ipf = 1.0f / (float)p;  // correctly rounded single division
+            pw = 1;
+            for (int j = 0; j < kMaxFChunks; ++j) {
+                const uint32_t r = (uint32_t)(pw % p);
+                mc.wf[j] = (float)(r >= mc.half ? (int)r - (int)p : (int)r);
+                pw = (pw % p) * ((1ull << kFChunkBits) % p);
+            }
             // Step II: q_l = (P/p_l)^-1 mod p_l, s_l = (P/p_l) q_l
             const Big Ml = P.div(p);
             const uint32_t q = inverse_mod(Ml.mod(p), p);

@@ -198,3 +198,59 @@ def test_trained_predictor_beats_fixed_rule(handle):
         assert used.mean() < n_fix
     finally:
         h2.close()
+
+
+def test_save_and_load_round_trip(handle, tmp_path):
+    """A saved network loads bit-identically into a new handle (same logits); files
+    that are truncated, corrupted, of other dimensions or with trailing bytes are
+    rejected without touching the loaded parameters."""
+    import struct
+
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    from oracle import mlp
+
+    p = _rand_params(13)
+    handle.mlp_set_params(p)
+    path = tmp_path / "mlp.bin"
+    handle.mlp_save(path)
+    raw = path.read_bytes()
+    P = mlp.n_params()
+    assert len(raw) == 8 + 5 * 4 + 4 * P + 8
+    assert raw[:8] == b"OZCMLP01"
+    assert struct.unpack("<5i", raw[8:28]) == (mlp.F, mlp.H, mlp.C, ozc.MLP_MIN_N, P)
+    assert np.array_equal(np.frombuffer(raw[28:28 + 4 * P], "<f4"), p)
+
+    h2 = ozc.Handle(0)
+    try:
+        with pytest.raises(ozc.OzcError):
+            h2.mlp_save(tmp_path / "none.bin")  # no parameters yet
+        h2.mlp_load(path)
+        assert np.array_equal(h2.mlp_get_params(), p)
+        X = torch.from_numpy(np.random.default_rng(14).normal(0, 1, (9, mlp.F)).astype(np.float32)).cuda()
+        z1 = torch.empty((9, mlp.C), dtype=torch.float32, device="cuda")
+        z2 = torch.empty_like(z1)
+        handle.mlp_forward(X, 9, z1)
+        h2.mlp_forward(X, 9, z2)
+        assert torch.equal(z1, z2)
+
+        q = _rand_params(15)
+        h2.mlp_set_params(q)
+        bad = {
+            "truncated": raw[:-9],
+            "trailing": raw + b"\0",
+            "magic": b"X" + raw[1:],
+            "dims": raw[:8] + struct.pack("<i", mlp.F + 1) + raw[12:],
+            "flipped": raw[:100] + bytes([raw[100] ^ 1]) + raw[101:],
+        }
+        for name, data in bad.items():
+            f = tmp_path / f"{name}.bin"
+            f.write_bytes(data)
+            with pytest.raises(ozc.OzcError):
+                h2.mlp_load(f)
+            assert np.array_equal(h2.mlp_get_params(), q), name
+        with pytest.raises(ozc.OzcError):
+            h2.mlp_load(tmp_path / "missing.bin")
+    finally:
+        h2.close()
