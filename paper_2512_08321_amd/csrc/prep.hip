@@ -400,7 +400,8 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
 // closer than 1 / (2p) to a half-integer; so s = x - q p (one exact fma) is the
 // symmetric residue.  For p = 256 an exact tie gives s = +128 instead of -128,
 // the same byte.
-constexpr int kDirectRows = 32;
+constexpr int kEPT = 4;                   // k-consecutive elements per thread
+constexpr int kDirectRows = 4 * kEPT;     // 256 threads, 64 / kEPT threads per row
 
 __device__ __forceinline__ uint32_t pack_bytes(int a, int b, int c, int d) {
     return (uint32_t)(a & 0xff) | ((uint32_t)(b & 0xff) << 8) | ((uint32_t)(c & 0xff) << 16) |
@@ -408,10 +409,18 @@ __device__ __forceinline__ uint32_t pack_bytes(int a, int b, int c, int d) {
 }
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-// The 8 residues r[0..7] as one 8-byte store.
-__device__ __forceinline__ void store8(int8_t *p, const int (&r)[8]) {
-    const u32x2 w{pack_bytes(r[0], r[1], r[2], r[3]), pack_bytes(r[4], r[5], r[6], r[7])};
-    *reinterpret_cast<u32x2 *>(p) = w;
+// The residues r[0..kEPT-1] as one store.
+static_assert(kEPT == 2 || kEPT == 4 || kEPT == 8, "2, 4 or 8 elements per thread");
+template <int E>
+__device__ __forceinline__ void store_res(int8_t *p, const int (&r)[E]) {
+    if constexpr (E == 8) {
+        const u32x2 w{pack_bytes(r[0], r[1], r[2], r[3]), pack_bytes(r[4], r[5], r[6], r[7])};
+        *reinterpret_cast<u32x2 *>(p) = w;
+    } else if constexpr (E == 4) {
+        *reinterpret_cast<uint32_t *>(p) = pack_bytes(r[0], r[1], r[2], r[3]);
+    } else {
+        *reinterpret_cast<uint16_t *>(p) = (uint16_t)((r[0] & 0xff) | ((r[1] & 0xff) << 8));
+    }
 }
 
 // a' = trunc(|x| 2^mu) as NF 11-bit chunks, signed like x, in FP32.
@@ -457,19 +466,20 @@ __global__ __launch_bounds__(256) void split_direct_kernel(OperandView v,
                                                            int8_t *__restrict__ dst,
                                                            int64_t rows_pad, int64_t k_pad) {
     const int tid = threadIdx.x;
-    const int rl = tid >> 3;
-    const int oc = tid & 7;
+    constexpr int TPR = kTileH / kEPT;  // threads per row
+    const int rl = tid / TPR;
+    const int oc = tid % TPR;
     const int64_t bx = blockIdx.x;
     const int64_t r = (int64_t)blockIdx.y * kDirectRows + rl;
-    const int64_t h0 = bx * kTileH + 8 * oc;
+    const int64_t h0 = bx * kTileH + kEPT * oc;
     const int64_t plane_pitch = rows_pad * k_pad;
 
     int ex = kExpZero;
     if (r < v.rows) ex = mu[r];
     const bool live = ex != kExpZero && ex != kExpNonfinite;
-    float cR[8][NF], cI[8][NF];
+    float cR[kEPT][NF], cI[kEPT][NF];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kEPT; ++j) {
         double re = 0.0, im = 0.0;
         const int64_t h = h0 + j;
         if (live && h < v.k) {
@@ -480,17 +490,17 @@ __global__ __launch_bounds__(256) void split_direct_kernel(OperandView v,
         trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
     }
 
-    int8_t *out = dst + (bx * rows_pad + r) * kTileH + 8 * oc;
+    int8_t *out = dst + (bx * rows_pad + r) * kTileH + kEPT * oc;
     for (int l = 0; l < nmod; ++l) {
         const ModConst &mc = tab->mod[l];
         const float p = mc.pf, ip = mc.ipf;
         float w[NF];
 #pragma unroll
         for (int c = 0; c < NF; ++c) w[c] = mc.wf[c];
-        float fa[8], fb[8];
-        int a[8], b[8];
+        float fa[kEPT], fb[kEPT];
+        int a[kEPT], b[kEPT];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kEPT; ++j) {
             float xr = cR[j][0] * w[0], xi = cI[j][0] * w[0];
 #pragma unroll
             for (int c = 1; c < NF; ++c) {
@@ -503,13 +513,13 @@ __global__ __launch_bounds__(256) void split_direct_kernel(OperandView v,
             b[j] = (int)fb[j];
         }
         int8_t *o = out + (int64_t)l * NPLANES * plane_pitch;
-        store8(o, a);
-        store8(o + plane_pitch, b);
+        store_res(o, a);
+        store_res(o + plane_pitch, b);
         if constexpr (NPLANES == 3) {
-            int c[8];
+            int c[kEPT];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) c[j] = (int)smod_f(fa[j] + fb[j], p, ip);
-            store8(o + 2 * plane_pitch, c);
+            for (int j = 0; j < kEPT; ++j) c[j] = (int)smod_f(fa[j] + fb[j], p, ip);
+            store_res(o + 2 * plane_pitch, c);
         }
     }
 }
