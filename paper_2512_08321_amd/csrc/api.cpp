@@ -277,14 +277,12 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         abits = th.max_abits_accu;
     }
     if (fault == 2) OZC_TRY(launch_debug_add_exp(muA, 12, s));
-    int nchunks = (abits + kChunkBits - 1) / kChunkBits;
-    if (nchunks < 1) nchunks = 1;
-    if (nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
+    if (abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
 
     // Steps IV, V-i/ii: truncation and residues
     OZC_TRY(pe.mark(1));
-    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, nchunks, abits, resA, L.m_pad, L.k_pad, s));
-    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, nchunks, abits, resB, L.n_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, abits, resA, L.m_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, abits, resB, L.n_pad, L.k_pad, s));
 
     // Step V-iii/iv: INT8 products and their residues
     OZC_TRY(pe.mark(2));

@@ -30,7 +30,7 @@ struct Problem {
 struct BatchPlan {
     std::vector<uint64_t> key;
     bool single = false;
-    int nmod = 0, algo = 0, planes = 0, nchunks = 1, nlimbs = 1, group = 1;
+    int nmod = 0, algo = 0, planes = 0, abits = 0, nlimbs = 1, group = 1;
     size_t ws_bytes = 0;
     std::vector<BatchOperand> ops;
     std::vector<BatchGemm> gm[2];  // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
@@ -165,8 +165,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     P.group = std::max(1, std::min(pol.moduli_group, h->nmod));
     const NTable &th = h->tab_host[(size_t)h->nmod - 1];
     P.nlimbs = th.nlimbs;
-    P.nchunks = std::max(1, (th.max_abits_fast + kChunkBits - 1) / kChunkBits);
-    if (P.nchunks > kMaxChunks) return OZC_STATUS_NOT_SUPPORTED;
+    P.abits = th.max_abits_fast;
+    if (P.abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
     const int nprod = P.algo == 0 ? 3 : 4;
 
     struct Pad {
@@ -396,7 +396,7 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
         OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, tab,
                                             (uint32_t *)h->status_dev, s));
         OZC_TRY(launch_batch_split(P.ops_dev, nops, P.blk_split, P.single, tab, P.nmod, P.planes,
-                                   P.nchunks, s));
+                                   P.abits, s));
     }
     if (phases & PH_GEMM) {
         OZC_TRY(launch_fill_u32(counters, 2, 0, s));

@@ -9,9 +9,7 @@ namespace ozc {
 constexpr int kMaxModuli = 24;
 constexpr int kLimbBits = 19;       // CRT limbs: N * 128 * (2^19 - 1) < 2^31 for N <= 24
 constexpr int kMaxLimbs = 11;       // ceil((log2 P + 1) / 19) for N <= 24
-constexpr int kChunkBits = 21;      // residue extraction: |a'| split into 21-bit chunks
-constexpr int kMaxChunks = 6;       // |a'| < 2^126
-constexpr int kFChunkBits = 11;     // FP32 residue path: |a'| split into 11-bit chunks
+constexpr int kFChunkBits = 11;     // residue split: |a'| as 11-bit chunks (FP32 arithmetic)
 constexpr int kMaxFChunks = 9;      // |a'| < 2^99 (N <= 24 needs at most 97 bits)
 constexpr int kThr = 64;            // threshold table length for the exponent rules
 constexpr int kSigmaFracBits = 20;  // fast mode: fixed-point fraction bits of sum of squares
@@ -25,7 +23,6 @@ struct ModConst {
     uint32_t half;               // ceil(p / 2): residues >= half map to r - p
     uint32_t barrett;            // floor(2^32 / p)
     uint32_t koff;               // multiple of p >= 2^31 (odd p), 0 for p = 256
-    uint32_t w[kMaxChunks];      // 2^(21 j) mod p
     int32_t slimb[kMaxLimbs];    // 19-bit limbs of s_l = (P / p_l) q_l
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float
@@ -74,10 +71,10 @@ hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbi
 hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int64_t rows,
                                  int64_t rows_pad, const NTable *tab, int16_t *mu,
                                  uint32_t *status, hipStream_t s);
-// abits bounds the bit length of |a'|; nchunks = ceil(abits / kChunkBits).
+// abits bounds the bit length of |a'| (at most 11 * kMaxFChunks).
 hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
-                        int nmod, int nplanes, int nchunks, int abits, int8_t *dst,
-                        int64_t rows_pad, int64_t k_pad, hipStream_t s);
+                        int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
+                        int64_t k_pad, hipStream_t s);
 
 struct GemmArgs {
     const int8_t *A;      // [N][planes][k_pad/64][m_pad][64] (slab-major planes)
@@ -143,7 +140,7 @@ hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, 
 hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
                                        const NTable *tab, uint32_t *status, hipStream_t s);
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                              const NTable *tab, int nmod, int nplanes, int nchunks,
+                              const NTable *tab, int nmod, int nplanes, int abits,
                               hipStream_t s);
 
 struct BatchGemm {          // one problem of a batched product launch

@@ -222,175 +222,70 @@ __global__ void accu_exponents_kernel(const uint64_t *maxbits, const int32_t *X,
     mu[r] = out;
 }
 
-// ---------------------------------------------------------------- residue split
-// Tile of 32 rows x 64 k-elements per block.  Each thread converts 8
-// elements to the integer chunks of |trunc(x 2^mu)| once, then for every
-// modulus computes the symmetric residues (and, for Karatsuba, the reduced
-// sum of the real and imaginary residues), stages them in LDS and writes them
-// zero-padded to rows_pad x k_pad in slab-major order: the 64-wide k-slab kb
-// of a plane is a contiguous rows_pad x 64-byte block (row r at byte 64 r),
-// so that the product kernels stream whole cache lines.
-//
-// CEIL7 (accurate mode): instead of residues, writes the 7-bit magnitudes
-// ceil(|x| 2^(5 - e)) of the real and imaginary parts and their difference.
+// ---------------------------------------------------------------- accurate-mode magnitudes
+// Tile of 32 rows x 64 k-elements per block.  Each thread takes 8 elements
+// and writes the 7-bit magnitudes ceil(|x| 2^(5 - e)) of the real and
+// imaginary parts and their difference (the three INT8 operands of the bound
+// product, Section III-B), staged in LDS and stored zero-padded to
+// rows_pad x k_pad in slab-major order: the 64-wide k-slab kb of a plane is a
+// contiguous rows_pad x 64-byte block (row r at byte 64 r), so that the
+// product kernels stream whole cache lines.
 
 constexpr int kTileR = 32, kTileH = 64, kLdsPitch = 80;
 
-template <int NCHUNK>
-__device__ __forceinline__ void trunc_chunks(double x, int mu, uint32_t (&c)[NCHUNK], bool &neg) {
-    uint64_t M;
-    int E;
-    decompose(x, M, E);
-    neg = x < 0.0;
-    const int s = E + mu;
-    uint64_t lo = 0, hi = 0;
-    if (M != 0) {
-        if (s >= 64) {
-            hi = M << (s - 64);
-        } else if (s > 0) {
-            lo = M << s;
-            hi = M >> (64 - s);
-        } else if (s > -64) {
-            lo = M >> (-s);
-        }
-    }
-    constexpr uint64_t mask = (1ull << kChunkBits) - 1;
-#pragma unroll
-    for (int j = 0; j < NCHUNK; ++j) {
-        const int o = kChunkBits * j;
-        uint64_t v;
-        if (o + kChunkBits <= 64) v = lo >> o;
-        else if (o >= 64) v = hi >> (o - 64);
-        else v = (lo >> o) | (hi << (64 - o));
-        c[j] = (uint32_t)(v & mask);
-    }
-}
-
-template <int NCHUNK>
-__device__ __forceinline__ int residue(const uint32_t (&c)[NCHUNK], bool neg, const ModConst &mc) {
-    uint32_t x = 0;
-#pragma unroll
-    for (int j = 0; j < NCHUNK; ++j) x += __umul24(c[j], mc.w[j]);
-    uint32_t r = x - __umulhi(x, mc.barrett) * mc.p;
-    if (r >= mc.p) r -= mc.p;
-    if (neg && r != 0) r = mc.p - r;
-    int s = (int)r;
-    if (r >= mc.half) s -= (int)mc.p;
-    return s;
-}
-
-__device__ __forceinline__ int sum_residue(int a, int b, const ModConst &mc) {
-    int s = a + b;
-    if (s >= (int)mc.half) s -= (int)mc.p;
-    else if (s < (int)mc.half - (int)mc.p) s += (int)mc.p;
-    return s;
-}
-
-template <bool SINGLE, bool CONTIG_H, int NPLANES, int NCHUNK, bool CEIL7>
-__device__ __forceinline__ void split_body(const OperandView &v, const int16_t *mu,
-                                           const uint64_t *maxbits, const NTable *tab, int nmod,
+template <bool SINGLE, bool CONTIG_H>
+__device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t *maxbits,
                                            int8_t *dst, int64_t rows_pad, int64_t k_pad,
                                            int64_t bx, int64_t by) {
+    constexpr int NPLANES = 3;
     __shared__ __align__(16) int8_t lds[NPLANES][kTileR][kLdsPitch];
     const int tid = threadIdx.x;
     const int64_t h0 = bx * kTileH;
     const int64_t r0 = by * kTileR;
     const int64_t plane_pitch = rows_pad * k_pad;
 
-    // element coordinates of this thread (8 elements)
-    int rl[8], hl[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        if constexpr (CONTIG_H) {
-            hl[e] = tid & 63;
-            rl[e] = (tid >> 6) + 4 * e;
-        } else {
-            rl[e] = tid & 31;
-            hl[e] = (tid >> 5) + 8 * e;
-        }
-    }
-
-    uint32_t cR[8][NCHUNK], cI[8][NCHUNK];
-    bool nR[8], nI[8];
-    int bar[8][3];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int64_t r = r0 + rl[e], h = h0 + hl[e];
-        double re = 0.0, im = 0.0;
-        int ex = kExpZero;
+        // element coordinates: consecutive lanes follow the contiguous direction
+        const int hl = CONTIG_H ? (tid & 63) : (tid >> 5) + 8 * e;
+        const int rl = CONTIG_H ? (tid >> 6) + 4 * e : (tid & 31);
+        const int64_t r = r0 + rl, h = h0 + hl;
+        int a = 0, b = 0;
         if (r < v.rows && h < v.k) {
-            if constexpr (CEIL7) {
-                const uint64_t mb = maxbits[r];
-                if (mb != 0 && mb < kInfBits) ex = ilogb_bits(mb);
-            } else {
-                ex = mu[r];
-            }
-            if (ex != kExpZero && ex != kExpNonfinite) {
+            const uint64_t mb = maxbits[r];
+            if (mb != 0 && mb < kInfBits) {
+                const int ex = ilogb_bits(mb);
+                double re, im;
                 load_elem<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
                 if (v.conj) im = -im;
-            } else {
-                ex = kExpZero;
-            }
-        }
-        if constexpr (CEIL7) {
-            int a = 0, b = 0;
-            if (ex != kExpZero) {
                 a = (int)ceil_scaled(re, (kAccuIntBits - 1) - ex);
                 b = (int)ceil_scaled(im, (kAccuIntBits - 1) - ex);
             }
-            bar[e][0] = a;
-            bar[e][1] = b;
-            bar[e][2] = a - b;
-        } else {
-            if (ex == kExpZero) {
-                re = 0.0;
-                im = 0.0;
-                ex = 0;
-            }
-            trunc_chunks<NCHUNK>(re, ex, cR[e], nR[e]);
-            trunc_chunks<NCHUNK>(im, ex, cI[e], nI[e]);
         }
+        lds[0][rl][hl] = (int8_t)a;
+        lds[1][rl][hl] = (int8_t)b;
+        lds[2][rl][hl] = (int8_t)(a - b);
     }
-
-    const int nl = CEIL7 ? 1 : nmod;
-    for (int l = 0; l < nl; ++l) {
-        if constexpr (CEIL7) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-#pragma unroll
-                for (int pl = 0; pl < NPLANES; ++pl) lds[pl][rl[e]][hl[e]] = (int8_t)bar[e][pl];
-        } else {
-            const ModConst &mc = tab->mod[l];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int a = residue<NCHUNK>(cR[e], nR[e], mc);
-                const int b = residue<NCHUNK>(cI[e], nI[e], mc);
-                lds[0][rl[e]][hl[e]] = (int8_t)a;
-                lds[1][rl[e]][hl[e]] = (int8_t)b;
-                if constexpr (NPLANES == 3) lds[2][rl[e]][hl[e]] = (int8_t)sum_residue(a, b, mc);
-            }
-        }
-        __syncthreads();
-        for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
-            const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
-            const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
-            int8_t *out = dst + ((int64_t)l * NPLANES + pl) * plane_pitch +
-                          (bx * rows_pad + r0 + row) * kTileH + seg * 16;
-            *reinterpret_cast<uint4 *>(out) = val;
-        }
-        __syncthreads();
+    __syncthreads();
+    for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
+        const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
+        const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
+        int8_t *out = dst + (int64_t)pl * plane_pitch + (bx * rows_pad + r0 + row) * kTileH + seg * 16;
+        *reinterpret_cast<uint4 *>(out) = val;
     }
 }
 
-// The same split without LDS staging (residues only).  A block of 256
-// threads covers 32 rows and one 64-wide k-slab; each thread holds 8
-// consecutive k of one row and writes their
-// residues as one 8-byte word per plane and modulus.  Eight consecutive lanes
-// share a row (lane i holds octet i), so each wave writes 8 whole 64-byte rows
-// (512 contiguous bytes) per plane and modulus, and the block writes each
-// plane's 32 x 64-byte block of the slab.  Loads: for rows contiguous with
-// each other a load instruction reads 8 rows at 8 k (128-byte runs); for rows
-// with contiguous k each lane reads its own 128-byte run.
+// ---------------------------------------------------------------- residue split
+// Truncation a' = trunc(x 2^mu) and symmetric residues modulo every p_l (and,
+// for Karatsuba, the reduced sum of the real and imaginary residues), written
+// zero-padded to rows_pad x k_pad in the slab-major order of the product
+// kernels.  No LDS staging: a block of 256 threads covers 16 rows and one
+// 64-wide k-slab; each thread holds 4 consecutive k of one row and writes
+// their residues as one 4-byte word per plane and modulus.  Sixteen
+// consecutive lanes share a row, so each wave writes 4 whole 64-byte rows
+// (256 contiguous bytes) per plane and modulus.  Loads: for rows contiguous
+// with each other one load instruction reads 4 rows at 16 k (64-byte runs);
+// for rows with contiguous k each lane reads its own 64-byte run.
 //
 // Residues in FP32: |a'| is held as NF signed 11-bit chunks c_j (a' =
 // sum_j c_j 2^(11 j)), so x = sum_j c_j w_j with w_j the symmetric residue of
@@ -460,17 +355,15 @@ __device__ __forceinline__ float smod_f(float x, float p, float ip) {
 }
 
 template <bool SINGLE, bool CONTIG_H, int NPLANES, int NF>
-__global__ __launch_bounds__(256) void split_direct_kernel(OperandView v,
-                                                           const int16_t *__restrict__ mu,
-                                                           const NTable *__restrict__ tab, int nmod,
-                                                           int8_t *__restrict__ dst,
-                                                           int64_t rows_pad, int64_t k_pad) {
+__device__ __forceinline__ void split_body(const OperandView &v, const int16_t *__restrict__ mu,
+                                           const NTable *__restrict__ tab, int nmod,
+                                           int8_t *__restrict__ dst, int64_t rows_pad,
+                                           int64_t k_pad, int64_t bx, int64_t by) {
     const int tid = threadIdx.x;
     constexpr int TPR = kTileH / kEPT;  // threads per row
     const int rl = tid / TPR;
     const int oc = tid % TPR;
-    const int64_t bx = blockIdx.x;
-    const int64_t r = (int64_t)blockIdx.y * kDirectRows + rl;
+    const int64_t r = by * kDirectRows + rl;
     const int64_t h0 = bx * kTileH + kEPT * oc;
     const int64_t plane_pitch = rows_pad * k_pad;
 
@@ -550,13 +443,19 @@ __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *max
                                                              int16_t *mu, uint32_t *status) {
     fast_exponents_body(maxbits, sigma, rows, rows_pad, tab, mu, status, blockIdx.x);
 }
-template <bool SINGLE, bool CONTIG_H, int NPLANES, int NCHUNK, bool CEIL7>
-__global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *mu,
-                                                    const uint64_t *maxbits, const NTable *tab,
-                                                    int nmod, int8_t *dst, int64_t rows_pad,
+template <bool SINGLE, bool CONTIG_H, int NPLANES, int NF>
+__global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *__restrict__ mu,
+                                                    const NTable *__restrict__ tab, int nmod,
+                                                    int8_t *__restrict__ dst, int64_t rows_pad,
                                                     int64_t k_pad) {
-    split_body<SINGLE, CONTIG_H, NPLANES, NCHUNK, CEIL7>(v, mu, maxbits, tab, nmod, dst, rows_pad,
-                                                         k_pad, blockIdx.x, blockIdx.y);
+    split_body<SINGLE, CONTIG_H, NPLANES, NF>(v, mu, tab, nmod, dst, rows_pad, k_pad, blockIdx.x,
+                                              blockIdx.y);
+}
+
+template <bool SINGLE, bool CONTIG_H>
+__global__ __launch_bounds__(256) void ceil7_kernel(OperandView v, const uint64_t *maxbits,
+                                                    int8_t *dst, int64_t rows_pad, int64_t k_pad) {
+    ceil7_body<SINGLE, CONTIG_H>(v, maxbits, dst, rows_pad, k_pad, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- kernels (batched)
@@ -607,20 +506,20 @@ __global__ __launch_bounds__(256) void batch_fast_exponents_kernel(const BatchOp
                         b - op.blk_exp);
 }
 
-template <bool SINGLE, int NPLANES, int NCHUNK>
+template <bool SINGLE, int NPLANES, int NF>
 __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops,
-                                                          const NTable *tab, int nmod) {
+                                                          const NTable *__restrict__ tab, int nmod) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_split; });
     const BatchOperand &op = ops[o];
     const int64_t lb = b - op.blk_split, gx = op.k_pad / kTileH;
     const int64_t bx = lb % gx, by = lb / gx;
     if (op.v.contig_h)
-        split_body<SINGLE, true, NPLANES, NCHUNK, false>(op.v, op.mu, nullptr, tab, nmod, op.res,
-                                                         op.rows_pad, op.k_pad, bx, by);
+        split_body<SINGLE, true, NPLANES, NF>(op.v, op.mu, tab, nmod, op.res, op.rows_pad, op.k_pad,
+                                              bx, by);
     else
-        split_body<SINGLE, false, NPLANES, NCHUNK, false>(op.v, op.mu, nullptr, tab, nmod, op.res,
-                                                          op.rows_pad, op.k_pad, bx, by);
+        split_body<SINGLE, false, NPLANES, NF>(op.v, op.mu, tab, nmod, op.res, op.rows_pad,
+                                               op.k_pad, bx, by);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -628,22 +527,20 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+#define OZC_NF_CASES(CASE) \
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
+
 template <bool SINGLE, int NPLANES>
-hipError_t batch_split_chunks(const BatchOperand *ops, int nops, int64_t blocks, const NTable *tab,
-                              int nmod, int nchunks, hipStream_t s) {
+hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, const NTable *tab,
+                          int nmod, int nf, hipStream_t s) {
     dim3 grid((unsigned)blocks);
-#define OZC_BSPLIT_CASE(NC)                                                                  \
-    case NC:                                                                                 \
-        hipLaunchKernelGGL((batch_split_kernel<SINGLE, NPLANES, NC>), grid, dim3(256), 0, s, \
+#define OZC_BSPLIT_CASE(NF)                                                                  \
+    case NF:                                                                                 \
+        hipLaunchKernelGGL((batch_split_kernel<SINGLE, NPLANES, NF>), grid, dim3(256), 0, s, \
                            ops, nops, tab, nmod);                                            \
         break;
-    switch (nchunks) {
-        OZC_BSPLIT_CASE(1)
-        OZC_BSPLIT_CASE(2)
-        OZC_BSPLIT_CASE(3)
-        OZC_BSPLIT_CASE(4)
-        OZC_BSPLIT_CASE(5)
-        OZC_BSPLIT_CASE(6)
+    switch (nf) {
+        OZC_NF_CASES(OZC_BSPLIT_CASE)
         default:
             return hipErrorInvalidValue;
     }
@@ -652,55 +549,26 @@ hipError_t batch_split_chunks(const BatchOperand *ops, int nops, int64_t blocks,
 }
 
 template <bool SINGLE, bool CONTIG_H, int NPLANES>
-hipError_t split_direct_chunks(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod,
-                               int nf, int8_t *dst, int64_t rows_pad, int64_t k_pad,
-                               hipStream_t s) {
+hipError_t split_nf(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod, int nf,
+                    int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kDirectRows));
-#define OZC_DIRECT_CASE(NF)                                                                  \
+#define OZC_SPLIT_CASE(NF)                                                                   \
     case NF:                                                                                 \
-        hipLaunchKernelGGL((split_direct_kernel<SINGLE, CONTIG_H, NPLANES, NF>), grid,       \
-                           dim3(256), 0, s, v, mu, tab, nmod, dst, rows_pad, k_pad);         \
+        hipLaunchKernelGGL((split_kernel<SINGLE, CONTIG_H, NPLANES, NF>), grid, dim3(256), 0, \
+                           s, v, mu, tab, nmod, dst, rows_pad, k_pad);                       \
         break;
     switch (nf) {
-        OZC_DIRECT_CASE(1)
-        OZC_DIRECT_CASE(2)
-        OZC_DIRECT_CASE(3)
-        OZC_DIRECT_CASE(4)
-        OZC_DIRECT_CASE(5)
-        OZC_DIRECT_CASE(6)
-        OZC_DIRECT_CASE(7)
-        OZC_DIRECT_CASE(8)
-        OZC_DIRECT_CASE(9)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef OZC_DIRECT_CASE
-    return hipGetLastError();
-}
-
-template <bool SINGLE, bool CONTIG_H, int NPLANES, bool CEIL7>
-hipError_t split_dispatch_chunks(const OperandView &v, const int16_t *mu, const uint64_t *maxbits,
-                                 const NTable *tab, int nmod, int nchunks, int8_t *dst,
-                                 int64_t rows_pad, int64_t k_pad, hipStream_t s) {
-    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kTileR));
-#define OZC_SPLIT_CASE(NC)                                                                   \
-    case NC:                                                                                 \
-        hipLaunchKernelGGL((split_kernel<SINGLE, CONTIG_H, NPLANES, NC, CEIL7>), grid,       \
-                           dim3(256), 0, s, v, mu, maxbits, tab, nmod, dst, rows_pad, k_pad); \
-        break;
-    switch (CEIL7 ? 1 : nchunks) {
-        OZC_SPLIT_CASE(1)
-        OZC_SPLIT_CASE(2)
-        OZC_SPLIT_CASE(3)
-        OZC_SPLIT_CASE(4)
-        OZC_SPLIT_CASE(5)
-        OZC_SPLIT_CASE(6)
+        OZC_NF_CASES(OZC_SPLIT_CASE)
         default:
             return hipErrorInvalidValue;
     }
 #undef OZC_SPLIT_CASE
     return hipGetLastError();
 }
+#undef OZC_NF_CASES
+
+// 11-bit chunks needed for |a'| < 2^abits.
+int fchunks(int abits) { return abits <= kFChunkBits ? 1 : (abits + kFChunkBits - 1) / kFChunkBits; }
 
 }  // namespace
 
@@ -759,51 +627,37 @@ hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int6
     return hipGetLastError();
 }
 
-#define OZC_DIRECT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
 hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
-                        int nmod, int nplanes, int nchunks, int abits, int8_t *dst,
-                        int64_t rows_pad, int64_t k_pad, hipStream_t s) {
-    if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
-    int nf = (abits + kFChunkBits - 1) / kFChunkBits;
-    if (nf < 1) nf = 1;
-    if (rows_pad % kDirectRows == 0 && nf <= kMaxFChunks) {
-        if (single) {
-            if (v.contig_h) return nplanes == 3 ? split_direct_chunks<true, true, 3>(OZC_DIRECT_ARGS)
-                                                : split_direct_chunks<true, true, 2>(OZC_DIRECT_ARGS);
-            return nplanes == 3 ? split_direct_chunks<true, false, 3>(OZC_DIRECT_ARGS)
-                                : split_direct_chunks<true, false, 2>(OZC_DIRECT_ARGS);
-        }
-        if (v.contig_h) return nplanes == 3 ? split_direct_chunks<false, true, 3>(OZC_DIRECT_ARGS)
-                                            : split_direct_chunks<false, true, 2>(OZC_DIRECT_ARGS);
-        return nplanes == 3 ? split_direct_chunks<false, false, 3>(OZC_DIRECT_ARGS)
-                            : split_direct_chunks<false, false, 2>(OZC_DIRECT_ARGS);
-    }
-#define OZC_SPLIT_ARGS v, mu, nullptr, tab, nmod, nchunks, dst, rows_pad, k_pad, s
+                        int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
+                        int64_t k_pad, hipStream_t s) {
+    const int nf = fchunks(abits);
+    if (rows_pad % kDirectRows || k_pad % kTileH || nf > kMaxFChunks) return hipErrorInvalidValue;
+#define OZC_SPLIT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
     if (single) {
-        if (v.contig_h) return nplanes == 3 ? split_dispatch_chunks<true, true, 3, false>(OZC_SPLIT_ARGS)
-                                            : split_dispatch_chunks<true, true, 2, false>(OZC_SPLIT_ARGS);
-        return nplanes == 3 ? split_dispatch_chunks<true, false, 3, false>(OZC_SPLIT_ARGS)
-                            : split_dispatch_chunks<true, false, 2, false>(OZC_SPLIT_ARGS);
+        if (v.contig_h) return nplanes == 3 ? split_nf<true, true, 3>(OZC_SPLIT_ARGS)
+                                            : split_nf<true, true, 2>(OZC_SPLIT_ARGS);
+        return nplanes == 3 ? split_nf<true, false, 3>(OZC_SPLIT_ARGS)
+                            : split_nf<true, false, 2>(OZC_SPLIT_ARGS);
     }
-    if (v.contig_h) return nplanes == 3 ? split_dispatch_chunks<false, true, 3, false>(OZC_SPLIT_ARGS)
-                                        : split_dispatch_chunks<false, true, 2, false>(OZC_SPLIT_ARGS);
-    return nplanes == 3 ? split_dispatch_chunks<false, false, 3, false>(OZC_SPLIT_ARGS)
-                        : split_dispatch_chunks<false, false, 2, false>(OZC_SPLIT_ARGS);
+    if (v.contig_h) return nplanes == 3 ? split_nf<false, true, 3>(OZC_SPLIT_ARGS)
+                                        : split_nf<false, true, 2>(OZC_SPLIT_ARGS);
+    return nplanes == 3 ? split_nf<false, false, 3>(OZC_SPLIT_ARGS)
+                        : split_nf<false, false, 2>(OZC_SPLIT_ARGS);
 #undef OZC_SPLIT_ARGS
 }
-#undef OZC_DIRECT_ARGS
 
 hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits, int8_t *dst,
                         int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
-#define OZC_C7_ARGS v, nullptr, maxbits, nullptr, 1, 1, dst, rows_pad, k_pad, s
+    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kTileR));
     if (single) {
-        return v.contig_h ? split_dispatch_chunks<true, true, 3, true>(OZC_C7_ARGS)
-                          : split_dispatch_chunks<true, false, 3, true>(OZC_C7_ARGS);
+        if (v.contig_h) hipLaunchKernelGGL((ceil7_kernel<true, true>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+        else hipLaunchKernelGGL((ceil7_kernel<true, false>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+    } else {
+        if (v.contig_h) hipLaunchKernelGGL((ceil7_kernel<false, true>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+        else hipLaunchKernelGGL((ceil7_kernel<false, false>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
     }
-    return v.contig_h ? split_dispatch_chunks<false, true, 3, true>(OZC_C7_ARGS)
-                      : split_dispatch_chunks<false, false, 3, true>(OZC_C7_ARGS);
-#undef OZC_C7_ARGS
+    return hipGetLastError();
 }
 
 int64_t batch_scan_blocks(const OperandView &v) {
@@ -812,7 +666,7 @@ int64_t batch_scan_blocks(const OperandView &v) {
 }
 int64_t batch_exp_blocks(int64_t rows_pad) { return (rows_pad + 255) / 256; }
 int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad) {
-    return (k_pad / kTileH) * (rows_pad / kTileR);
+    return (k_pad / kTileH) * (rows_pad / kDirectRows);
 }
 
 hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
@@ -838,14 +692,15 @@ hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_
 }
 
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                              const NTable *tab, int nmod, int nplanes, int nchunks,
-                              hipStream_t s) {
+                              const NTable *tab, int nmod, int nplanes, int abits, hipStream_t s) {
     if (blocks <= 0 || nops <= 0) return hipSuccess;
+    const int nf = fchunks(abits);
+    if (nf > kMaxFChunks) return hipErrorInvalidValue;
     if (single)
-        return nplanes == 3 ? batch_split_chunks<true, 3>(ops, nops, blocks, tab, nmod, nchunks, s)
-                            : batch_split_chunks<true, 2>(ops, nops, blocks, tab, nmod, nchunks, s);
-    return nplanes == 3 ? batch_split_chunks<false, 3>(ops, nops, blocks, tab, nmod, nchunks, s)
-                        : batch_split_chunks<false, 2>(ops, nops, blocks, tab, nmod, nchunks, s);
+        return nplanes == 3 ? batch_split_nf<true, 3>(ops, nops, blocks, tab, nmod, nf, s)
+                            : batch_split_nf<true, 2>(ops, nops, blocks, tab, nmod, nf, s);
+    return nplanes == 3 ? batch_split_nf<false, 3>(ops, nops, blocks, tab, nmod, nf, s)
+                        : batch_split_nf<false, 2>(ops, nops, blocks, tab, nmod, nf, s);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {

@@ -161,14 +161,9 @@ void build_tables(NTable *tables) {
             mc.half = (p + 1) / 2;
             mc.barrett = (uint32_t)((1ull << 32) / p);
             mc.koff = (p & 1u) ? (uint32_t)(((1ull << 31) + p - 1) / p * p) : 0u;
-            uint64_t pw = 1;
-            for (int j = 0; j < kMaxChunks; ++j) {
-                mc.w[j] = (uint32_t)(pw % p);
-                pw = (pw % p) * ((1ull << kChunkBits) % p);
-            }
             mc.pf = (float)p;
             mc.ipf = 1.0f / (float)p;  // correctly rounded single division
-            pw = 1;
+            uint64_t pw = 1;
             for (int j = 0; j < kMaxFChunks; ++j) {
                 const uint32_t r = (uint32_t)(pw % p);
                 mc.wf[j] = (float)(r >= mc.half ? (int)r - (int)p : (int)r);
