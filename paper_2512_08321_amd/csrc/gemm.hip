@@ -4,10 +4,11 @@
 // One block computes a TM x TN output tile of one modulus l with WM x WN
 // waves; each wave owns (BM*32) x (BN*32) outputs as BM x BN blocks of
 // v_mfma_i32_32x32x32_i8 (large problems: 256 x 256 tiles, 8 waves of
-// 128 x 64, two waves per SIMD; small problems: 128 x 128, 4 waves of 64 x 64).  The products of the chosen algorithm run one after
-// another over the same tile, each as a k-loop over double-buffered LDS
-// tiles (one barrier per 64-wide k-step, the next tile prefetched into
-// registers while the current one feeds the matrix cores).  Between products
+// 128 x 64, two waves per SIMD; small problems: 128 x 128, 4 waves of
+// 64 x 64).  The products of the chosen algorithm run one after another over
+// the same tile, each as a k-loop over a ring of LDS buffers that the load
+// units fill straight from global memory a few 64-wide k-slabs ahead of the
+// matrix cores (one barrier per k-slab).  Between products
 // the INT32 accumulators are reduced to symmetric residues in registers; one
 // packed INT8 carry per output survives to the next product, and E'_R, E'_I
 // are stored as soon as they are final, so only INT8 data leaves the chip:
@@ -112,30 +113,20 @@ __device__ __forceinline__ void map_tile(int64_t L, int64_t TR, int64_t TC, int6
 }
 
 // WM x WN waves of BM x BN blocks; KS 64-byte k sub-slabs per pipeline stage.
-// DMA: k-slabs are copied global -> LDS by the load units directly (gfx950
+// k-slabs are copied global -> LDS by the load units directly (gfx950
 // global_load_lds_dwordx4) into a ring of NSTAGE buffers, NSTAGE - 1 slabs
-// ahead of the matrix cores; otherwise they are staged through registers
-// one slab ahead into two LDS buffers.
-template <int WM_, int WN_, int BM_, int BN_, int KS_, int DMA_ = 0>
+// ahead of the matrix cores.
+template <int WM_, int WN_, int BM_, int BN_, int KS_, int NSTAGE_>
 struct TileCfg {
     static constexpr int WM = WM_, WN = WN_, BM = BM_, BN = BN_, KS = KS_;
-    static constexpr bool DMA = DMA_ != 0;
-    static constexpr int NSTAGE = DMA ? 4 : 2;
+    static constexpr int NSTAGE = NSTAGE_;
     static constexpr int TM = WM * BM * 32, TN = WN * BN * 32;
     static constexpr int THREADS = 64 * WM * WN;
-    static constexpr int NLA = TM * 4 / THREADS;  // 16-byte loads per thread per sub-slab (A)
-    static constexpr int NLB = TN * 4 / THREADS;  // (B)
-    static constexpr int ROWS_PER_LOAD = THREADS / 4;
     static constexpr int STAGE = (TM + TN) * 4;   // uint4 per sub-slab in LDS
     static constexpr int KSTEP = BK * KS;
 };
-#ifndef OZC_LARGE_CFG
-#define OZC_LARGE_CFG 2, 4, 4, 2, 1, 1
-#endif
-using CfgLarge = TileCfg<OZC_LARGE_CFG>;  // 256 x 256 output tiles
-using CfgSmall = TileCfg<2, 2, 2, 2, 1>;  // 128 x 128, 256 threads
-
-__device__ __forceinline__ uint4 ld16(const int8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+using CfgLarge = TileCfg<2, 4, 4, 2, 1, 4>;  // 256 x 256 output tiles, 512 threads, 128 KB LDS
+using CfgSmall = TileCfg<2, 2, 2, 2, 1, 4>;  // 128 x 128, 256 threads, 64 KB LDS
 
 // One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS:
 // lane i reads sbase + voff_i + OFF and writes lds_base + OFF + 16 i (the
@@ -194,10 +185,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
     const int8_t *baseA = (bound ? b.A : a.A) + (int64_t)l * P::nplanes * planeA + i0 * BK;
     const int8_t *baseB = (bound ? b.B : a.B) + (int64_t)l * P::nplanes * planeB + j0 * BK;
 
-    const int lrow = tid >> 2, lseg = tid & 3;
     const int nk = (int)(k_pad / C::KSTEP);
-    constexpr int64_t rstep = (int64_t)C::ROWS_PER_LOAD * BK;
-    constexpr int NLA = C::NLA, NLB = C::NLB;
 
     ModConst mc;
     if constexpr (!bound) mc = a.tab->mod[l];
@@ -207,8 +195,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
 
 #pragma unroll 1
     for (int sgi = 0; sgi < P::nseg; ++sgi) {
-        const int8_t *Ap = baseA + (int64_t)P::pa(sgi) * planeA + lrow * BK + lseg * 16;
-        const int8_t *Bp = baseB + (int64_t)P::pb(sgi) * planeB + lrow * BK + lseg * 16;
         if (!bound || sgi == 0) {
             static_for<BM>([&](auto bi) { static_for<BN>([&](auto bj) { acc[bi][bj] = v16i{}; }); });
         }
@@ -239,16 +225,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                 });
             });
         };
-        auto compute = [&](const uint4 *Lbuf) {
-            static_for<KS>([&](auto ks) {
-                static_for<2>([&](auto kk) {
-                    v4i fa[BM], fb[BN];
-                    read_frags(Lbuf + ks * C::STAGE, kk, fa, fb);
-                    mfmas(fa, fb);
-                });
-            });
-        };
-        if constexpr (C::DMA) {
+        {
             // Each wave fills whole 1 KB chunks (16 rows) of the A and B slabs: lane i of a
             // chunk writes LDS granule i, i.e. row 16c + i/4 at position i mod 4, which holds
             // the swizzled global granule (i mod 4) ^ swz_bits(row).  A ring stage holds KS
@@ -342,37 +319,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
             for (; s + 1 < nk; ++s) stage(s, T{}, F{}, W0{});
             stage(s, F{}, F{}, W0{});
             block_barrier();  // all waves done with the ring before it is refilled
-        } else {
-            uint4 ra[KS * NLA], rb[KS * NLB];
-            auto gload = [&](int64_t st) {
-                static_for<KS>([&](auto ks) {
-                    const int64_t ks_idx = st * KS + ks;
-                    static_for<NLA>([&](auto q) { ra[ks * NLA + q] = ld16(Ap + q * rstep + ks_idx * slabA); });
-                    static_for<NLB>([&](auto q) { rb[ks * NLB + q] = ld16(Bp + q * rstep + ks_idx * slabB); });
-                });
-            };
-            // rows handled by one thread differ by multiples of 16, so they share swz_bits
-            auto lstore = [&](uint4 *L) {
-                uint4 *Ls = L + lrow * 4 + (lseg ^ swz_bits(lrow));
-                static_for<KS>([&](auto ks) {
-                    static_for<NLA>([&](auto q) { Ls[ks * C::STAGE + q * C::ROWS_PER_LOAD * 4] = ra[ks * NLA + q]; });
-                    static_for<NLB>([&](auto q) {
-                        Ls[ks * C::STAGE + TM * 4 + q * C::ROWS_PER_LOAD * 4] = rb[ks * NLB + q];
-                    });
-                });
-            };
-            gload(0);
-            lstore(lds[0]);
-            __syncthreads();
-
-            for (int s = 0; s < nk; ++s) {
-                const int cur = s & 1;
-                const bool more = s + 1 < nk;
-                if (more) gload((int64_t)(s + 1));
-                compute(lds[cur]);
-                if (more) lstore(lds[cur ^ 1]);
-                __syncthreads();
-            }
         }
 
         // ------------------------------------------------ per-product epilogue

@@ -370,6 +370,12 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
     int ex = kExpZero;
     if (r < v.rows) ex = mu[r];
     const bool live = ex != kExpZero && ex != kExpNonfinite;
+    int8_t *out = dst + (bx * rows_pad + r) * kTileH + kEPT * oc;
+    if (!live || h0 >= v.k) {  // padding, or a row without scaling: every residue is 0
+        const int z[kEPT] = {};
+        for (int q = 0; q < nmod * NPLANES; ++q) store_res(out + (int64_t)q * plane_pitch, z);
+        return;
+    }
     float cR[kEPT][NF], cI[kEPT][NF];
 #pragma unroll
     for (int j = 0; j < kEPT; ++j) {
@@ -383,7 +389,6 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
         trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
     }
 
-    int8_t *out = dst + (bx * rows_pad + r) * kTileH + kEPT * oc;
     for (int l = 0; l < nmod; ++l) {
         const ModConst &mc = tab->mod[l];
         const float p = mc.pf, ip = mc.ipf;
