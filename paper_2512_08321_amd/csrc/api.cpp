@@ -25,8 +25,8 @@ struct Layout {
 Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool with_prods) {
     Layout L{};
     L.tile = gemm_tile_for(m, n);
-    L.m_pad = round_up(m > 0 ? m : 1, L.tile);
-    L.n_pad = round_up(n > 0 ? n : 1, L.tile);
+    L.m_pad = round_up(m > 0 ? m : 1, gemm_tile_rows(L.tile));
+    L.n_pad = round_up(n > 0 ? n : 1, gemm_tile_cols(L.tile));
     L.k_pad = round_up(k > 0 ? k : 1, gemm_kstep_for(L.tile));
     L.planes = h->algo == OZC_ALGO_KARATSUBA ? 3 : 2;
     L.nprod = h->algo == OZC_ALGO_KARATSUBA ? 3 : 4;

@@ -188,8 +188,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         Pad d{};
         d.p = p;
         d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
-        d.m_pad = round_up(q.m, d.tile);
-        d.n_pad = round_up(q.n, d.tile);
+        d.m_pad = round_up(q.m, gemm_tile_rows(d.tile));
+        d.n_pad = round_up(q.n, gemm_tile_cols(d.tile));
         d.k_pad = round_up(q.k, gemm_kstep_for(d.tile));
         d.sA = stats_words;
         stats_words += 2 * (size_t)d.m_pad;  // maxbits, sigma
@@ -283,8 +283,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         g.m_pad = d.m_pad;
         g.n_pad = d.n_pad;
         g.k_pad = d.k_pad;
-        g.TR = (int32_t)(d.m_pad / d.tile);
-        g.TC = (int32_t)(d.n_pad / d.tile);
+        g.TR = (int32_t)(d.m_pad / gemm_tile_rows(d.tile));
+        g.TC = (int32_t)(d.n_pad / gemm_tile_cols(d.tile));
         P.gm[d.tile == 256 ? 0 : 1].push_back(g);
     }
     // largest k first, so that the long items start early and the short ones fill the tail

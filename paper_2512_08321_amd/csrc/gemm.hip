@@ -470,13 +470,16 @@ void launch_kind(const GemmArgs &a, const BoundArgs &b, bool dump, int64_t block
 
 int gemm_tile_for(int64_t m, int64_t n) { return (m >= 1024 && n >= 1024) ? 256 : 128; }
 int gemm_kstep_for(int tile) { return tile == 256 ? CfgLarge::KSTEP : CfgSmall::KSTEP; }
+int gemm_tile_rows(int tile) { return tile == 256 ? CfgLarge::TM : CfgSmall::TM; }
+int gemm_tile_cols(int tile) { return tile == 256 ? CfgLarge::TN : CfgSmall::TN; }
 
 hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s) {
     const int tile = a.tile;
-    if ((tile != 128 && tile != 256) || a.m_pad % tile || a.n_pad % tile ||
-        a.k_pad % gemm_kstep_for(tile) || a.nmod < 1)
+    if (tile != 128 && tile != 256) return hipErrorInvalidValue;
+    const int tr = gemm_tile_rows(tile), tc = gemm_tile_cols(tile);
+    if (a.m_pad % tr || a.n_pad % tc || a.k_pad % gemm_kstep_for(tile) || a.nmod < 1)
         return hipErrorInvalidValue;
-    const int64_t blocks = (int64_t)a.nmod * (a.m_pad / tile) * (a.n_pad / tile);
+    const int64_t blocks = (int64_t)a.nmod * (a.m_pad / tr) * (a.n_pad / tc);
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     BoundArgs none{};
     const bool dump = a.prods != nullptr;

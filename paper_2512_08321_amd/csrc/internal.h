@@ -92,6 +92,10 @@ hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s);
 int gemm_tile_for(int64_t m, int64_t n);
 // k padding granule of the product kernel for a tile edge (every buffer's k_pad follows it).
 int gemm_kstep_for(int tile);
+// Output rows (of op(A)) and columns (of op(B)) of one product tile of size class `tile`:
+// m_pad and n_pad are multiples of these.
+int gemm_tile_rows(int tile);
+int gemm_tile_cols(int tile);
 
 // Accurate-mode bound product: X[i] = max_j max(Cbar_R, Cbar_I)_ij, Y[j] likewise.
 struct BoundArgs {
