@@ -37,6 +37,7 @@ Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool w
         off = align_up(off + bytes);
         return o;
     };
+    // maxA ... YB must stay adjacent and in this order: the scaling phase zeroes them with one fill
     L.maxA = take(8 * (size_t)L.m_pad);
     L.maxB = take(8 * (size_t)L.n_pad);
     L.sigA = take(8 * (size_t)L.m_pad);
@@ -251,14 +252,12 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     const int fault = h->fault;
     // Step III: scaling exponents
     OZC_TRY(pe.mark(0));
-    OZC_TRY(launch_fill_u64(maxA, L.m_pad, 0, s));
-    OZC_TRY(launch_fill_u64(maxB, L.n_pad, 0, s));
+    // one fill zeroes the row statistics maxA, maxB, sigA, sigB, XA, YB (adjacent in the layout)
+    OZC_TRY(launch_fill_u64(maxA, (int64_t)(L.muA - L.maxA) / 8, 0, s));
     OZC_TRY(launch_row_maxabs(vA, single, maxA, s));
     OZC_TRY(launch_row_maxabs(vB, single, maxB, s));
     int abits;
     if (h->mode == OZC_MODE_FAST) {
-        OZC_TRY(launch_fill_u64(sigA, L.m_pad, 0, s));
-        OZC_TRY(launch_fill_u64(sigB, L.n_pad, 0, s));
         OZC_TRY(launch_row_sigma(vA, single, maxA, sigA, s));
         OZC_TRY(launch_row_sigma(vB, single, maxB, sigB, s));
         OZC_TRY(launch_fast_exponents(maxA, sigA, m, L.m_pad, tab, muA, status, s));
@@ -266,8 +265,6 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         abits = th.max_abits_fast;
     } else {
         int8_t *barA = (int8_t *)(ws + L.barA), *barB = (int8_t *)(ws + L.barB);
-        OZC_TRY(launch_fill_u64((uint64_t *)XA, L.m_pad / 2, 0, s));
-        OZC_TRY(launch_fill_u64((uint64_t *)YB, L.n_pad / 2, 0, s));
         OZC_TRY(launch_ceil7(vA, single, maxA, barA, L.m_pad, L.k_pad, s));
         OZC_TRY(launch_ceil7(vB, single, maxB, barB, L.n_pad, L.k_pad, s));
         BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB, L.tile};

@@ -113,11 +113,11 @@ __device__ __forceinline__ void maxabs_contig_body(const OperandView &v, uint64_
 
 template <bool SINGLE>
 __device__ __forceinline__ void maxabs_strided_body(const OperandView &v, uint64_t *maxbits,
-                                                    int64_t bx, int64_t by) {
+                                                    int64_t bx, int64_t by, int hc) {
     const int64_t r = bx * 256 + threadIdx.x;
     if (r >= v.rows) return;
-    const int64_t h0 = by * (kHChunk / 8);
-    const int64_t h1 = min(v.k, h0 + kHChunk / 8);
+    const int64_t h0 = by * hc;
+    const int64_t h1 = min(v.k, h0 + hc);
     uint64_t m = 0;
     for (int64_t h = h0; h < h1; ++h) {
         double re, im;
@@ -155,14 +155,14 @@ __device__ __forceinline__ void sigma_contig_body(const OperandView &v, const ui
 
 template <bool SINGLE>
 __device__ __forceinline__ void sigma_strided_body(const OperandView &v, const uint64_t *maxbits,
-                                                   uint64_t *sigma, int64_t bx, int64_t by) {
+                                                   uint64_t *sigma, int64_t bx, int64_t by, int hc) {
     const int64_t r = bx * 256 + threadIdx.x;
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
     if (mb == 0 || mb >= kInfBits) return;
     const int sh = kSigmaFracBits - ilogb_bits(mb);
-    const int64_t h0 = by * (kHChunk / 8);
-    const int64_t h1 = min(v.k, h0 + kHChunk / 8);
+    const int64_t h0 = by * hc;
+    const int64_t h1 = min(v.k, h0 + hc);
     uint64_t s = 0;
     for (int64_t h = h0; h < h1; ++h) {
         double re, im;
@@ -429,8 +429,8 @@ __global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t
     maxabs_contig_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y);
 }
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits) {
-    maxabs_strided_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits, int hc) {
+    maxabs_strided_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y, hc);
 }
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uint64_t *maxbits,
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uin
 }
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const uint64_t *maxbits,
-                                                         uint64_t *sigma) {
-    sigma_strided_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y);
+                                                         uint64_t *sigma, int hc) {
+    sigma_strided_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y, hc);
 }
 __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *maxbits,
                                                              const uint64_t *sigma, int64_t rows,
@@ -496,8 +496,8 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const BatchOperand *ops
         if constexpr (SIGMA) sigma_contig_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by);
         else maxabs_contig_body<SINGLE>(v, ops[o].maxbits, bx, by);
     } else {
-        if constexpr (SIGMA) sigma_strided_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by);
-        else maxabs_strided_body<SINGLE>(v, ops[o].maxbits, bx, by);
+        if constexpr (SIGMA) sigma_strided_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by, kHChunk / 8);
+        else maxabs_strided_body<SINGLE>(v, ops[o].maxbits, bx, by, kHChunk / 8);
     }
 }
 
@@ -583,6 +583,15 @@ hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// k-elements per thread of the strided scans: 256, halved (down to 16) while the grid
+// would have fewer than 1024 blocks, so that small operands still spread over the chip.
+static int strided_chunk(const OperandView &v) {
+    const int64_t bx = (v.rows + 255) / 256;
+    int hc = kHChunk / 8;
+    while (hc > 16 && bx * ((v.k + hc - 1) / hc) < 1024) hc /= 2;
+    return hc;
+}
+
 hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbits, hipStream_t s) {
     if (v.rows <= 0 || v.k <= 0) return hipSuccess;
     if (v.contig_h) {
@@ -590,10 +599,10 @@ hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbit
         if (single) hipLaunchKernelGGL(row_maxabs_contig<true>, grid, dim3(256), 0, s, v, maxbits);
         else hipLaunchKernelGGL(row_maxabs_contig<false>, grid, dim3(256), 0, s, v, maxbits);
     } else {
-        const int hc = kHChunk / 8;
+        const int hc = strided_chunk(v);
         dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
-        if (single) hipLaunchKernelGGL(row_maxabs_strided<true>, grid, dim3(256), 0, s, v, maxbits);
-        else hipLaunchKernelGGL(row_maxabs_strided<false>, grid, dim3(256), 0, s, v, maxbits);
+        if (single) hipLaunchKernelGGL(row_maxabs_strided<true>, grid, dim3(256), 0, s, v, maxbits, hc);
+        else hipLaunchKernelGGL(row_maxabs_strided<false>, grid, dim3(256), 0, s, v, maxbits, hc);
     }
     return hipGetLastError();
 }
@@ -606,10 +615,10 @@ hipError_t launch_row_sigma(const OperandView &v, bool single, const uint64_t *m
         if (single) hipLaunchKernelGGL(row_sigma_contig<true>, grid, dim3(256), 0, s, v, maxbits, sigma);
         else hipLaunchKernelGGL(row_sigma_contig<false>, grid, dim3(256), 0, s, v, maxbits, sigma);
     } else {
-        const int hc = kHChunk / 8;
+        const int hc = strided_chunk(v);
         dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
-        if (single) hipLaunchKernelGGL(row_sigma_strided<true>, grid, dim3(256), 0, s, v, maxbits, sigma);
-        else hipLaunchKernelGGL(row_sigma_strided<false>, grid, dim3(256), 0, s, v, maxbits, sigma);
+        if (single) hipLaunchKernelGGL(row_sigma_strided<true>, grid, dim3(256), 0, s, v, maxbits, sigma, hc);
+        else hipLaunchKernelGGL(row_sigma_strided<false>, grid, dim3(256), 0, s, v, maxbits, sigma, hc);
     }
     return hipGetLastError();
 }
