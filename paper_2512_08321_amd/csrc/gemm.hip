@@ -191,7 +191,49 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
     if constexpr (!bound) mc = a.tab->mod[l];
     const int64_t planeC = bound ? 0 : a.n_pad * a.m_pad;
 
+    // Each wave fills whole 1 KB chunks (16 rows) of the A and B slabs: lane i of a
+    // chunk writes LDS granule i, i.e. row 16c + i/4 at position i mod 4, which holds
+    // the swizzled global granule (i mod 4) ^ swz_bits(row).  A ring stage holds KS
+    // consecutive 64-wide k-slabs.
+    constexpr int CA = TM / 16, CB = TN / 16, NW = C::WM * C::WN;
+    static_assert(CA % NW == 0 && CB % NW == 0, "chunks per wave");
+    // a stage is waited for one stage before it is consumed and issued AHEAD >= 2
+    // stages ahead, so its buffer was released by the barrier of the stage before
+    static_assert(C::NSTAGE >= 3, "DMA ring needs at least three buffers");
+    constexpr int QA = CA / NW, QB = CB / NW, NLOAD = KS * (QA + QB);  // loads per wave per stage
+    static_assert(QA <= 4 && QB <= 4, "chunk offsets must fit the instruction offset");
+    constexpr int AHEAD = C::NSTAGE - 1, NH = 2 * KS;
+    const int crow = lane >> 2;
+    const int cg = (lane & 3) ^ swz_bits(crow);  // chunk rows start at multiples of 16
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // per-lane offsets inside the wave's first chunk (same for every stage and product)
+    const uint32_t voffA = (uint32_t)(wv * QA * 1024 + crow * BK + cg * 16);
+    const uint32_t voffB = (uint32_t)(wv * QB * 1024 + crow * BK + cg * 16);
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint4 *)(&lds[0][0]);
+    // plane bases of product g (wave-uniform)
+    auto pa_of = [&](int g) { return uniform_ptr(baseA + (int64_t)P::pa(g) * planeA); };
+    auto pb_of = [&](int g) { return uniform_ptr(baseB + (int64_t)P::pb(g) * planeB); };
+    auto issue_from = [&](const int8_t *sa, const int8_t *sb_, int st) {  // stage st -> buffer st % NSTAGE
+        const uint32_t buf = lbase + (uint32_t)((st % C::NSTAGE) * KS * C::STAGE * 16);
+        static_for<KS>([&](auto ks) {
+            const int64_t ks_idx = (int64_t)st * KS + ks;
+            const uint32_t la = buf + (uint32_t)(ks * C::STAGE * 16 + wv * QA * 1024);
+            const uint32_t lb = buf + (uint32_t)(ks * C::STAGE * 16 + TM * 64 + wv * QB * 1024);
+            static_for<QA>([&](auto q) { dma16<q * 1024>(sa + ks_idx * slabA, voffA, la); });
+            static_for<QB>([&](auto q) { dma16<q * 1024>(sb_ + ks_idx * slabB, voffB, lb); });
+        });
+    };
+    // The first AHEAD stages of a product.  Those of product g + 1 are issued right
+    // after product g's last barrier, so they load while g's epilogue runs.
+    auto issue_first = [&](int g) {
+        const int8_t *sa = pa_of(g), *sb_ = pb_of(g);
+        static_for<AHEAD>([&](auto st) {
+            if (st < nk) issue_from(sa, sb_, st);
+        });
+    };
+
     v16i acc[BM][BN];
+    issue_first(0);
 
 #pragma unroll 1
     for (int sgi = 0; sgi < P::nseg; ++sgi) {
@@ -226,47 +268,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
             });
         };
         {
-            // Each wave fills whole 1 KB chunks (16 rows) of the A and B slabs: lane i of a
-            // chunk writes LDS granule i, i.e. row 16c + i/4 at position i mod 4, which holds
-            // the swizzled global granule (i mod 4) ^ swz_bits(row).  A ring stage holds KS
-            // consecutive 64-wide k-slabs.
-            constexpr int CA = TM / 16, CB = TN / 16, NW = C::WM * C::WN;
-            static_assert(CA % NW == 0 && CB % NW == 0, "chunks per wave");
-            // a stage is waited for one stage before it is consumed and issued AHEAD >= 2
-            // stages ahead, so its buffer was released by the barrier of the stage before
-            static_assert(C::NSTAGE >= 3, "DMA ring needs at least three buffers");
-            constexpr int QA = CA / NW, QB = CB / NW, NLOAD = KS * (QA + QB);  // loads per wave per stage
-            static_assert(QA <= 4 && QB <= 4, "chunk offsets must fit the instruction offset");
-            const int crow = lane >> 2;
-            const int cg = (lane & 3) ^ swz_bits(crow);  // chunk rows start at multiples of 16
-            const int wv = __builtin_amdgcn_readfirstlane(wave);
-            // per-lane offsets inside the wave's first chunk (same for every stage and product)
-            const uint32_t voffA = (uint32_t)(wv * QA * 1024 + crow * BK + cg * 16);
-            const uint32_t voffB = (uint32_t)(wv * QB * 1024 + crow * BK + cg * 16);
-            const int8_t *sa = uniform_ptr(baseA + (int64_t)P::pa(sgi) * planeA);
-            const int8_t *sb_ = uniform_ptr(baseB + (int64_t)P::pb(sgi) * planeB);
-            const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint4 *)(&lds[0][0]);
-            auto issue = [&](int st) {  // ring stage st -> buffer st % NSTAGE
-                const uint32_t buf = lbase + (uint32_t)((st % C::NSTAGE) * KS * C::STAGE * 16);
-                static_for<KS>([&](auto ks) {
-                    const int64_t ks_idx = (int64_t)st * KS + ks;
-                    const uint32_t la = buf + (uint32_t)(ks * C::STAGE * 16 + wv * QA * 1024);
-                    const uint32_t lb = buf + (uint32_t)(ks * C::STAGE * 16 + TM * 64 + wv * QB * 1024);
-                    static_for<QA>([&](auto q) { dma16<q * 1024>(sa + ks_idx * slabA, voffA, la); });
-                    static_for<QB>([&](auto q) { dma16<q * 1024>(sb_ + ks_idx * slabB, voffB, lb); });
-                });
-            };
+            const int8_t *sa = pa_of(sgi), *sb_ = pb_of(sgi);
+            auto issue = [&](int st) { issue_from(sa, sb_, st); };
             // Software pipeline over half-slabs (32-wide k): the fragments of the next half
             // are read while the current half's matrix instructions run.  The one barrier
             // per stage sits before the last half's MFMAs, after the wait for the next
             // stage, so queued MFMAs keep the matrix pipe busy while the waves meet; after
             // it the oldest buffer is free and receives the stage AHEAD steps ahead.
-            constexpr int AHEAD = C::NSTAGE - 1, NH = 2 * KS;
-            static_for<AHEAD>([&](auto st) {
-                if (st < nk) issue(st);
-            });
-            if (nk > 2 && AHEAD >= 3) vmcnt_wait<2 * NLOAD>();
-            else if (nk > 1 && AHEAD >= 2) vmcnt_wait<NLOAD>();
+            // product 0: stages 1 .. AHEAD-1 may stay in flight; a later product's first
+            // stages were issued before the previous epilogue's stores, so wait for all
+            if (sgi == 0 && nk > 2 && AHEAD >= 3) vmcnt_wait<2 * NLOAD>();
+            else if (sgi == 0 && nk > 1 && AHEAD >= 2) vmcnt_wait<NLOAD>();
             else vmcnt_wait<0>();
             block_barrier();
             v4i fa[2][BM], fb[2][BN];
@@ -323,6 +335,33 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
 
         // ------------------------------------------------ per-product epilogue
         // (compile-time loops only: the accumulators must stay in registers)
+        // The residue carried from one product to the next (mod(D) then mod(D + E) for
+        // Karatsuba, mod(RR) and mod(RI) for the expanded form) is parked in this
+        // thread's own E'_I words, which receive the final E'_I last; each lane
+        // re-reads only what it wrote, so no synchronisation is needed.  The carries are
+        // loaded and awaited first; then the next product's first stages are queued, so
+        // that their copies overlap the rest of this epilogue.
+        constexpr bool karatsuba = KIND == KIND_KARATSUBA;
+        auto eword = [&](int8_t *E, int bi, int bj, int g) {
+            const int64_t i = i0 + wm * WTM + bi * 32 + 8 * g + 4 * (lane >> 5);
+            const int64_t j = j0 + wn * WTN + bj * 32 + (lane & 31);
+            return reinterpret_cast<uint32_t *>(E + j * a.m_pad + i);
+        };
+        int8_t *ER = nullptr, *EI = nullptr;
+        uint32_t cw[BM][BN][4];
+        if constexpr (!bound) {
+            ER = a.eprime + (int64_t)l * 2 * planeC;
+            EI = ER + planeC;
+            if (sgi >= 1 && (karatsuba || sgi != 2)) {
+                static_for<BM>([&](auto bi) {
+                    static_for<BN>([&](auto bj) {
+                        static_for<4>([&](auto g) { cw[bi][bj][g] = *eword(EI, bi, bj, g); });
+                    });
+                });
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the carries are in registers
+            }
+        }
+        if (sgi + 1 < P::nseg) issue_first(sgi + 1);
         if constexpr (DUMP) {
             int32_t *D = a.prods + ((int64_t)l * P::nseg + sgi) * planeC;
             static_for<BM>([&](auto bi) {
@@ -357,27 +396,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                 });
             }
         } else {
-            // The residue carried from one product to the next (mod(D) then mod(D + E) for
-            // Karatsuba, mod(RR) and mod(RI) for the expanded form) is parked in this
-            // thread's own E'_I words, which receive the final E'_I last; each lane
-            // re-reads only what it wrote, so no synchronisation is needed.
-            int8_t *ER = a.eprime + (int64_t)l * 2 * planeC;
-            int8_t *EI = ER + planeC;
-            constexpr bool karatsuba = KIND == KIND_KARATSUBA;
             static_for<BM>([&](auto bi) {
                 static_for<BN>([&](auto bj) {
                     static_for<4>([&](auto g) {
-                        const int64_t i = i0 + wm * WTM + bi * 32 + 8 * g + 4 * (lane >> 5);
-                        const int64_t j = j0 + wn * WTN + bj * 32 + (lane & 31);
-                        uint32_t *er = reinterpret_cast<uint32_t *>(ER + j * a.m_pad + i);
-                        uint32_t *ei = reinterpret_cast<uint32_t *>(EI + j * a.m_pad + i);
+                        uint32_t *er = eword(ER, bi, bj, g);
+                        uint32_t *ei = eword(EI, bi, bj, g);
                         int v[4], o[4];
                         static_for<4>([&](auto u) { v[u] = reduce_acc(acc[bi][bj][4 * (int)g + (int)u], mc); });
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
                             *ei = pack4(v);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
-                            const uint32_t w = *ei;
+                            const uint32_t w = cw[bi][bj][g];
                             static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) - v[u], mc); });
                             *er = pack4(o);
                             if constexpr (karatsuba) {
@@ -386,7 +416,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             }
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
-                            const uint32_t w = *ei;
+                            const uint32_t w = cw[bi][bj][g];
                             static_for<4>([&](auto u) {
                                 o[u] = reduce_acc(karatsuba ? v[u] - byte_of(w, u) : byte_of(w, u) + v[u], mc);
                             });
