@@ -115,18 +115,28 @@ __device__ __forceinline__ void map_tile(int64_t L, int64_t TR, int64_t TC, int6
 // WM x WN waves of BM x BN blocks; KS 64-byte k sub-slabs per pipeline stage.
 // k-slabs are copied global -> LDS by the load units directly (gfx950
 // global_load_lds_dwordx4) into a ring of NSTAGE buffers, NSTAGE - 1 slabs
-// ahead of the matrix cores.
-template <int WM_, int WN_, int BM_, int BN_, int KS_, int NSTAGE_>
+// ahead of the matrix cores.  REG_CARRY: the residue carried between the
+// products of a modulus stays in registers; otherwise it is parked in the
+// thread's own E'_I words (measured faster for the large tiles at 16384^3,
+// slower for the small tiles of short-k batches).
+template <int WM_, int WN_, int BM_, int BN_, int KS_, int NSTAGE_, bool REG_CARRY_>
 struct TileCfg {
     static constexpr int WM = WM_, WN = WN_, BM = BM_, BN = BN_, KS = KS_;
     static constexpr int NSTAGE = NSTAGE_;
+    static constexpr bool REG_CARRY = REG_CARRY_;
     static constexpr int TM = WM * BM * 32, TN = WN * BN * 32;
     static constexpr int THREADS = 64 * WM * WN;
     static constexpr int STAGE = (TM + TN) * 4;   // uint4 per sub-slab in LDS
     static constexpr int KSTEP = BK * KS;
 };
-using CfgLarge = TileCfg<2, 4, 4, 2, 1, 4>;  // 256 x 256 output tiles, 512 threads, 128 KB LDS
-using CfgSmall = TileCfg<2, 2, 2, 2, 1, 4>;  // 128 x 128, 256 threads, 64 KB LDS
+using CfgLarge = TileCfg<2, 4, 4, 2, 1, 4, false>;  // 256 x 256 output tiles, 512 threads, 128 KB LDS
+using CfgSmall = TileCfg<2, 2, 2, 2, 1, 4, true>;   // 128 x 128, 256 threads, 64 KB LDS
+// Batched problems have short k (many products per tile and little work each): both tile
+// sizes keep the carry in registers there.
+using CfgLargeBatch = TileCfg<2, 4, 4, 2, 1, 4, true>;
+static_assert(CfgLargeBatch::TM == CfgLarge::TM && CfgLargeBatch::TN == CfgLarge::TN &&
+                  CfgLargeBatch::KSTEP == CfgLarge::KSTEP,
+              "batched and single large tiles share the operand padding");
 
 // One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS:
 // lane i reads sbase + voff_i + OFF and writes lds_base + OFF + 16 i (the
@@ -233,6 +243,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
     };
 
     v16i acc[BM][BN];
+    uint32_t cw[BM][BN][4];  // packed carry residues (kept here, or reloaded from E'_I)
     issue_first(0);
 
 #pragma unroll 1
@@ -336,11 +347,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
         // ------------------------------------------------ per-product epilogue
         // (compile-time loops only: the accumulators must stay in registers)
         // The residue carried from one product to the next (mod(D) then mod(D + E) for
-        // Karatsuba, mod(RR) and mod(RI) for the expanded form) is parked in this
-        // thread's own E'_I words, which receive the final E'_I last; each lane
-        // re-reads only what it wrote, so no synchronisation is needed.  The carries are
-        // loaded and awaited first; then the next product's first stages are queued, so
-        // that their copies overlap the rest of this epilogue.
+        // Karatsuba, mod(RR) and mod(RI) for the expanded form) stays in registers, or
+        // is parked in this thread's own E'_I words, which receive the final E'_I last
+        // (each lane re-reads only what it wrote, so no synchronisation is needed).
+        // Parked carries are loaded and awaited first; then the next product's first
+        // stages are queued, so that their copies overlap the rest of this epilogue.
         constexpr bool karatsuba = KIND == KIND_KARATSUBA;
         auto eword = [&](int8_t *E, int bi, int bj, int g) {
             const int64_t i = i0 + wm * WTM + bi * 32 + 8 * g + 4 * (lane >> 5);
@@ -348,11 +359,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
             return reinterpret_cast<uint32_t *>(E + j * a.m_pad + i);
         };
         int8_t *ER = nullptr, *EI = nullptr;
-        uint32_t cw[BM][BN][4];
         if constexpr (!bound) {
             ER = a.eprime + (int64_t)l * 2 * planeC;
             EI = ER + planeC;
-            if (sgi >= 1 && (karatsuba || sgi != 2)) {
+            if (!C::REG_CARRY && sgi >= 1 && (karatsuba || sgi != 2)) {
                 static_for<BM>([&](auto bi) {
                     static_for<BN>([&](auto bj) {
                         static_for<4>([&](auto g) { cw[bi][bj][g] = *eword(EI, bi, bj, g); });
@@ -404,7 +414,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                         int v[4], o[4];
                         static_for<4>([&](auto u) { v[u] = reduce_acc(acc[bi][bj][4 * (int)g + (int)u], mc); });
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
-                            *ei = pack4(v);
+                            if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(v);
+                            else *ei = pack4(v);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
                             const uint32_t w = cw[bi][bj][g];
@@ -412,7 +423,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             *er = pack4(o);
                             if constexpr (karatsuba) {
                                 static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) + v[u], mc); });
-                                *ei = pack4(o);
+                                if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
+                                else *ei = pack4(o);
                             }
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
@@ -535,7 +547,7 @@ hipError_t launch_bound_gemm(const BoundArgs &b, hipStream_t s) {
 }
 
 int batch_gemm_blocks_per_cu(int tile) {
-    return tile == 256 ? blocks_per_cu<KIND_KARATSUBA, CfgLarge>() : blocks_per_cu<KIND_KARATSUBA, CfgSmall>();
+    return tile == 256 ? blocks_per_cu<KIND_KARATSUBA, CfgLargeBatch>() : blocks_per_cu<KIND_KARATSUBA, CfgSmall>();
 }
 
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile, int group,
@@ -552,8 +564,8 @@ hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, i
     }
     if ((int64_t)grid_blocks > items) grid_blocks = (int)items;
     if (tile == 256) {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLarge>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgLarge>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeBatch>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgLargeBatch>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
     } else {
         if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
         else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
