@@ -28,14 +28,22 @@ struct Problem {
 }  // namespace
 
 struct BatchPlan {
+    // A launch over a contiguous range of descriptors; param = chunk bits (split) or limbs (CRT).
+    struct Range {
+        int first, count;
+        int64_t blocks;
+        int param;
+    };
     std::vector<uint64_t> key;
     bool single = false;
-    int nmod = 0, algo = 0, planes = 0, abits = 0, nlimbs = 1, group = 1;
+    int algo = 0, planes = 0, group = 1, nmax = 0;
     size_t ws_bytes = 0;
-    std::vector<BatchOperand> ops;
-    std::vector<BatchGemm> gm[2];  // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
-    std::vector<BatchCrt> crt;
-    int64_t blk_scan = 0, blk_exp = 0, blk_split = 0, items[2] = {0, 0}, crt_blocks = 0;
+    std::vector<BatchOperand> ops;  // ordered by split launch
+    std::vector<Range> splits;      // one split launch per chunk count
+    std::vector<BatchGemm> gm[2];   // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
+    std::vector<BatchCrt> crt;      // ordered by CRT launch
+    std::vector<Range> crts;        // one CRT launch per limb count
+    int64_t blk_scan = 0, blk_exp = 0, items[2] = {0, 0};
     size_t stats_off = 0, stats_words = 0, counter_off = 0;
     std::vector<Problem> degenerate;  // k == 0 or alpha == 0: C = beta C
     char *desc = nullptr;             // device copy of ops, gm[0], gm[1], crt
@@ -125,17 +133,17 @@ bool is_degenerate(const Problem &q) {
 }
 
 std::vector<uint64_t> make_key(const ozc_context *h, bool single, const ozc_batch_policy_t &pol,
-                               const std::vector<Problem> &probs) {
+                               const std::vector<Problem> &probs, const std::vector<int> &Ns) {
     std::vector<uint64_t> key;
     key.reserve(8 + probs.size() * 16);
     key.push_back(single);
-    key.push_back((uint64_t)h->nmod);
     key.push_back((uint64_t)h->algo);
     key.push_back((uint64_t)pol.tile_threshold);
     key.push_back((uint64_t)pol.moduli_group);
     key.push_back((uint64_t)pol.use_graph);
     key.push_back(probs.size());
-    for (const Problem &q : probs) {
+    for (size_t p = 0; p < probs.size(); ++p) {
+        const Problem &q = probs[p];
         uint64_t w[16];
         w[0] = (uint64_t)q.ta | ((uint64_t)q.tb << 8);
         w[1] = (uint64_t)q.m;
@@ -149,34 +157,31 @@ std::vector<uint64_t> make_key(const ozc_context *h, bool single, const ozc_batc
         w[9] = (uint64_t)(uintptr_t)q.C;
         memcpy(&w[10], q.alpha, 16);
         memcpy(&w[12], q.beta, 16);
-        w[14] = w[15] = 0;
+        w[14] = (uint64_t)Ns[p];
+        w[15] = 0;
         key.insert(key.end(), w, w + 16);
     }
     return key;
 }
 
-// Padding, workspace layout and descriptors of a batch (host side only).
+// Padding, workspace layout and descriptors of a batch (host side only); problem p
+// runs with Ns[p] moduli.
 ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_policy_t &pol,
-                        const std::vector<Problem> &probs, BatchPlan &P) {
+                        const std::vector<Problem> &probs, const std::vector<int> &Ns,
+                        BatchPlan &P) {
     P.single = single;
-    P.nmod = h->nmod;
     P.algo = h->algo == OZC_ALGO_KARATSUBA ? 0 : 1;
     P.planes = P.algo == 0 ? 3 : 2;
-    P.group = std::max(1, std::min(pol.moduli_group, h->nmod));
-    const NTable &th = h->tab_host[(size_t)h->nmod - 1];
-    P.nlimbs = th.nlimbs;
-    P.abits = th.max_abits_fast;
-    if (P.abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
+    P.group = std::max(1, pol.moduli_group);
     const int nprod = P.algo == 0 ? 3 : 4;
 
     struct Pad {
-        int tile;
+        int tile, nmod, nf, nlimbs;
         int64_t m_pad, n_pad, k_pad;
         size_t sA, sB, muA, muB, resA, resB, ep;
         size_t p;  // index into probs
     };
     std::vector<Pad> pads;
-    const size_t N = (size_t)P.nmod;
     size_t stats_words = 0, mu_bytes = 0, res_bytes = 0, ep_bytes = 0;
     for (size_t p = 0; p < probs.size(); ++p) {
         const Problem &q = probs[p];
@@ -185,8 +190,15 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
             P.degenerate.push_back(q);
             continue;
         }
+        const int N = Ns[p];
+        if (N < OZC_MIN_MODULI || N > OZC_MAX_MODULI) return OZC_STATUS_INVALID_VALUE;
+        const NTable &th = h->tab_host[(size_t)N - 1];
+        if (th.max_abits_fast > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
         Pad d{};
         d.p = p;
+        d.nmod = N;
+        d.nf = split_fchunks(th.max_abits_fast);
+        d.nlimbs = th.nlimbs;
         d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
         d.m_pad = round_up(q.m, gemm_tile_rows(d.tile));
         d.n_pad = round_up(q.n, gemm_tile_cols(d.tile));
@@ -200,13 +212,14 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         d.muB = mu_bytes;
         mu_bytes = align_up(mu_bytes + 2 * (size_t)d.n_pad);
         d.resA = res_bytes;
-        res_bytes = align_up(res_bytes + N * P.planes * (size_t)d.m_pad * d.k_pad);
+        res_bytes = align_up(res_bytes + (size_t)N * P.planes * (size_t)d.m_pad * d.k_pad);
         d.resB = res_bytes;
-        res_bytes = align_up(res_bytes + N * P.planes * (size_t)d.n_pad * d.k_pad);
+        res_bytes = align_up(res_bytes + (size_t)N * P.planes * (size_t)d.n_pad * d.k_pad);
         d.ep = ep_bytes;
-        ep_bytes = align_up(ep_bytes + N * 2 * (size_t)d.m_pad * d.n_pad);
+        ep_bytes = align_up(ep_bytes + (size_t)N * 2 * (size_t)d.m_pad * d.n_pad);
         pads.push_back(d);
-        P.int8_ops += 2.0 * nprod * (double)P.nmod * (double)q.m * (double)q.n * (double)q.k;
+        P.nmax = std::max(P.nmax, N);
+        P.int8_ops += 2.0 * nprod * (double)N * (double)q.m * (double)q.n * (double)q.k;
         P.sum_m += q.m;
         P.sum_n += q.n;
         P.sum_k += q.k;
@@ -225,13 +238,23 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     off = align_up(off + ep_bytes);
     P.ws_bytes = off;
 
-    // Descriptors hold offsets from the workspace base until bind() adds it.
+    // Descriptors hold offsets from the workspace base (and no tables) until bind().
     P.ops.clear();
     P.crt.clear();
+    P.splits.clear();
+    P.crts.clear();
     P.gm[0].clear();
     P.gm[1].clear();
-    for (const Pad &d : pads) {
+    // operands ordered by chunk count: one split launch per count
+    std::vector<const Pad *> by_nf;
+    for (const Pad &d : pads) by_nf.push_back(&d);
+    std::stable_sort(by_nf.begin(), by_nf.end(), [](const Pad *x, const Pad *y) { return x->nf < y->nf; });
+    for (const Pad *dp : by_nf) {
+        const Pad &d = *dp;
         const Problem &q = probs[d.p];
+        if (P.splits.empty() || P.splits.back().param != d.nf * kFChunkBits)
+            P.splits.push_back({(int)P.ops.size(), 0, 0, d.nf * kFChunkBits});
+        BatchPlan::Range &sr = P.splits.back();
         BatchOperand a{}, b{};
         a.v = view_A(q.A, q.ta, q.m, q.k, q.lda);
         b.v = view_B(q.B, q.tb, q.n, q.k, q.ldb);
@@ -246,36 +269,17 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         a.rows_pad = d.m_pad;
         b.rows_pad = d.n_pad;
         a.k_pad = b.k_pad = d.k_pad;
+        a.nmod = b.nmod = d.nmod;
         for (BatchOperand *o : {&a, &b}) {
             o->blk_scan = P.blk_scan;
             P.blk_scan += batch_scan_blocks(o->v);
             o->blk_exp = P.blk_exp;
             P.blk_exp += batch_exp_blocks(o->rows_pad);
-            o->blk_split = P.blk_split;
-            P.blk_split += batch_split_blocks(o->rows_pad, o->k_pad);
+            o->blk_split = sr.blocks;
+            sr.blocks += batch_split_blocks(o->rows_pad, o->k_pad);
+            ++sr.count;
             P.ops.push_back(*o);
         }
-        BatchCrt c{};
-        c.a.eprime = (const int8_t *)(uintptr_t)(ep_off + d.ep);
-        c.a.m = q.m;
-        c.a.n = q.n;
-        c.a.m_pad = d.m_pad;
-        c.a.n_pad = d.n_pad;
-        c.a.nmod = P.nmod;
-        c.a.nlimbs = P.nlimbs;
-        c.a.tab = nullptr;  // bound later
-        c.a.mu = a.mu;
-        c.a.nu = b.mu;
-        c.a.alpha_r = q.alpha[0];
-        c.a.alpha_i = q.alpha[1];
-        c.a.beta_r = q.beta[0];
-        c.a.beta_i = q.beta[1];
-        c.a.C = q.C;
-        c.a.ldc = q.ldc;
-        c.a.single = single;
-        c.blk0 = P.crt_blocks;
-        P.crt_blocks += batch_crt_blocks(d.m_pad, q.n);
-        P.crt.push_back(c);
         BatchGemm g{};
         g.A = a.res;
         g.B = b.res;
@@ -285,47 +289,82 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         g.k_pad = d.k_pad;
         g.TR = (int32_t)(d.m_pad / gemm_tile_rows(d.tile));
         g.TC = (int32_t)(d.n_pad / gemm_tile_cols(d.tile));
+        g.nmod = d.nmod;
         P.gm[d.tile == 256 ? 0 : 1].push_back(g);
     }
+    // reconstruction ordered by limb count: one CRT launch per count
+    std::vector<const Pad *> by_limbs;
+    for (const Pad &d : pads) by_limbs.push_back(&d);
+    std::stable_sort(by_limbs.begin(), by_limbs.end(),
+                     [](const Pad *x, const Pad *y) { return x->nlimbs < y->nlimbs; });
+    for (const Pad *dp : by_limbs) {
+        const Pad &d = *dp;
+        const Problem &q = probs[d.p];
+        if (P.crts.empty() || P.crts.back().param != d.nlimbs)
+            P.crts.push_back({(int)P.crt.size(), 0, 0, d.nlimbs});
+        BatchPlan::Range &cr = P.crts.back();
+        BatchCrt c{};
+        c.a.eprime = (const int8_t *)(uintptr_t)(ep_off + d.ep);
+        c.a.m = q.m;
+        c.a.n = q.n;
+        c.a.m_pad = d.m_pad;
+        c.a.n_pad = d.n_pad;
+        c.a.nmod = d.nmod;
+        c.a.nlimbs = d.nlimbs;
+        c.a.tab = nullptr;  // bound later
+        c.a.mu = (const int16_t *)(uintptr_t)(mu_off + d.muA);
+        c.a.nu = (const int16_t *)(uintptr_t)(mu_off + d.muB);
+        c.a.alpha_r = q.alpha[0];
+        c.a.alpha_i = q.alpha[1];
+        c.a.beta_r = q.beta[0];
+        c.a.beta_i = q.beta[1];
+        c.a.C = q.C;
+        c.a.ldc = q.ldc;
+        c.a.single = single;
+        c.blk0 = cr.blocks;
+        cr.blocks += batch_crt_blocks(d.m_pad, q.n);
+        ++cr.count;
+        P.crt.push_back(c);
+    }
     // largest k first, so that the long items start early and the short ones fill the tail
-    const int ngroups = (P.nmod + P.group - 1) / P.group;
     for (int t = 0; t < 2; ++t) {
         std::stable_sort(P.gm[t].begin(), P.gm[t].end(),
                          [](const BatchGemm &x, const BatchGemm &y) { return x.k_pad > y.k_pad; });
         P.items[t] = 0;
         for (BatchGemm &g : P.gm[t]) {
             g.item0 = P.items[t];
-            P.items[t] += (int64_t)ngroups * g.TR * g.TC;
+            P.items[t] += (int64_t)((g.nmod + P.group - 1) / P.group) * g.TR * g.TC;
         }
     }
-    if (P.blk_scan >= ((int64_t)1 << 31) || P.blk_split >= ((int64_t)1 << 31) ||
-        P.crt_blocks >= ((int64_t)1 << 31) || P.items[0] >= ((int64_t)1 << 32) ||
-        P.items[1] >= ((int64_t)1 << 32))
-        return OZC_STATUS_NOT_SUPPORTED;
-    return OZC_STATUS_SUCCESS;
+    bool too_big = P.blk_scan >= ((int64_t)1 << 31) || P.items[0] >= ((int64_t)1 << 32) ||
+                   P.items[1] >= ((int64_t)1 << 32);
+    for (const BatchPlan::Range &r : P.splits) too_big = too_big || r.blocks >= ((int64_t)1 << 31);
+    for (const BatchPlan::Range &r : P.crts) too_big = too_big || r.blocks >= ((int64_t)1 << 31);
+    return too_big ? OZC_STATUS_NOT_SUPPORTED : OZC_STATUS_SUCCESS;
 }
 
 // Turn workspace offsets into addresses and copy the descriptors to the device.
 ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
     const uintptr_t base = (uintptr_t)ws;
-    const NTable *tab = h->tab_dev + (P.nmod - 1);
     for (BatchOperand &o : P.ops) {
         o.maxbits = (uint64_t *)(base + (uintptr_t)o.maxbits);
         o.sigma = (uint64_t *)(base + (uintptr_t)o.sigma);
         o.mu = (int16_t *)(base + (uintptr_t)o.mu);
         o.res = (int8_t *)(base + (uintptr_t)o.res);
+        o.tab = h->tab_dev + (o.nmod - 1);
     }
     for (int t = 0; t < 2; ++t)
         for (BatchGemm &g : P.gm[t]) {
             g.A = (const int8_t *)(base + (uintptr_t)g.A);
             g.B = (const int8_t *)(base + (uintptr_t)g.B);
             g.eprime = (int8_t *)(base + (uintptr_t)g.eprime);
+            g.tab = h->tab_dev + (g.nmod - 1);
         }
     for (BatchCrt &c : P.crt) {
         c.a.eprime = (const int8_t *)(base + (uintptr_t)c.a.eprime);
         c.a.mu = (const int16_t *)(base + (uintptr_t)c.a.mu);
         c.a.nu = (const int16_t *)(base + (uintptr_t)c.a.nu);
-        c.a.tab = tab;
+        c.a.tab = h->tab_dev + (c.a.nmod - 1);
     }
     const size_t b_ops = align_up(sizeof(BatchOperand) * P.ops.size());
     const size_t b_g0 = align_up(sizeof(BatchGemm) * P.gm[0].size());
@@ -385,7 +424,6 @@ enum { PH_PREP = 1, PH_GEMM = 2, PH_CRT = 4, PH_ALL = 7 };
 // The launch sequence of a bound plan (no host synchronisation, no memset nodes).
 ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, char *ws,
                           hipStream_t s, int phases, int group) {
-    const NTable *tab = h->tab_dev + (P.nmod - 1);
     uint32_t *counters = (uint32_t *)(ws + P.counter_off);
     const int nops = (int)P.ops.size();
     if (phases & PH_PREP) {
@@ -393,10 +431,10 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
         OZC_TRY(launch_fill_u64((uint64_t *)(ws + P.stats_off), (int64_t)P.stats_words, 0, s));
         OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, false, s));
         OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
-        OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, tab,
-                                            (uint32_t *)h->status_dev, s));
-        OZC_TRY(launch_batch_split(P.ops_dev, nops, P.blk_split, P.single, tab, P.nmod, P.planes,
-                                   P.abits, s));
+        OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
+        for (const BatchPlan::Range &r : P.splits)
+            OZC_TRY(launch_batch_split(P.ops_dev + r.first, r.count, r.blocks, P.single, P.planes,
+                                       r.param, s));
     }
     if (phases & PH_GEMM) {
         OZC_TRY(launch_fill_u32(counters, 2, 0, s));
@@ -404,11 +442,12 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
         for (int t = 0; t < 2; ++t) {
             if (P.items[t] == 0) continue;
             OZC_TRY(launch_batch_gemm(P.gm_dev[t], (int)P.gm[t].size(), P.items[t], tiles[t], group,
-                                      P.nmod, P.algo, tab, counters + t, bs->grid[t], s));
+                                      P.algo, counters + t, bs->grid[t], s));
         }
     }
     if (phases & PH_CRT) {
-        OZC_TRY(launch_batch_crt(P.crt_dev, (int)P.crt.size(), P.crt_blocks, P.nlimbs, P.single, s));
+        for (const BatchPlan::Range &r : P.crts)
+            OZC_TRY(launch_batch_crt(P.crt_dev + r.first, r.count, r.blocks, r.param, P.single, s));
         for (const Problem &q : P.degenerate)
             OZC_TRY(launch_scale_c(q.C, q.m, q.n, q.ldc, P.single, q.alpha[0], q.alpha[1], q.beta[0],
                                    q.beta[1], s));
@@ -431,11 +470,11 @@ ozc_status_t record_graph(ozc_context *h, BatchState *bs, BatchPlan &P) {
     return st;
 }
 
-// One batch with the handle's current N: plan lookup (or build and record), launch.
-ozc_status_t run_group(ozc_context *h, BatchState *bs, bool single,
-                       const std::vector<Problem> &probs) {
+// One batch, problem p with Ns[p] moduli: plan lookup (or build and record), launch.
+ozc_status_t run_plan(ozc_context *h, BatchState *bs, bool single,
+                      const std::vector<Problem> &probs, const std::vector<int> &Ns) {
     const ozc_batch_policy_t pol = bs->policy;
-    std::vector<uint64_t> key = make_key(h, single, pol, probs);
+    std::vector<uint64_t> key = make_key(h, single, pol, probs, Ns);
     BatchPlan *P = nullptr;
     for (size_t i = 0; i < bs->plans.size(); ++i)
         if (bs->plans[i]->key == key) {
@@ -447,7 +486,7 @@ ozc_status_t run_group(ozc_context *h, BatchState *bs, bool single,
     if (!P) {
         BatchPlan *Q = new (std::nothrow) BatchPlan();
         if (!Q) return OZC_STATUS_ALLOC_FAILED;
-        ozc_status_t st = plan_batch(h, single, pol, probs, *Q);
+        ozc_status_t st = plan_batch(h, single, pol, probs, Ns, *Q);
         if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, Q->ws_bytes);
         if (st == OZC_STATUS_SUCCESS) st = bind(h, *Q, bs->ws);
         if (st == OZC_STATUS_SUCCESS && pol.use_graph) st = record_graph(h, bs, *Q);
@@ -476,6 +515,7 @@ ozc_status_t run_group(ozc_context *h, BatchState *bs, bool single,
     h->last.k += P->sum_k;
     h->last.workspace = std::max(h->last.workspace, P->ws_bytes);
     h->last.int8_ops += P->int8_ops;
+    h->last.num_moduli = std::max(h->last.num_moduli, P->nmax);
     return OZC_STATUS_SUCCESS;
 }
 
@@ -500,11 +540,14 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
     if (probs.empty()) return OZC_STATUS_SUCCESS;
     st = grid_sizes(h, bs);
     if (st != OZC_STATUS_SUCCESS) return st;
-    if (!h->auto_n) return run_group(h, bs, single, probs);
+    std::vector<int> Ns(probs.size(), h->nmod);
+    if (!h->auto_n) return run_plan(h, bs, single, probs, Ns);
 
-    // Learned N per problem (complex64: the fixed count), then one batch per N.
-    std::vector<int> Ns(probs.size(), 9);
-    if (!single) {
+    // Learned N per problem (complex64: the fixed count), all in one batch.
+    h->last.num_moduli = 0;
+    if (single) {
+        std::fill(Ns.begin(), Ns.end(), 9);
+    } else {
         std::vector<OperandView> va, vb;
         std::vector<size_t> which;
         for (size_t p = 0; p < probs.size(); ++p) {
@@ -519,24 +562,7 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
         if (st != OZC_STATUS_SUCCESS) return st;
         for (size_t i = 0; i < which.size(); ++i) Ns[which[i]] = pred[i];
     }
-    struct RestoreN {
-        ozc_context *h;
-        int n0;
-        ~RestoreN() { h->nmod = n0; }
-    } restore{h, h->nmod};
-    int nmax = 0;
-    for (int N = OZC_MIN_MODULI; N <= OZC_MAX_MODULI; ++N) {
-        std::vector<Problem> group;
-        for (size_t p = 0; p < probs.size(); ++p)
-            if (Ns[p] == N) group.push_back(probs[p]);
-        if (group.empty()) continue;
-        h->nmod = N;
-        nmax = N;
-        st = run_group(h, bs, single, group);
-        if (st != OZC_STATUS_SUCCESS) return st;
-    }
-    h->last.num_moduli = nmax;  // the largest count used
-    return OZC_STATUS_SUCCESS;
+    return run_plan(h, bs, single, probs, Ns);  // num_moduli: the largest count used
 }
 
 // Median of the product phase over `reps` runs.
@@ -644,7 +670,7 @@ ozc_status_t ozc_batch_tune(ozc_handle_t h, int single, int count, const ozc_op_
         pol.tile_threshold = thr;
         pol.moduli_group = 1;
         BatchPlan P;
-        st = plan_batch(h, single != 0, pol, probs, P);
+        st = plan_batch(h, single != 0, pol, probs, std::vector<int>(probs.size(), h->nmod), P);
         if (st == OZC_STATUS_SUCCESS) st = ensure_batch_ws(h, bs, P.ws_bytes);
         if (st == OZC_STATUS_SUCCESS) st = bind(h, P, bs->ws);
         if (st == OZC_STATUS_SUCCESS) st = launch_batch(h, bs, P, bs->ws, h->stream, PH_PREP, 1);

@@ -464,8 +464,7 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
 // host (largest k first).
 template <int KIND, typename C>
 __global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm *probs, int nprob,
-                                                                int64_t items, int group, int nmod,
-                                                                const NTable *tab,
+                                                                int64_t items, int group,
                                                                 uint32_t *counter) {
     __shared__ int64_t item_s;
     for (;;) {
@@ -485,18 +484,18 @@ __global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm 
         const int lg = (int)(local / T);
         const int64_t t = local - (int64_t)lg * T;
         const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
-        GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, nmod, KIND == KIND_4M ? 1 : 0, tab,
+        GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, pb.nmod, KIND == KIND_4M ? 1 : 0, pb.tab,
                    pb.eprime, nullptr, C::TM};
-        const int l1 = min(nmod, (lg + 1) * group);
+        const int l1 = min(pb.nmod, (lg + 1) * group);
         for (int l = lg * group; l < l1; ++l) gemm_tile<KIND, C, false>(a, BoundArgs{}, l, ti, tj);
     }
 }
 
 template <int KIND, typename C>
-void launch_batch_kind(const BatchGemm *probs, int nprob, int64_t items, int group, int nmod,
-                       const NTable *tab, uint32_t *counter, int grid, hipStream_t s) {
+void launch_batch_kind(const BatchGemm *probs, int nprob, int64_t items, int group,
+                       uint32_t *counter, int grid, hipStream_t s) {
     hipLaunchKernelGGL((batch_gemm_kernel<KIND, C>), dim3((unsigned)grid), dim3(C::THREADS), 0, s,
-                       probs, nprob, items, group, nmod, tab, counter);
+                       probs, nprob, items, group, counter);
 }
 
 template <int KIND, typename C>
@@ -557,10 +556,9 @@ int batch_gemm_blocks_per_cu(int tile) {
 }
 
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile, int group,
-                             int nmod, int algo, const NTable *tab, uint32_t *counter,
-                             int grid_blocks, hipStream_t s) {
+                             int algo, uint32_t *counter, int grid_blocks, hipStream_t s) {
     if (items <= 0 || nprob <= 0) return hipSuccess;
-    if ((tile != 128 && tile != 256) || group < 1 || nmod < 1) return hipErrorInvalidValue;
+    if ((tile != 128 && tile != 256) || group < 1) return hipErrorInvalidValue;
     if (grid_blocks <= 0) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -570,11 +568,11 @@ hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, i
     }
     if ((int64_t)grid_blocks > items) grid_blocks = (int)items;
     if (tile == 256) {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeBatch>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgLargeBatch>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeBatch>(probs, nprob, items, group, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgLargeBatch>(probs, nprob, items, group, counter, grid_blocks, s);
     } else {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, nmod, tab, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);
     }
     return hipGetLastError();
 }

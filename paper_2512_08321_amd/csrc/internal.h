@@ -132,8 +132,11 @@ struct BatchOperand {       // op(A) rows or op(B) columns of one problem
     uint64_t *maxbits, *sigma;  // rows_pad entries each, zeroed before the scan
     int16_t *mu;                // rows_pad
     int8_t *res;                // residue planes, slab-major, rows_pad x k_pad each
+    const NTable *tab;          // constants of the problem's moduli count
     int64_t rows_pad, k_pad;
-    int64_t blk_scan, blk_exp, blk_split;  // first block in each phase's grid
+    int64_t blk_scan, blk_exp;  // first block in the scan and exponent grids
+    int64_t blk_split;          // first block in the grid of its split launch
+    int32_t nmod;               // the problem's moduli count
 };
 // Blocks an operand needs in each phase (the host builds the prefix sums with these).
 int64_t batch_scan_blocks(const OperandView &v);
@@ -142,25 +145,31 @@ int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad);
 hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
                              bool sigma, hipStream_t s);
 hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
-                                       const NTable *tab, uint32_t *status, hipStream_t s);
+                                       uint32_t *status, hipStream_t s);
+// 11-bit chunks that hold |a'| < 2^abits.
+inline int split_fchunks(int abits) {
+    return abits <= kFChunkBits ? 1 : (abits + kFChunkBits - 1) / kFChunkBits;
+}
+// abits: the largest bit length of |a'| among the operands (the chunk count of the launch).
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                              const NTable *tab, int nmod, int nplanes, int abits,
-                              hipStream_t s);
+                              int nplanes, int abits, hipStream_t s);
 
 struct BatchGemm {          // one problem of a batched product launch
     const int8_t *A, *B;
     int8_t *eprime;
+    const NTable *tab;      // constants of the problem's moduli count
     int64_t m_pad, n_pad, k_pad;
     int64_t item0;          // first work item; items run (modulus group, tile row, tile column)
     int32_t TR, TC;         // tiles per column and per row of the output
+    int32_t nmod;           // the problem's moduli count
 };
 // Persistent product kernel over a work queue of (problem, modulus group, tile)
 // items, handed out by an atomic counter that must be zero at launch.  `group`
 // moduli are computed one after another per item.  grid_blocks <= 0 picks one
 // wave of resident blocks.
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile,
-                             int group, int nmod, int algo, const NTable *tab, uint32_t *counter,
-                             int grid_blocks, hipStream_t s);
+                             int group, int algo, uint32_t *counter, int grid_blocks,
+                             hipStream_t s);
 // Resident blocks of the persistent product kernel per compute unit, for a tile edge.
 int batch_gemm_blocks_per_cu(int tile);
 

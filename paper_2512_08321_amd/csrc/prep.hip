@@ -502,28 +502,27 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const BatchOperand *ops
 }
 
 __global__ __launch_bounds__(256) void batch_fast_exponents_kernel(const BatchOperand *ops, int nops,
-                                                                   const NTable *tab,
                                                                    uint32_t *status) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_exp; });
     const BatchOperand &op = ops[o];
-    fast_exponents_body(op.maxbits, op.sigma, op.v.rows, op.rows_pad, tab, op.mu, status,
+    fast_exponents_body(op.maxbits, op.sigma, op.v.rows, op.rows_pad, op.tab, op.mu, status,
                         b - op.blk_exp);
 }
 
+// Operands of one launch may have different moduli counts; NF covers the largest |a'|.
 template <bool SINGLE, int NPLANES, int NF>
-__global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops,
-                                                          const NTable *__restrict__ tab, int nmod) {
+__global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_split; });
     const BatchOperand &op = ops[o];
     const int64_t lb = b - op.blk_split, gx = op.k_pad / kTileH;
     const int64_t bx = lb % gx, by = lb / gx;
     if (op.v.contig_h)
-        split_body<SINGLE, true, NPLANES, NF>(op.v, op.mu, tab, nmod, op.res, op.rows_pad, op.k_pad,
-                                              bx, by);
+        split_body<SINGLE, true, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
+                                              op.k_pad, bx, by);
     else
-        split_body<SINGLE, false, NPLANES, NF>(op.v, op.mu, tab, nmod, op.res, op.rows_pad,
+        split_body<SINGLE, false, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
                                                op.k_pad, bx, by);
 }
 
@@ -536,13 +535,12 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 
 template <bool SINGLE, int NPLANES>
-hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, const NTable *tab,
-                          int nmod, int nf, hipStream_t s) {
+hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, int nf, hipStream_t s) {
     dim3 grid((unsigned)blocks);
 #define OZC_BSPLIT_CASE(NF)                                                                  \
     case NF:                                                                                 \
         hipLaunchKernelGGL((batch_split_kernel<SINGLE, NPLANES, NF>), grid, dim3(256), 0, s, \
-                           ops, nops, tab, nmod);                                            \
+                           ops, nops);                                                       \
         break;
     switch (nf) {
         OZC_NF_CASES(OZC_BSPLIT_CASE)
@@ -572,8 +570,6 @@ hipError_t split_nf(const OperandView &v, const int16_t *mu, const NTable *tab, 
 }
 #undef OZC_NF_CASES
 
-// 11-bit chunks needed for |a'| < 2^abits.
-int fchunks(int abits) { return abits <= kFChunkBits ? 1 : (abits + kFChunkBits - 1) / kFChunkBits; }
 
 }  // namespace
 
@@ -644,7 +640,7 @@ hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int6
 hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
                         int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
                         int64_t k_pad, hipStream_t s) {
-    const int nf = fchunks(abits);
+    const int nf = split_fchunks(abits);
     if (rows_pad % kDirectRows || k_pad % kTileH || nf > kMaxFChunks) return hipErrorInvalidValue;
 #define OZC_SPLIT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
     if (single) {
@@ -698,23 +694,23 @@ hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, 
 }
 
 hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
-                                       const NTable *tab, uint32_t *status, hipStream_t s) {
+                                       uint32_t *status, hipStream_t s) {
     if (blocks <= 0 || nops <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_fast_exponents_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops,
-                       tab, status);
+                       status);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                              const NTable *tab, int nmod, int nplanes, int abits, hipStream_t s) {
+                              int nplanes, int abits, hipStream_t s) {
     if (blocks <= 0 || nops <= 0) return hipSuccess;
-    const int nf = fchunks(abits);
+    const int nf = split_fchunks(abits);
     if (nf > kMaxFChunks) return hipErrorInvalidValue;
     if (single)
-        return nplanes == 3 ? batch_split_nf<true, 3>(ops, nops, blocks, tab, nmod, nf, s)
-                            : batch_split_nf<true, 2>(ops, nops, blocks, tab, nmod, nf, s);
-    return nplanes == 3 ? batch_split_nf<false, 3>(ops, nops, blocks, tab, nmod, nf, s)
-                        : batch_split_nf<false, 2>(ops, nops, blocks, tab, nmod, nf, s);
+        return nplanes == 3 ? batch_split_nf<true, 3>(ops, nops, blocks, nf, s)
+                            : batch_split_nf<true, 2>(ops, nops, blocks, nf, s);
+    return nplanes == 3 ? batch_split_nf<false, 3>(ops, nops, blocks, nf, s)
+                        : batch_split_nf<false, 2>(ops, nops, blocks, nf, s);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
