@@ -293,8 +293,10 @@ def test_learned_moduli_batch_matches_single_calls(handle):
         Ns = [h2.predict_moduli(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["A"],
                                 d["lda"], d["B"], d["ldb"]) for d in dev]
         print(f"predicted N {Ns}", flush=True)
+        assert len(set(Ns)) >= 2  # one launch sequence serves several moduli counts
         h2.set_config(0, "fast", "karatsuba")
         h2.gemm_vbatched(dev)
+        assert h2.last_info()["num_moduli"] == max(Ns)
         got = _download(dev)
         ref_dev = _upload(probs)
         for d, N in zip(ref_dev, Ns):
@@ -303,7 +305,6 @@ def test_learned_moduli_batch_matches_single_calls(handle):
                      d["B"], d["ldb"], d["beta"], d["C"], d["ldc"])
         ref = _download(ref_dev)
         assert all(_same(a, b) for a, b in zip(got, ref))
-        assert h2.last_info()["num_moduli"] == Ns[-1]
         torch.cuda.synchronize()
     finally:
         h2.close()
