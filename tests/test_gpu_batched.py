@@ -281,11 +281,15 @@ def test_learned_moduli_batch_matches_single_calls(handle):
 
     h2 = ozc.Handle(0)
     try:
-        rng = np.random.default_rng(13)
-        p = rng.normal(0, 0.5, mlp.n_params()).astype(np.float32)
-        n = mlp.n_params()
-        p[n - 2 * mlp.F:n - mlp.F] = rng.normal(0, 3, mlp.F)
-        p[n - mlp.F:] = rng.uniform(0.5, 2.0, mlp.F)
+        # a network whose class is round(log2 k): problems with different k get different N
+        W1, W2, W3 = (np.zeros((mlp.H, mlp.F)), np.zeros((mlp.H, mlp.H)), np.zeros((mlp.C, mlp.H)))
+        W1[0, 2] = 1.0  # feature 2 is log2 k
+        W2[0, 0] = 1.0
+        c = np.arange(mlp.C, dtype=np.float64)
+        W3[:, 0] = 2.0 * c  # z_c = 2 c t - c^2 peaks at c = round(t)
+        p = np.concatenate([W1.ravel(), np.zeros(mlp.H), W2.ravel(), np.zeros(mlp.H), W3.ravel(),
+                            -c * c, np.zeros(mlp.F), np.ones(mlp.F)]).astype(np.float32)
+        assert p.size == mlp.n_params()
         h2.mlp_set_params(p)
         h2.set_batch_policy(1024, 1, True)
         probs = _make_batch(81, 12, 16, 300, phi_max=6.0)
