@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--verify", action="store_true",
                     help="enable the Freivalds check on every call (its cost shows in ms/step)")
     ap.add_argument("--workload", default="zgemm",
-                    choices=["zgemm", "batch", "batch-auto", "vendor-int8"],
+                    choices=["zgemm", "batch", "batch-auto", "vendor-int8", "vendor-complex"],
                     help="zgemm: one large product (default); batch: 512 uneven products; "
                          "batch-auto: the same with the learned moduli count; vendor-int8: the "
                          "vendor's INT8 GEMM (torch._int_mm) on size^3 int8 operands, for "
@@ -99,6 +99,8 @@ def main():
         return bench_batch(args)
     if args.workload == "batch-auto":
         return bench_batch_auto(args)
+    if args.workload == "vendor-complex":
+        return bench_vendor_complex(args)
     if args.workload == "vendor-int8":
         return bench_vendor_int8(args)
 
@@ -357,6 +359,41 @@ def bench_vendor_int8(args):
                       "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "int8", "data": "synthetic",
                       "config": {"workload": f"int8 GEMM {n}^3 (torch._int_mm)"}}), flush=True)
+
+
+def bench_vendor_complex(args):
+    """The vendor complex GEMM (torch.matmul on complex128, or complex64 with --single) on the
+    same m, n, k as the emulation benchmark, for comparison with the emulated rate."""
+    import torch
+
+    import workloads
+
+    torch.cuda.set_device(0)
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    dt = torch.complex64 if args.single else torch.complex128
+    A = workloads.complex_matrix_torch(m, k, args.phi, workloads.seed_for(2, 0, "A"), dtype=dt)
+    B = workloads.complex_matrix_torch(k, n, args.phi, workloads.seed_for(2, 0, "B"), dtype=dt)
+    At, Bt = A.t(), B.t()  # column-major m x k and k x n as torch views
+    for _ in range(args.warmup):
+        C = torch.matmul(At, Bt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C = torch.matmul(At, Bt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tflops = 8.0 * m * n * k / (ms * 1e-3) / 1e12
+    name = "CGEMM" if args.single else "ZGEMM"
+    log(f"[bench] vendor {name} {m}x{n}x{k}: {ms:.3f} ms, {tflops:.1f} TFLOPS")
+    del C
+    print(json.dumps({"metric": f"vendor {name} TFLOPS (8mnk/t)", "value": round(tflops, 3),
+                      "unit": "TFLOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "c64" if args.single else "c128",
+                      "data": "synthetic",
+                      "config": {"workload": f"{name} {m}x{n}x{k} (torch.matmul)"}}), flush=True)
 
 
 def uneven_batch(count, seed_base):
