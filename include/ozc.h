@@ -237,10 +237,12 @@ ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
  * own (kept until the handle is destroyed or a larger batch needs more).
  * With the learned moduli count configured (N = 0), one statistics pass over
  * all problems and one forward pass of the predictor choose N per problem (one
- * synchronisation), and the batch runs as one launch sequence per distinct N
- * (up to 8 recorded sequences are kept).  Fast mode only: NOT_SUPPORTED in
- * accurate mode.  Problems must not overlap in C.  Asynchronous on the handle's stream; non-finite inputs are
- * reported by ozc_last_info as for a single call. */
+ * synchronisation), and the batch runs as one launch sequence in which every
+ * problem uses its own N; ozc_last_info reports the largest.  Up to 8
+ * recorded sequences are kept.  Fast mode only: NOT_SUPPORTED in accurate
+ * mode.  Problems must not overlap in C.  Asynchronous on the handle's
+ * stream; non-finite inputs are reported by ozc_last_info as for a single
+ * call. */
 ozc_status_t ozc_zgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,
                                 const ozc_op_t *transb, const int64_t *m, const int64_t *n,
                                 const int64_t *k, const double *alpha, const void *const *A,
