@@ -119,9 +119,9 @@ __device__ __forceinline__ void map_tile(int64_t L, int64_t TR, int64_t TC, int6
 // products of a modulus stays in registers; otherwise it is parked in the
 // thread's own E'_I words.  PREFETCH: the next product's first stages are
 // queued before the current product's epilogue; otherwise each product
-// starts its own ring after the epilogue.  Both pay where k is short (many
-// products, little work each); for long k the plain schedule keeps the tiles
-// of an XCD in step (L2 hit rate 84% against 65% with both, same duration).
+// starts its own ring after the epilogue.  Both pay where k is short (4096^3:
+// 15% faster products); for long k the plain schedule keeps the tiles of an
+// XCD in step (16384^3: L2 hit rate 84% against 65%, 2.6% faster).
 template <int WM_, int WN_, int BM_, int BN_, int KS_, int NSTAGE_, bool REG_CARRY_, bool PREFETCH_>
 struct TileCfg {
     static constexpr int WM = WM_, WN = WN_, BM = BM_, BN = BN_, KS = KS_;
@@ -134,11 +134,12 @@ struct TileCfg {
 };
 using CfgLarge = TileCfg<2, 4, 4, 2, 1, 4, false, false>;  // 256 x 256 output tiles, 512 threads, 128 KB LDS
 using CfgSmall = TileCfg<2, 2, 2, 2, 1, 4, true, true>;    // 128 x 128, 256 threads, 64 KB LDS
-// Batched problems have short k: their 256 x 256 tiles use the short-k schedule too.
-using CfgLargeBatch = TileCfg<2, 4, 4, 2, 1, 4, true, true>;
-static_assert(CfgLargeBatch::TM == CfgLarge::TM && CfgLargeBatch::TN == CfgLarge::TN &&
-                  CfgLargeBatch::KSTEP == CfgLarge::KSTEP,
-              "batched and single large tiles share the operand padding");
+// 256 x 256 tiles with the short-k schedule: single calls with k_pad < kLongK and batches.
+using CfgLargeShortK = TileCfg<2, 4, 4, 2, 1, 4, true, true>;
+static_assert(CfgLargeShortK::TM == CfgLarge::TM && CfgLargeShortK::TN == CfgLarge::TN &&
+                  CfgLargeShortK::KSTEP == CfgLarge::KSTEP,
+              "both large-tile schedules share the operand padding");
+constexpr int64_t kLongK = 16384;  // measured: short-k faster up to 12288^3, plain at 16384^3
 
 // One wave copies 64 x 16 bytes from global memory straight into 1 KB of LDS:
 // lane i reads sbase + voff_i + OFF and writes lds_base + OFF + 16 i (the
@@ -531,8 +532,13 @@ hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s) {
     BoundArgs none{};
     const bool dump = a.prods != nullptr;
     if (tile == 256) {
-        if (a.algo == 0) launch_kind<KIND_KARATSUBA, CfgLarge>(a, none, dump, blocks, s);
-        else launch_kind<KIND_4M, CfgLarge>(a, none, dump, blocks, s);
+        if (a.k_pad >= kLongK) {
+            if (a.algo == 0) launch_kind<KIND_KARATSUBA, CfgLarge>(a, none, dump, blocks, s);
+            else launch_kind<KIND_4M, CfgLarge>(a, none, dump, blocks, s);
+        } else {
+            if (a.algo == 0) launch_kind<KIND_KARATSUBA, CfgLargeShortK>(a, none, dump, blocks, s);
+            else launch_kind<KIND_4M, CfgLargeShortK>(a, none, dump, blocks, s);
+        }
     } else {
         if (a.algo == 0) launch_kind<KIND_KARATSUBA, CfgSmall>(a, none, dump, blocks, s);
         else launch_kind<KIND_4M, CfgSmall>(a, none, dump, blocks, s);
@@ -552,7 +558,7 @@ hipError_t launch_bound_gemm(const BoundArgs &b, hipStream_t s) {
 }
 
 int batch_gemm_blocks_per_cu(int tile) {
-    return tile == 256 ? blocks_per_cu<KIND_KARATSUBA, CfgLargeBatch>() : blocks_per_cu<KIND_KARATSUBA, CfgSmall>();
+    return tile == 256 ? blocks_per_cu<KIND_KARATSUBA, CfgLargeShortK>() : blocks_per_cu<KIND_KARATSUBA, CfgSmall>();
 }
 
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile, int group,
@@ -568,8 +574,8 @@ hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, i
     }
     if ((int64_t)grid_blocks > items) grid_blocks = (int)items;
     if (tile == 256) {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeBatch>(probs, nprob, items, group, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgLargeBatch>(probs, nprob, items, group, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeShortK>(probs, nprob, items, group, counter, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgLargeShortK>(probs, nprob, items, group, counter, grid_blocks, s);
     } else {
         if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);
         else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);

@@ -264,3 +264,22 @@ def test_deterministic_and_row_major_api(handle):
     ref = (A.cpu() @ B.cpu())
     rel = ((c1.cpu() - ref).abs() / (A.cpu().abs() @ B.cpu().abs())).max().item()
     assert rel < 4 * 257 * 2.0 ** -53
+
+
+@pytest.mark.parametrize("algo", ["karatsuba", "4m"])
+def test_large_tiles_both_schedules_sampled(handle, orc, algo):
+    """256 x 256 product tiles with k below and at the long-k bound (16384): the two
+    product schedules.  Fast-mode exponents depend only on their own row or column, so
+    sampled rows and columns of the full GPU result are checked bit for bit against the
+    oracle run on those rows and columns alone (full k)."""
+    rng = np.random.default_rng(151)
+    for k in (8192, 16384):
+        m, n = 1030, 1100
+        print(f"large tiles {algo} k={k}", flush=True)
+        A = workloads.complex_matrix(m, k, 1.0, 152 + k)
+        B = workloads.complex_matrix(k, n, 1.0, 153 + k)
+        got = _gemm_call(handle, A, B, np.zeros((m, n)), 1.0, 0.0, 14, "fast", algo)
+        rows = np.unique(np.r_[0, m - 1, rng.choice(m, 10, replace=False)])
+        cols = np.unique(np.r_[0, n - 1, rng.choice(n, 10, replace=False)])
+        ref = orc.emulate(A[rows], B[:, cols], 14, "fast", algo)["out"]
+        assert _same(got[np.ix_(rows, cols)], ref)
