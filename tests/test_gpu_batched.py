@@ -271,6 +271,51 @@ def test_uneven_batch_full_sizes_against_single_calls(handle):
         assert torch.equal(torch.view_as_real(got[p]), torch.view_as_real(d["C"])), p
 
 
+def _log2k_predictor():
+    """Parameters of a network whose class is round(log2 k), so that problems with different
+    k get different moduli counts (N = 6 + class)."""
+    from oracle import mlp
+
+    W1, W2, W3 = (np.zeros((mlp.H, mlp.F)), np.zeros((mlp.H, mlp.H)), np.zeros((mlp.C, mlp.H)))
+    W1[0, 2] = 1.0  # feature 2 is log2 k
+    W2[0, 0] = 1.0
+    c = np.arange(mlp.C, dtype=np.float64)
+    W3[:, 0] = 2.0 * c  # z_c = 2 c t - c^2 peaks at c = round(t)
+    p = np.concatenate([W1.ravel(), np.zeros(mlp.H), W2.ravel(), np.zeros(mlp.H), W3.ravel(),
+                        -c * c, np.zeros(mlp.F), np.ones(mlp.F)]).astype(np.float32)
+    assert p.size == mlp.n_params()
+    return p
+
+
+def test_learned_moduli_batch_grouped_expanded(handle):
+    """Per-problem moduli counts with moduli groups of 4 and the expanded products: each
+    problem bit-identical to a single call at its own count."""
+    import paper_2512_08321_amd as ozc
+
+    h2 = ozc.Handle(0)
+    try:
+        h2.mlp_set_params(_log2k_predictor())
+        h2.set_batch_policy(256, 4, True)
+        probs = _make_batch(83, 10, 8, 700, phi_max=3.0)
+        dev = _upload(probs)
+        Ns = [h2.predict_moduli(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["A"],
+                                d["lda"], d["B"], d["ldb"]) for d in dev]
+        print(f"predicted N {Ns}", flush=True)
+        assert len(set(Ns)) >= 3
+        h2.set_config(0, "fast", "4m")
+        h2.gemm_vbatched(dev)
+        got = _download(dev)
+        ref_dev = _upload(probs)
+        for d, N in zip(ref_dev, Ns):
+            h2.set_config(N, "fast", "4m")
+            h2.zgemm(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["alpha"], d["A"], d["lda"],
+                     d["B"], d["ldb"], d["beta"], d["C"], d["ldc"])
+        ref = _download(ref_dev)
+        assert all(_same(a, b) for a, b in zip(got, ref))
+    finally:
+        h2.close()
+
+
 def test_learned_moduli_batch_matches_single_calls(handle):
     """N = 0 in a batch: each problem runs with its own predicted N, bit-identical to a
     single call at that N."""
@@ -281,16 +326,7 @@ def test_learned_moduli_batch_matches_single_calls(handle):
 
     h2 = ozc.Handle(0)
     try:
-        # a network whose class is round(log2 k): problems with different k get different N
-        W1, W2, W3 = (np.zeros((mlp.H, mlp.F)), np.zeros((mlp.H, mlp.H)), np.zeros((mlp.C, mlp.H)))
-        W1[0, 2] = 1.0  # feature 2 is log2 k
-        W2[0, 0] = 1.0
-        c = np.arange(mlp.C, dtype=np.float64)
-        W3[:, 0] = 2.0 * c  # z_c = 2 c t - c^2 peaks at c = round(t)
-        p = np.concatenate([W1.ravel(), np.zeros(mlp.H), W2.ravel(), np.zeros(mlp.H), W3.ravel(),
-                            -c * c, np.zeros(mlp.F), np.ones(mlp.F)]).astype(np.float32)
-        assert p.size == mlp.n_params()
-        h2.mlp_set_params(p)
+        h2.mlp_set_params(_log2k_predictor())
         h2.set_batch_policy(1024, 1, True)
         probs = _make_batch(81, 12, 16, 300, phi_max=6.0)
         dev = _upload(probs)
