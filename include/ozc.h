@@ -239,8 +239,10 @@ ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
  * all problems and one forward pass of the predictor choose N per problem (one
  * synchronisation), and the batch runs as one launch sequence in which every
  * problem uses its own N; ozc_last_info reports the largest.  Up to 8
- * recorded sequences are kept.  Fast mode only: NOT_SUPPORTED in accurate
- * mode.  Problems must not overlap in C.  Asynchronous on the handle's
+ * recorded sequences are kept.  Both scaling modes: in accurate mode the
+ * magnitudes and the bound products of all problems run as batched launches
+ * too (the bound products in a persistent kernel over their 128 x 128
+ * tiles).  Problems must not overlap in C.  Asynchronous on the handle's
  * stream; non-finite inputs are reported by ozc_last_info as for a single
  * call. */
 ozc_status_t ozc_zgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,

@@ -35,7 +35,7 @@ struct BatchPlan {
         int param;
     };
     std::vector<uint64_t> key;
-    bool single = false;
+    bool single = false, accurate = false;
     int algo = 0, planes = 0, group = 1, nmax = 0;
     size_t ws_bytes = 0;
     std::vector<BatchOperand> ops;  // ordered by split launch
@@ -43,13 +43,15 @@ struct BatchPlan {
     std::vector<BatchGemm> gm[2];   // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
     std::vector<BatchCrt> crt;      // ordered by CRT launch
     std::vector<Range> crts;        // one CRT launch per limb count
-    int64_t blk_scan = 0, blk_exp = 0, items[2] = {0, 0};
+    std::vector<BatchBound> bound;  // accurate mode: bound products
+    int64_t blk_scan = 0, blk_exp = 0, blk_ceil7 = 0, items[2] = {0, 0}, bound_items = 0;
     size_t stats_off = 0, stats_words = 0, counter_off = 0;
     std::vector<Problem> degenerate;  // k == 0 or alpha == 0: C = beta C
-    char *desc = nullptr;             // device copy of ops, gm[0], gm[1], crt
+    char *desc = nullptr;             // device copy of ops, gm[0], gm[1], crt, bound
     BatchOperand *ops_dev = nullptr;
     BatchGemm *gm_dev[2] = {nullptr, nullptr};
     BatchCrt *crt_dev = nullptr;
+    BatchBound *bound_dev = nullptr;
     hipGraphExec_t exec = nullptr;
     double int8_ops = 0.0;
     int64_t sum_m = 0, sum_n = 0, sum_k = 0;
@@ -138,6 +140,7 @@ std::vector<uint64_t> make_key(const ozc_context *h, bool single, const ozc_batc
     key.reserve(8 + probs.size() * 16);
     key.push_back(single);
     key.push_back((uint64_t)h->algo);
+    key.push_back((uint64_t)h->mode);
     key.push_back((uint64_t)pol.tile_threshold);
     key.push_back((uint64_t)pol.moduli_group);
     key.push_back((uint64_t)pol.use_graph);
@@ -170,6 +173,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
                         const std::vector<Problem> &probs, const std::vector<int> &Ns,
                         BatchPlan &P) {
     P.single = single;
+    P.accurate = h->mode == OZC_MODE_ACCURATE;
     P.algo = h->algo == OZC_ALGO_KARATSUBA ? 0 : 1;
     P.planes = P.algo == 0 ? 3 : 2;
     P.group = std::max(1, pol.moduli_group);
@@ -178,11 +182,11 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     struct Pad {
         int tile, nmod, nf, nlimbs;
         int64_t m_pad, n_pad, k_pad;
-        size_t sA, sB, muA, muB, resA, resB, ep;
+        size_t sA, sB, xA, xB, muA, muB, barA, barB, resA, resB, ep;
         size_t p;  // index into probs
     };
     std::vector<Pad> pads;
-    size_t stats_words = 0, mu_bytes = 0, res_bytes = 0, ep_bytes = 0;
+    size_t stats_words = 0, mu_bytes = 0, bar_bytes = 0, res_bytes = 0, ep_bytes = 0;
     for (size_t p = 0; p < probs.size(); ++p) {
         const Problem &q = probs[p];
         if (q.m == 0 || q.n == 0) continue;
@@ -193,11 +197,12 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         const int N = Ns[p];
         if (N < OZC_MIN_MODULI || N > OZC_MAX_MODULI) return OZC_STATUS_INVALID_VALUE;
         const NTable &th = h->tab_host[(size_t)N - 1];
-        if (th.max_abits_fast > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
+        const int abits = P.accurate ? th.max_abits_accu : th.max_abits_fast;
+        if (abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
         Pad d{};
         d.p = p;
         d.nmod = N;
-        d.nf = split_fchunks(th.max_abits_fast);
+        d.nf = split_fchunks(abits);
         d.nlimbs = th.nlimbs;
         d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
         d.m_pad = round_up(q.m, gemm_tile_rows(d.tile));
@@ -207,6 +212,16 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         stats_words += 2 * (size_t)d.m_pad;  // maxbits, sigma
         d.sB = stats_words;
         stats_words += 2 * (size_t)d.n_pad;
+        if (P.accurate) {  // bound maxima X, Y (int32), zeroed with the statistics
+            d.xA = stats_words;
+            stats_words += ((size_t)d.m_pad + 1) / 2;
+            d.xB = stats_words;
+            stats_words += ((size_t)d.n_pad + 1) / 2;
+            d.barA = bar_bytes;
+            bar_bytes = align_up(bar_bytes + 3 * (size_t)d.m_pad * d.k_pad);
+            d.barB = bar_bytes;
+            bar_bytes = align_up(bar_bytes + 3 * (size_t)d.n_pad * d.k_pad);
+        }
         d.muA = mu_bytes;
         mu_bytes = align_up(mu_bytes + 2 * (size_t)d.m_pad);
         d.muB = mu_bytes;
@@ -232,6 +247,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     off = align_up(off + 8 * stats_words);
     const size_t mu_off = off;
     off = align_up(off + mu_bytes);
+    const size_t bar_off = off;
+    off = align_up(off + bar_bytes);
     const size_t res_off = off;
     off = align_up(off + res_bytes);
     const size_t ep_off = off;
@@ -243,6 +260,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     P.crt.clear();
     P.splits.clear();
     P.crts.clear();
+    P.bound.clear();
     P.gm[0].clear();
     P.gm[1].clear();
     // operands ordered by chunk count: one split launch per count
@@ -270,7 +288,24 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         b.rows_pad = d.n_pad;
         a.k_pad = b.k_pad = d.k_pad;
         a.nmod = b.nmod = d.nmod;
+        if (P.accurate) {
+            a.X = (int32_t *)(uintptr_t)(P.stats_off + 8 * d.xA);
+            b.X = (int32_t *)(uintptr_t)(P.stats_off + 8 * d.xB);
+            a.bar = (int8_t *)(uintptr_t)(bar_off + d.barA);
+            b.bar = (int8_t *)(uintptr_t)(bar_off + d.barB);
+            BatchBound bb{};
+            bb.b = BoundArgs{a.bar, b.bar, d.m_pad, d.n_pad, d.k_pad, a.X, b.X, 128};
+            bb.item0 = P.bound_items;
+            bb.TR = (int32_t)(d.m_pad / 128);
+            bb.TC = (int32_t)(d.n_pad / 128);
+            P.bound_items += (int64_t)bb.TR * bb.TC;
+            P.bound.push_back(bb);
+        }
         for (BatchOperand *o : {&a, &b}) {
+            if (P.accurate) {
+                o->blk_ceil7 = P.blk_ceil7;
+                P.blk_ceil7 += batch_ceil7_blocks(o->rows_pad, o->k_pad);
+            }
             o->blk_scan = P.blk_scan;
             P.blk_scan += batch_scan_blocks(o->v);
             o->blk_exp = P.blk_exp;
@@ -337,7 +372,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         }
     }
     bool too_big = P.blk_scan >= ((int64_t)1 << 31) || P.items[0] >= ((int64_t)1 << 32) ||
-                   P.items[1] >= ((int64_t)1 << 32);
+                   P.items[1] >= ((int64_t)1 << 32) || P.blk_ceil7 >= ((int64_t)1 << 31) ||
+                   P.bound_items >= ((int64_t)1 << 32);
     for (const BatchPlan::Range &r : P.splits) too_big = too_big || r.blocks >= ((int64_t)1 << 31);
     for (const BatchPlan::Range &r : P.crts) too_big = too_big || r.blocks >= ((int64_t)1 << 31);
     return too_big ? OZC_STATUS_NOT_SUPPORTED : OZC_STATUS_SUCCESS;
@@ -352,6 +388,16 @@ ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
         o.mu = (int16_t *)(base + (uintptr_t)o.mu);
         o.res = (int8_t *)(base + (uintptr_t)o.res);
         o.tab = h->tab_dev + (o.nmod - 1);
+        if (P.accurate) {
+            o.X = (int32_t *)(base + (uintptr_t)o.X);
+            o.bar = (int8_t *)(base + (uintptr_t)o.bar);
+        }
+    }
+    for (BatchBound &bb : P.bound) {
+        bb.b.A = (const int8_t *)(base + (uintptr_t)bb.b.A);
+        bb.b.B = (const int8_t *)(base + (uintptr_t)bb.b.B);
+        bb.b.X = (int32_t *)(base + (uintptr_t)bb.b.X);
+        bb.b.Y = (int32_t *)(base + (uintptr_t)bb.b.Y);
     }
     for (int t = 0; t < 2; ++t)
         for (BatchGemm &g : P.gm[t]) {
@@ -370,13 +416,16 @@ ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
     const size_t b_g0 = align_up(sizeof(BatchGemm) * P.gm[0].size());
     const size_t b_g1 = align_up(sizeof(BatchGemm) * P.gm[1].size());
     const size_t b_crt = align_up(sizeof(BatchCrt) * P.crt.size());
-    const size_t total = b_ops + b_g0 + b_g1 + b_crt;
+    const size_t b_bound = align_up(sizeof(BatchBound) * P.bound.size());
+    const size_t total = b_ops + b_g0 + b_g1 + b_crt + b_bound;
     if (total == 0) return OZC_STATUS_SUCCESS;
     std::vector<char> host(total, 0);
     memcpy(host.data(), P.ops.data(), sizeof(BatchOperand) * P.ops.size());
     memcpy(host.data() + b_ops, P.gm[0].data(), sizeof(BatchGemm) * P.gm[0].size());
     memcpy(host.data() + b_ops + b_g0, P.gm[1].data(), sizeof(BatchGemm) * P.gm[1].size());
     memcpy(host.data() + b_ops + b_g0 + b_g1, P.crt.data(), sizeof(BatchCrt) * P.crt.size());
+    memcpy(host.data() + b_ops + b_g0 + b_g1 + b_crt, P.bound.data(),
+           sizeof(BatchBound) * P.bound.size());
     if (hipMalloc(&P.desc, total) != hipSuccess) {
         P.desc = nullptr;
         (void)hipGetLastError();
@@ -387,6 +436,7 @@ ozc_status_t bind(const ozc_context *h, BatchPlan &P, char *ws) {
     P.gm_dev[0] = (BatchGemm *)(P.desc + b_ops);
     P.gm_dev[1] = (BatchGemm *)(P.desc + b_ops + b_g0);
     P.crt_dev = (BatchCrt *)(P.desc + b_ops + b_g0 + b_g1);
+    P.bound_dev = (BatchBound *)(P.desc + b_ops + b_g0 + b_g1 + b_crt);
     return OZC_STATUS_SUCCESS;
 }
 
@@ -430,8 +480,15 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
         OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
         OZC_TRY(launch_fill_u64((uint64_t *)(ws + P.stats_off), (int64_t)P.stats_words, 0, s));
         OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, false, s));
-        OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
-        OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
+        if (P.accurate) {
+            OZC_TRY(launch_batch_ceil7(P.ops_dev, nops, P.blk_ceil7, P.single, s));
+            OZC_TRY(launch_fill_u32(counters + 2, 1, 0, s));
+            OZC_TRY(launch_batch_bound(P.bound_dev, (int)P.bound.size(), P.bound_items, counters + 2, s));
+            OZC_TRY(launch_batch_accu_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
+        } else {
+            OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
+            OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
+        }
         for (const BatchPlan::Range &r : P.splits)
             OZC_TRY(launch_batch_split(P.ops_dev + r.first, r.count, r.blocks, P.single, P.planes,
                                        r.param, s));
@@ -525,7 +582,6 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
                           const int64_t *lda, const void *const *B, const int64_t *ldb,
                           const double *beta, void *const *C, const int64_t *ldc) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
-    if (h->mode != OZC_MODE_FAST) return OZC_STATUS_NOT_SUPPORTED;
     std::vector<Problem> probs;
     ozc_status_t st = gather(count, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, true, probs);
     if (st != OZC_STATUS_SUCCESS) return st;
@@ -651,7 +707,6 @@ ozc_status_t ozc_batch_tune(ozc_handle_t h, int single, int count, const ozc_op_
                             const int64_t *k, const void *const *A, const int64_t *lda,
                             const void *const *B, const int64_t *ldb, ozc_batch_policy_t *chosen) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
-    if (h->mode != OZC_MODE_FAST) return OZC_STATUS_NOT_SUPPORTED;
     std::vector<Problem> probs;
     ozc_status_t st = gather(count, transa, transb, m, n, k, nullptr, A, lda, B, ldb, nullptr,
                              nullptr, nullptr, false, probs);

@@ -492,6 +492,30 @@ __global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm 
     }
 }
 
+// Persistent kernel over the tiles of a batch's bound products (accurate mode).
+template <typename C>
+__global__ __launch_bounds__(C::THREADS) void batch_bound_kernel(const BatchBound *probs, int nprob,
+                                                                int64_t items, uint32_t *counter) {
+    __shared__ int64_t item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t w = item_s;
+        __syncthreads();
+        if (w >= items) break;
+        int lo = 0, hi = nprob - 1;  // last problem whose first item is <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].item0 <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchBound &pb = probs[lo];
+        const int64_t t = w - pb.item0;
+        const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
+        gemm_tile<KIND_BOUND, C, false>(GemmArgs{}, pb.b, 0, ti, tj);
+    }
+}
+
 template <int KIND, typename C>
 void launch_batch_kind(const BatchGemm *probs, int nprob, int64_t items, int group,
                        uint32_t *counter, int grid, hipStream_t s) {
@@ -554,6 +578,24 @@ hipError_t launch_bound_gemm(const BoundArgs &b, hipStream_t s) {
     const int64_t blocks = (b.m_pad / tile) * (b.n_pad / tile);
     GemmArgs none{};
     launch_kind<KIND_BOUND, CfgSmall>(none, b, false, blocks, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bound(const BatchBound *probs, int nprob, int64_t items,
+                              uint32_t *counter, hipStream_t s) {
+    if (items <= 0 || nprob <= 0) return hipSuccess;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_bound_kernel<CfgSmall>,
+                                                     CfgSmall::THREADS, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t grid = (int64_t)cus * per_cu;
+    if (grid > items) grid = items;
+    hipLaunchKernelGGL((batch_bound_kernel<CfgSmall>), dim3((unsigned)grid), dim3(CfgSmall::THREADS), 0,
+                       s, probs, nprob, items, counter);
     return hipGetLastError();
 }
 

@@ -106,6 +106,15 @@ struct BoundArgs {
     int tile;
 };
 hipError_t launch_bound_gemm(const BoundArgs &a, hipStream_t s);
+// Batched bound products (accurate mode): a persistent kernel over the 128 x 128 tiles of
+// all problems, handed out by an atomic counter that must be zero at launch.
+struct BatchBound {
+    BoundArgs b;
+    int64_t item0;          // first work item (tile) of the problem
+    int32_t TR, TC;         // tiles per column and per row of the output
+};
+hipError_t launch_batch_bound(const BatchBound *probs, int nprob, int64_t items,
+                              uint32_t *counter, hipStream_t s);
 
 struct CrtArgs {
     const int8_t *eprime;  // [N][2][n_pad][m_pad]
@@ -133,8 +142,11 @@ struct BatchOperand {       // op(A) rows or op(B) columns of one problem
     int16_t *mu;                // rows_pad
     int8_t *res;                // residue planes, slab-major, rows_pad x k_pad each
     const NTable *tab;          // constants of the problem's moduli count
+    int8_t *bar;                // accurate mode: the 3 magnitude planes, slab-major
+    int32_t *X;                 // accurate mode: bound-product row maxima (rows_pad, zeroed)
     int64_t rows_pad, k_pad;
     int64_t blk_scan, blk_exp;  // first block in the scan and exponent grids
+    int64_t blk_ceil7;          // first block in the magnitude grid (accurate mode)
     int64_t blk_split;          // first block in the grid of its split launch
     int32_t nmod;               // the problem's moduli count
 };
@@ -145,6 +157,12 @@ int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad);
 hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
                              bool sigma, hipStream_t s);
 hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
+                                       uint32_t *status, hipStream_t s);
+// Accurate mode: magnitudes of every operand, then exponents from maxbits and X.
+int64_t batch_ceil7_blocks(int64_t rows_pad, int64_t k_pad);
+hipError_t launch_batch_ceil7(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                              hipStream_t s);
+hipError_t launch_batch_accu_exponents(const BatchOperand *ops, int nops, int64_t blocks,
                                        uint32_t *status, hipStream_t s);
 // 11-bit chunks that hold |a'| < 2^abits.
 inline int split_fchunks(int abits) {

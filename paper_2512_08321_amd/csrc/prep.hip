@@ -201,10 +201,11 @@ __device__ __forceinline__ void fast_exponents_body(const uint64_t *maxbits, con
     mu[r] = out;
 }
 
-__global__ void accu_exponents_kernel(const uint64_t *maxbits, const int32_t *X, int64_t rows,
-                                      int64_t rows_pad, const NTable *tab, int16_t *mu,
-                                      uint32_t *status) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void accu_exponents_body(const uint64_t *maxbits, const int32_t *X,
+                                                    int64_t rows, int64_t rows_pad,
+                                                    const NTable *tab, int16_t *mu,
+                                                    uint32_t *status, int64_t bx) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= rows_pad) return;
     int16_t out = kExpZero;
     if (r < rows) {
@@ -220,6 +221,13 @@ __global__ void accu_exponents_kernel(const uint64_t *maxbits, const int32_t *X,
         }
     }
     mu[r] = out;
+}
+
+__global__ __launch_bounds__(256) void accu_exponents_kernel(const uint64_t *maxbits,
+                                                             const int32_t *X, int64_t rows,
+                                                             int64_t rows_pad, const NTable *tab,
+                                                             int16_t *mu, uint32_t *status) {
+    accu_exponents_body(maxbits, X, rows, rows_pad, tab, mu, status, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- accurate-mode magnitudes
@@ -510,6 +518,26 @@ __global__ __launch_bounds__(256) void batch_fast_exponents_kernel(const BatchOp
                         b - op.blk_exp);
 }
 
+__global__ __launch_bounds__(256) void batch_accu_exponents_kernel(const BatchOperand *ops, int nops,
+                                                                   uint32_t *status) {
+    const int64_t b = blockIdx.x;
+    const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_exp; });
+    const BatchOperand &op = ops[o];
+    accu_exponents_body(op.maxbits, op.X, op.v.rows, op.rows_pad, op.tab, op.mu, status,
+                        b - op.blk_exp);
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void batch_ceil7_kernel(const BatchOperand *ops, int nops) {
+    const int64_t b = blockIdx.x;
+    const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_ceil7; });
+    const BatchOperand &op = ops[o];
+    const int64_t lb = b - op.blk_ceil7, gx = op.k_pad / kTileH;
+    const int64_t bx = lb % gx, by = lb / gx;
+    if (op.v.contig_h) ceil7_body<SINGLE, true>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
+    else ceil7_body<SINGLE, false>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
+}
+
 // Operands of one launch may have different moduli counts; NF covers the largest |a'|.
 template <bool SINGLE, int NPLANES, int NF>
 __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops) {
@@ -698,6 +726,26 @@ hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_
     if (blocks <= 0 || nops <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_fast_exponents_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops,
                        status);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_accu_exponents(const BatchOperand *ops, int nops, int64_t blocks,
+                                       uint32_t *status, hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_accu_exponents_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops,
+                       status);
+    return hipGetLastError();
+}
+
+int64_t batch_ceil7_blocks(int64_t rows_pad, int64_t k_pad) {
+    return (k_pad / kTileH) * (rows_pad / kTileR);
+}
+
+hipError_t launch_batch_ceil7(const BatchOperand *ops, int nops, int64_t blocks, bool single,
+                              hipStream_t s) {
+    if (blocks <= 0 || nops <= 0) return hipSuccess;
+    if (single) hipLaunchKernelGGL((batch_ceil7_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
+    else hipLaunchKernelGGL((batch_ceil7_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
     return hipGetLastError();
 }
 
