@@ -81,7 +81,10 @@ def main():
                          "batch-auto: the same with the learned moduli count; vendor-int8: the "
                          "vendor's INT8 GEMM (torch._int_mm) on size^3 int8 operands, for "
                          "comparison with one residue product")
-    ap.add_argument("--train-count", type=int, default=400, help="batch-auto: training instances")
+    ap.add_argument("--train-count", type=int, default=2000, help="batch-auto: training instances")
+    ap.add_argument("--margin", type=int, default=2,
+                    help="batch-auto: moduli added to each prediction (2 meets the target on "
+                         "every problem of the batch, as the fixed count does)")
     ap.add_argument("--target", type=float, default=1e-15, help="batch-auto: accuracy target")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--tune", action="store_true", help="batch: run the schedule autotuner first")
@@ -467,7 +470,7 @@ def bench_batch_auto(args):
     loop_ms = timed(loop, max(1, args.steps // 2), 1)
     fixed_batch_ms = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
     out_fixed = [q["C"].clone() for q in probs]
-    h.set_auto_moduli(fallback=n_fix, margin=1)
+    h.set_auto_moduli(fallback=n_fix, margin=args.margin)
     h.set_config(0, "fast", "karatsuba")
     auto_ms = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
     out_auto = [q["C"].clone() for q in probs]
