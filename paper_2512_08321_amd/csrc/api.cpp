@@ -140,6 +140,95 @@ ozc_status_t check_args(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t 
     return OZC_STATUS_SUCCESS;
 }
 
+size_t check_bytes(int64_t rows, int64_t inner, size_t scratch_bytes) {
+    const size_t vk = (size_t)(inner > 0 ? inner : 1), vm = (size_t)(rows > 0 ? rows : 1);
+    return 3 * align_up(40 * vk) + 9 * align_up(40 * vm) + align_up(scratch_bytes);
+}
+
+// Layout: y, yl, ya (inner); then z, zl, za, w, wl, wa, v, vl, va (rows); then scratch.
+// The high and low parts are double2 vectors, the absolute sums doubles.
+CheckBufs carve_check(char *base, int64_t rows, int64_t inner) {
+    const size_t vk = (size_t)(inner > 0 ? inner : 1), vm = (size_t)(rows > 0 ? rows : 1);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *p = base + off;
+        off += align_up(b);
+        return p;
+    };
+    CheckBufs c{};
+    c.y = (double2 *)take(16 * vk);
+    c.yl = (double2 *)take(16 * vk);
+    c.ya = (double *)take(8 * vk);
+    c.z = (double2 *)take(16 * vm);
+    c.zl = (double2 *)take(16 * vm);
+    c.za = (double *)take(8 * vm);
+    c.w = (double2 *)take(16 * vm);
+    c.wl = (double2 *)take(16 * vm);
+    c.wa = (double *)take(8 * vm);
+    c.v = (double2 *)take(16 * vm);
+    c.vl = (double2 *)take(16 * vm);
+    c.va = (double *)take(8 * vm);
+    c.scratch = base + off;
+    return c;
+}
+
+size_t check_scratch_bytes(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k) {
+    size_t scr = gemv_scratch_bytes(m, n);
+    if (ta == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(m, k));
+    if (tb == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(k, n));
+    return scr;
+}
+
+ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                           int64_t n, int64_t k, const double alpha[2], const void *A,
+                           int64_t lda, const void *B, int64_t ldb, const double beta[2],
+                           const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
+                           const CheckBufs &b, unsigned long long *word, hipStream_t s) {
+    const uint64_t seed = h->verify_seed;
+    const double rel = h->verify_rel > 0.0 ? h->verify_rel
+                                            : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
+    // rounding of the double-double evaluation itself
+    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-104;
+    const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
+    // v = C_in x (m), y = op(B) x (k), z = op(A) y (m), w = C x (m)
+    if (!beta_zero)
+        OZC_TRY(launch_gemv(cin, single, 0, m, n, ld_cin, nullptr, nullptr, nullptr, seed, b.v, b.vl,
+                            b.va, b.scratch, s));
+    if (tb == OZC_OP_N)
+        OZC_TRY(launch_gemv(B, single, 0, k, n, ldb, nullptr, nullptr, nullptr, seed, b.y, b.yl, b.ya,
+                            b.scratch, s));
+    else
+        OZC_TRY(launch_gemv(B, single, (int)tb, n, k, ldb, nullptr, nullptr, nullptr, seed, b.y, b.yl,
+                            b.ya, b.scratch, s));
+    if (ta == OZC_OP_N)
+        OZC_TRY(launch_gemv(A, single, 0, m, k, lda, b.y, b.yl, b.ya, 0, b.z, b.zl, b.za, b.scratch, s));
+    else
+        OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, b.y, b.yl, b.ya, 0, b.z, b.zl, b.za,
+                            b.scratch, s));
+    OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, b.w, b.wl, b.wa,
+                        b.scratch, s));
+    OZC_TRY(launch_freivalds_rows(b.w, b.wl, b.wa, b.z, b.zl, b.za, beta_zero ? nullptr : b.v, b.vl,
+                                  b.va, m, alpha, beta, rel, gam, word, s));
+    return OZC_STATUS_SUCCESS;
+}
+
+
+ozc_status_t ensure_vws(ozc_context *h, size_t bytes) {
+    if (bytes <= h->vws_bytes) return OZC_STATUS_SUCCESS;
+    if (h->vws) {
+        OZC_TRY(hipStreamSynchronize(h->stream));
+        OZC_TRY(hipFree(h->vws));
+        h->vws = nullptr;
+        h->vws_bytes = 0;
+    }
+    if (hipMalloc(&h->vws, bytes) != hipSuccess) {
+        h->vws = nullptr;
+        (void)hipGetLastError();
+        return OZC_STATUS_ALLOC_FAILED;
+    }
+    h->vws_bytes = bytes;
+    return OZC_STATUS_SUCCESS;
+}
 }  // namespace ozc
 
 namespace {
@@ -354,22 +443,6 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     return OZC_STATUS_SUCCESS;
 }
 
-ozc_status_t ensure_vws(ozc_context *h, size_t bytes) {
-    if (bytes <= h->vws_bytes) return OZC_STATUS_SUCCESS;
-    if (h->vws) {
-        OZC_TRY(hipStreamSynchronize(h->stream));
-        OZC_TRY(hipFree(h->vws));
-        h->vws = nullptr;
-        h->vws_bytes = 0;
-    }
-    if (hipMalloc(&h->vws, bytes) != hipSuccess) {
-        h->vws = nullptr;
-        (void)hipGetLastError();
-        return OZC_STATUS_ALLOC_FAILED;
-    }
-    h->vws_bytes = bytes;
-    return OZC_STATUS_SUCCESS;
-}
 
 // One call with the Freivalds check and moduli escalation (see ozc_set_verify).
 ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
@@ -403,47 +476,19 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
     OZC_TRY(hipSetDevice(h->device));
     const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
     const size_t es = single ? 8 : 16;
-    // vectors: y (k), z, w, v (m) as double2 + abs; scratch for partial sums; saved C_in
-    const int64_t vk = k > 0 ? k : 1, vm = m;
-    size_t off = 0;
-    auto take = [&](size_t b) {
-        size_t o = off;
-        off = align_up(off + b);
-        return o;
-    };
-    // double-double vectors: high parts, low parts, absolute sums
-    const size_t o_y = take(16 * vk), o_yl = take(16 * vk), o_ya = take(8 * vk);
-    const size_t o_z = take(16 * vm), o_zl = take(16 * vm), o_za = take(8 * vm);
-    const size_t o_w = take(16 * vm), o_wl = take(16 * vm), o_wa = take(8 * vm);
-    const size_t o_v = take(16 * vm), o_vl = take(16 * vm), o_va = take(8 * vm);
-    size_t scr = gemv_scratch_bytes(m, n);
-    if (ta == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(m, k));
-    if (tb == OZC_OP_N) scr = std::max(scr, gemv_scratch_bytes(k, n));
-    const size_t o_scr = take(scr);
-    const size_t o_word = take(16);
-    const size_t o_cin = take(beta_zero ? 0 : es * (size_t)m * (size_t)n);
-    st = ensure_vws(h, off);
+    // check vectors, the result word and (beta != 0) a copy of C_in for the check and reruns
+    const size_t cb = check_bytes(m, k, check_scratch_bytes(ta, tb, m, n, k));
+    const size_t o_word = cb;
+    const size_t o_cin = align_up(o_word + 16);
+    const size_t total = o_cin + (beta_zero ? 0 : es * (size_t)m * (size_t)n);
+    st = ensure_vws(h, total);
     if (st != OZC_STATUS_SUCCESS) return st;
     char *vw = (char *)h->vws;
-    double2 *y = (double2 *)(vw + o_y), *z = (double2 *)(vw + o_z), *w = (double2 *)(vw + o_w),
-            *v = (double2 *)(vw + o_v);
-    double2 *yl = (double2 *)(vw + o_yl), *zl = (double2 *)(vw + o_zl),
-            *wl = (double2 *)(vw + o_wl), *vl = (double2 *)(vw + o_vl);
-    double *ya = (double *)(vw + o_ya), *za = (double *)(vw + o_za), *wa = (double *)(vw + o_wa),
-           *va = (double *)(vw + o_va);
-    void *scratch = vw + o_scr;
+    const CheckBufs bufs = carve_check(vw, m, k);
     unsigned long long *word = (unsigned long long *)(vw + o_word);
     void *cin = vw + o_cin;
-    const uint64_t seed = h->verify_seed;
-    const double rel = h->verify_rel > 0.0 ? h->verify_rel
-                                            : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
-    // rounding of the double-double evaluation itself
-    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-104;
-    if (!beta_zero) {
+    if (!beta_zero)
         OZC_TRY(hipMemcpy2DAsync(cin, es * m, C, es * ldc, es * m, n, hipMemcpyDeviceToDevice, s));
-        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, v, vl, va,
-                            scratch, s));
-    }
     struct RestoreN {
         ozc_context *h;
         int n0;
@@ -456,16 +501,9 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
         h->nmod = N;
         st = run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
         if (st != OZC_STATUS_SUCCESS) break;
-        // y = op(B) x (k), z = op(A) y (m), w = C x (m)
-        if (tb == OZC_OP_N)
-            OZC_TRY(launch_gemv(B, single, 0, k, n, ldb, nullptr, nullptr, nullptr, seed, y, yl, ya, scratch, s));
-        else
-            OZC_TRY(launch_gemv(B, single, (int)tb, n, k, ldb, nullptr, nullptr, nullptr, seed, y, yl, ya, scratch, s));
-        if (ta == OZC_OP_N) OZC_TRY(launch_gemv(A, single, 0, m, k, lda, y, yl, ya, 0, z, zl, za, scratch, s));
-        else OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, y, yl, ya, 0, z, zl, za, scratch, s));
-        OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, w, wl, wa, scratch, s));
-        OZC_TRY(launch_freivalds_rows(w, wl, wa, z, zl, za, beta_zero ? nullptr : v, vl, va, m, alpha,
-                                      beta, rel, gam, word, s));
+        st = enqueue_check(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cin, m,
+                           bufs, word, s);
+        if (st != OZC_STATUS_SUCCESS) break;
         unsigned long long host[2] = {0, 0};
         OZC_TRY(hipMemcpyAsync(host, word, sizeof(host), hipMemcpyDeviceToHost, s));
         OZC_TRY(hipStreamSynchronize(s));

@@ -576,6 +576,100 @@ ozc_status_t run_plan(ozc_context *h, BatchState *bs, bool single,
     return OZC_STATUS_SUCCESS;
 }
 
+// A batch with the Freivalds check per problem (see ozc_set_verify): problems that fail
+// are rerun as a smaller batch with two more moduli, up to OZC_MAX_MODULI.
+ozc_status_t run_plan_verified(ozc_context *h, BatchState *bs, bool single,
+                               const std::vector<Problem> &probs, std::vector<int> Ns) {
+    hipStream_t s = h->stream;
+    const size_t es = single ? 8 : 16;
+    std::vector<size_t> chk;                    // checked problems
+    std::vector<size_t> slot(probs.size(), 0);  // their index in chk
+    std::vector<size_t> cin_off(probs.size(), 0);
+    int64_t mmax = 1, kmax = 1;
+    size_t scr = 0, cin_bytes = 0;
+    for (size_t p = 0; p < probs.size(); ++p) {
+        const Problem &q = probs[p];
+        if (q.m == 0 || q.n == 0 || is_degenerate(q)) continue;
+        slot[p] = chk.size();
+        chk.push_back(p);
+        mmax = std::max(mmax, q.m);
+        kmax = std::max(kmax, q.k);
+        scr = std::max(scr, check_scratch_bytes(q.ta, q.tb, q.m, q.n, q.k));
+        if (q.beta[0] != 0.0 || q.beta[1] != 0.0) {
+            cin_off[p] = cin_bytes;
+            cin_bytes = align_up(cin_bytes + es * (size_t)q.m * (size_t)q.n);
+        }
+    }
+    const size_t o_words = check_bytes(mmax, kmax, scr);
+    const size_t o_cin = align_up(o_words + 16 * std::max<size_t>(1, chk.size()));
+    ozc_status_t st = ensure_vws(h, o_cin + cin_bytes);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    char *vw = (char *)h->vws;
+    const CheckBufs bufs = carve_check(vw, mmax, kmax);
+    unsigned long long *words = (unsigned long long *)(vw + o_words);
+    auto has_cin = [&](const Problem &q) { return q.beta[0] != 0.0 || q.beta[1] != 0.0; };
+    for (size_t p : chk) {  // C_in for the check and for reruns
+        const Problem &q = probs[p];
+        if (has_cin(q))
+            OZC_TRY(hipMemcpy2DAsync(vw + o_cin + cin_off[p], es * q.m, q.C, es * q.ldc, es * q.m, q.n,
+                                     hipMemcpyDeviceToDevice, s));
+    }
+    st = run_plan(h, bs, single, probs, Ns);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    std::vector<size_t> todo = chk;
+    std::vector<double> ratio(chk.size(), 0.0);
+    std::vector<int64_t> failed(chk.size(), 0);
+    int rounds = 0;
+    for (;;) {
+        for (size_t p : todo) {
+            const Problem &q = probs[p];
+            st = enqueue_check(h, single, q.ta, q.tb, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb,
+                               q.beta, q.C, q.ldc, has_cin(q) ? vw + o_cin + cin_off[p] : nullptr, q.m,
+                               bufs, words + 2 * slot[p], s);
+            if (st != OZC_STATUS_SUCCESS) return st;
+        }
+        std::vector<unsigned long long> host(2 * std::max<size_t>(1, chk.size()), 0);
+        OZC_TRY(hipMemcpyAsync(host.data(), words, 16 * chk.size(), hipMemcpyDeviceToHost, s));
+        OZC_TRY(hipStreamSynchronize(s));
+        std::vector<size_t> again;
+        bool stuck = false;
+        for (size_t p : todo) {
+            const size_t i = slot[p];
+            memcpy(&ratio[i], &host[2 * i], sizeof(double));
+            failed[i] = (int64_t)host[2 * i + 1];
+            if (failed[i] == 0) continue;
+            if (h->escalate && Ns[p] < OZC_MAX_MODULI) again.push_back(p);
+            else stuck = true;
+        }
+        if (stuck) st = OZC_STATUS_VERIFY_FAILED;
+        if (again.empty()) break;
+        ++rounds;
+        std::vector<Problem> sub;
+        std::vector<int> subN;
+        for (size_t p : again) {
+            const Problem &q = probs[p];
+            Ns[p] = std::min(OZC_MAX_MODULI, Ns[p] + 2);
+            if (has_cin(q))
+                OZC_TRY(hipMemcpy2DAsync(q.C, es * q.ldc, vw + o_cin + cin_off[p], es * q.m, es * q.m,
+                                         q.n, hipMemcpyDeviceToDevice, s));
+            sub.push_back(q);
+            subN.push_back(Ns[p]);
+        }
+        ozc_status_t sr = run_plan(h, bs, single, sub, subN);
+        if (sr != OZC_STATUS_SUCCESS) return sr;
+        todo = again;
+    }
+    h->last.verified = 1;
+    h->last.escalations = rounds;
+    h->last.verify_failed_rows = 0;
+    h->last.verify_ratio = 0.0;
+    for (size_t i = 0; i < chk.size(); ++i) {
+        h->last.verify_failed_rows += failed[i];
+        h->last.verify_ratio = std::max(h->last.verify_ratio, ratio[i]);
+    }
+    return st;
+}
+
 ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t *ta,
                           const ozc_op_t *tb, const int64_t *m, const int64_t *n,
                           const int64_t *k, const double *alpha, const void *const *A,
@@ -597,7 +691,9 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
     st = grid_sizes(h, bs);
     if (st != OZC_STATUS_SUCCESS) return st;
     std::vector<int> Ns(probs.size(), h->nmod);
-    if (!h->auto_n) return run_plan(h, bs, single, probs, Ns);
+    if (!h->auto_n)
+        return h->verify ? run_plan_verified(h, bs, single, probs, Ns)
+                         : run_plan(h, bs, single, probs, Ns);
 
     // Learned N per problem (complex64: the fixed count), all in one batch.
     h->last.num_moduli = 0;
@@ -618,7 +714,8 @@ ozc_status_t run_vbatched(ozc_context *h, bool single, int count, const ozc_op_t
         if (st != OZC_STATUS_SUCCESS) return st;
         for (size_t i = 0; i < which.size(); ++i) Ns[which[i]] = pred[i];
     }
-    return run_plan(h, bs, single, probs, Ns);  // num_moduli: the largest count used
+    // num_moduli: the largest count used
+    return h->verify ? run_plan_verified(h, bs, single, probs, Ns) : run_plan(h, bs, single, probs, Ns);
 }
 
 // Median of the product phase over `reps` runs.

@@ -66,4 +66,23 @@ ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t t
                             int64_t ldb, int *N);
 ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<OperandView> &va,
                                  const std::vector<OperandView> &vb, std::vector<int> &N);
+
+// Freivalds check (api.cpp): device vectors for products with up to `rows` rows of C and
+// inner dimension up to `inner`, carved from one buffer of check_bytes(...) bytes.
+struct CheckBufs {
+    double2 *y, *yl, *z, *zl, *w, *wl, *v, *vl;
+    double *ya, *za, *wa, *va;
+    void *scratch;
+};
+size_t check_bytes(int64_t rows, int64_t inner, size_t scratch_bytes);
+ozc_status_t ensure_vws(ozc_context *h, size_t bytes);  // the handle's verification buffer
+CheckBufs carve_check(char *base, int64_t rows, int64_t inner);
+size_t check_scratch_bytes(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k);
+// Enqueues the check of C = alpha op(A) op(B) + beta C_in on stream s; C_in (m x n, leading
+// dimension ld_cin) is read only when beta != 0.  word receives (max ratio, failed rows).
+ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                           int64_t n, int64_t k, const double alpha[2], const void *A,
+                           int64_t lda, const void *B, int64_t ldb, const double beta[2],
+                           const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
+                           const CheckBufs &b, unsigned long long *word, hipStream_t s);
 }  // namespace ozc

@@ -345,3 +345,45 @@ def test_learned_moduli_batch_matches_single_calls(handle):
         torch.cuda.synchronize()
     finally:
         h2.close()
+
+
+def test_verified_batch_escalates_like_single_calls(handle):
+    """Freivalds check in a batch: starting from too few moduli, every problem is rerun with
+    two more until its check passes, exactly as a verified single call does (same checks,
+    same seed), so each result equals the verified single call's bit for bit."""
+    import paper_2512_08321_amd as ozc
+
+    h2 = ozc.Handle(0)
+    try:
+        probs = _make_batch(91, 8, 16, 200, phi_max=2.0)
+        h2.set_config(6, "fast", "karatsuba")
+        h2.set_verify(True, 0.0, True)
+        dev = _upload(probs)
+        h2.gemm_vbatched(dev)
+        info = h2.last_info()
+        got = _download(dev)
+        assert info["verified"] == 1 and info["escalations"] >= 1
+        assert info["verify_failed_rows"] == 0 and info["verify_ratio"] <= 1.0
+        ref_dev = _upload(probs)
+        for d in ref_dev:
+            h2.zgemm(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["alpha"], d["A"], d["lda"],
+                     d["B"], d["ldb"], d["beta"], d["C"], d["ldc"])
+        ref = _download(ref_dev)
+        assert all(_same(a, b) for a, b in zip(got, ref))
+        # without escalation the same batch ends in VERIFY_FAILED
+        h2.set_verify(True, 0.0, False)
+        with pytest.raises(ozc.OzcError) as e:
+            h2.gemm_vbatched(_upload(probs))
+        assert e.value.status == 7
+        # a clean batch at 14 moduli passes without reruns and matches the unverified batch
+        h2.set_config(14, "fast", "karatsuba")
+        h2.set_verify(True, 0.0, True)
+        d1 = _upload(probs)
+        h2.gemm_vbatched(d1)
+        assert h2.last_info()["escalations"] == 0
+        h2.set_verify(False)
+        d2 = _upload(probs)
+        h2.gemm_vbatched(d2)
+        assert all(_same(a, b) for a, b in zip(_download(d1), _download(d2)))
+    finally:
+        h2.close()
