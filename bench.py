@@ -497,6 +497,25 @@ def bench_batch_auto(args):
         met_auto += ea <= target
         worst_auto = max(worst_auto, ea)
     P = len(probs)
+    verified = None
+    if args.verify:  # the same three runs with the Freivalds check at the target (escalation on)
+        log("[bench] the same runs with the Freivalds check at the target")
+        h.set_verify(True, rel=target, escalate=True)
+        h.set_config(n_fix, "fast", "karatsuba")
+        v_loop = timed(loop, max(1, args.steps // 2), 1)
+        v_fixed = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
+        esc_fixed = h.last_info()["escalations"]
+        h.set_config(0, "fast", "karatsuba")
+        v_auto = timed(lambda: h.gemm_vbatched(probs), args.steps, args.warmup)
+        info = h.last_info()
+        h.set_verify(False)
+        verified = {"loop_fixed_ms": round(v_loop, 4), "batched_fixed_ms": round(v_fixed, 4),
+                    "batched_learned_ms": round(v_auto, 4),
+                    "escalation_rounds": {"fixed": esc_fixed, "learned": info["escalations"]},
+                    "speedup_vs_loop_fixed": round(v_loop / v_auto, 3),
+                    "speedup_vs_batched_fixed": round(v_fixed / v_auto, 3)}
+        log(f"[bench] verified: loop {v_loop:.2f} ms, fixed batch {v_fixed:.2f} ms, learned batch "
+            f"{v_auto:.2f} ms (escalation rounds {info['escalations']})")
     value = flops / (auto_ms * 1e-3) / 1e12
     log(f"[bench] loop N={n_fix}: {loop_ms:.2f} ms; batched N={n_fix}: {fixed_batch_ms:.2f} ms; "
         f"batched learned N (mean {np.mean(Ns):.2f}): {auto_ms:.2f} ms; target met "
@@ -525,6 +544,7 @@ def bench_batch_auto(args):
         "speedup_vs_batched_fixed": round(fixed_batch_ms / auto_ms, 3),
         "target_met": {"fixed": met_fixed, "learned": met_auto, "of": P},
         "worst_err_learned": worst_auto,
+        "freivalds_verified": verified,
     }
     print(json.dumps(out), flush=True)
     h.close()

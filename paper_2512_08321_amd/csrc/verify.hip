@@ -91,18 +91,19 @@ __device__ __forceinline__ void accum(const VecIn &x, int64_t j, double2 m, dd &
     }
 }
 
-constexpr int kChunk = 1024;  // columns per partial sum (N case)
+constexpr int kChunk = 1024;  // largest number of columns per partial sum (N case)
 
 // y = op(M) x for M stored column-major (rows x cols, ld) with op = N:
 // y_r = sum_c M[r + c ld] x_c.  Thread per row, block column chunks write
 // partials[chunk][r], reduced in order afterwards.
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void gemv_n_partial(const void *M, int64_t rows, int64_t cols,
-                                                      int64_t ld, VecIn x, double2 *part_hi,
-                                                      double2 *part_lo, double *part_abs) {
+                                                      int64_t ld, int64_t chunk, VecIn x,
+                                                      double2 *part_hi, double2 *part_lo,
+                                                      double *part_abs) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
-    const int64_t c0 = (int64_t)blockIdx.y * kChunk, c1 = min(cols, c0 + kChunk);
+    const int64_t c0 = (int64_t)blockIdx.y * chunk, c1 = min(cols, c0 + chunk);
     dd re{0.0, 0.0}, im{0.0, 0.0};
     double ab = 0.0;
     for (int64_t c = c0; c < c1; ++c) accum(x, c, load_c<SINGLE>(M, r + c * ld), re, im, ab);
@@ -224,6 +225,17 @@ hipError_t launch_debug_add_exp(int16_t *mu, int delta, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Columns per partial sum (op = N): kChunk, halved down to 32 while the grid would have
+// fewer than 2048 blocks, so that small products still spread over the chip (a thread
+// accumulates its chunk serially).  A fixed function of the shape: the summation order,
+// and with it the verdict, stays reproducible.
+static int64_t gemv_chunk(int64_t rows, int64_t cols) {
+    const int64_t bx = (rows + 255) / 256;
+    int64_t ch = kChunk;
+    while (ch > 32 && bx * ((cols + ch - 1) / ch) < 2048) ch /= 2;
+    return ch;
+}
+
 // y = op(M) x (double-double: y, ylo), ya = |op(M)| |x|.  M column-major rows x
 // cols (ld); op: 0 N, 1 T, 2 C.  scratch: gemv_scratch_bytes(rows, cols) for op = N.
 hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t cols, int64_t ld,
@@ -232,14 +244,15 @@ hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t
     VecIn x{xv, xlo, xa, seed};
     if (op == 0) {
         if (rows <= 0) return hipSuccess;
-        const int nchunk = (int)((cols + kChunk - 1) / kChunk);
+        const int64_t chunk = gemv_chunk(rows, cols);
+        const int nchunk = (int)((cols + chunk - 1) / chunk);
         double2 *ph = (double2 *)scratch;
         double2 *pl = ph + (size_t)nchunk * rows;
         double *pa = (double *)(pl + (size_t)nchunk * rows);
         if (nchunk > 0) {
             dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nchunk);
-            if (single) hipLaunchKernelGGL(gemv_n_partial<true>, grid, dim3(256), 0, s, M, rows, cols, ld, x, ph, pl, pa);
-            else hipLaunchKernelGGL(gemv_n_partial<false>, grid, dim3(256), 0, s, M, rows, cols, ld, x, ph, pl, pa);
+            if (single) hipLaunchKernelGGL(gemv_n_partial<true>, grid, dim3(256), 0, s, M, rows, cols, ld, chunk, x, ph, pl, pa);
+            else hipLaunchKernelGGL(gemv_n_partial<false>, grid, dim3(256), 0, s, M, rows, cols, ld, chunk, x, ph, pl, pa);
         }
         hipLaunchKernelGGL(reduce_partials, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, ph, pl,
                            pa, rows, nchunk, y, ylo, ya);
@@ -253,7 +266,8 @@ hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t
 }
 
 size_t gemv_scratch_bytes(int64_t rows, int64_t cols) {
-    const int64_t nchunk = (cols + kChunk - 1) / kChunk;
+    const int64_t chunk = gemv_chunk(rows, cols);
+    const int64_t nchunk = (cols + chunk - 1) / chunk;
     return (size_t)(nchunk > 0 ? nchunk : 1) * (size_t)(rows > 0 ? rows : 1) * 40;
 }
 
