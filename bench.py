@@ -76,12 +76,17 @@ def main():
     ap.add_argument("--verify", action="store_true",
                     help="enable the Freivalds check on every call (its cost shows in ms/step)")
     ap.add_argument("--workload", default="zgemm",
-                    choices=["zgemm", "batch", "batch-auto", "vendor-int8", "vendor-complex"],
+                    choices=["zgemm", "batch", "batch-auto", "learned-n", "vendor-int8",
+                             "vendor-complex"],
                     help="zgemm: one large product (default); batch: 512 uneven products; "
-                         "batch-auto: the same with the learned moduli count; vendor-int8: the "
+                         "batch-auto: the same with the learned moduli count; learned-n: "
+                         "held-out evaluation of the moduli-count predictor on square "
+                         "products (n up to 1024, k up to 16384); vendor-int8: the "
                          "vendor's INT8 GEMM (torch._int_mm) on size^3 int8 operands, for "
                          "comparison with one residue product")
-    ap.add_argument("--train-count", type=int, default=2000, help="batch-auto: training instances")
+    ap.add_argument("--train-count", type=int, default=2000,
+                    help="batch-auto, learned-n: training instances")
+    ap.add_argument("--heldout-count", type=int, default=200, help="learned-n: held-out instances")
     ap.add_argument("--margin", type=int, default=2,
                     help="batch-auto: moduli added to each prediction (2 meets the target on "
                          "every problem of the batch, as the fixed count does)")
@@ -102,6 +107,8 @@ def main():
         return bench_batch(args)
     if args.workload == "batch-auto":
         return bench_batch_auto(args)
+    if args.workload == "learned-n":
+        return bench_learned_n(args)
     if args.workload == "vendor-complex":
         return bench_vendor_complex(args)
     if args.workload == "vendor-int8":
@@ -545,6 +552,123 @@ def bench_batch_auto(args):
         "target_met": {"fixed": met_fixed, "learned": met_auto, "of": P},
         "worst_err_learned": worst_auto,
         "freivalds_verified": verified,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+def bench_learned_n(args):
+    """The moduli-count predictor on held-out instances of the learned-N workload
+    (square products, n log-uniform in [256, 1024], k in [256, 16384], phi uniform in
+    [0, 8], power-of-two skews along k): label accuracy, escalation rate and the
+    verified throughput of single calls with the learned count against the fixed
+    count.  Labels and errors come from the emulation itself (smallest N meeting the
+    target against the 24-moduli result)."""
+    import numpy as np
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    import workloads
+    from paper_2512_08321_amd import autoN
+
+    torch.cuda.set_device(0)
+    h = ozc.Handle(0)
+    target = args.target
+    kw = dict(lo=256, hi=1024, klo=256, khi=16384, phi_max=8.0, skew_max=40, square=True)
+    log(f"[bench] labelling {args.train_count} training instances (target {target:g})")
+    t0 = time.perf_counter()
+    X, y, meta = autoN.generate(h, args.train_count, seed=workloads.seed_for(5, 0, "A"),
+                                target=target, log=log, **kw)
+    labels = [r[-1] for r in meta]
+    n_fix = autoN.fixed_rule(labels)
+    losses = h.mlp_train(X, y, len(meta), epochs=200, batch=64, lr=3e-3, seed=7)
+    log(f"[bench] labels N: mean {np.mean(labels):.2f}, fixed rule N={n_fix}; training loss "
+        f"{losses[0]:.3f} -> {losses[-1]:.3f} ({time.perf_counter() - t0:.1f} s)")
+    h.set_auto_moduli(fallback=n_fix, margin=args.margin)
+
+    def timed_call(inst, N):
+        m, n, k = inst["m"], inst["n"], inst["k"]
+        C = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+        h.set_config(N, "fast", "karatsuba")
+        h.set_verify(True, rel=target, escalate=True)
+        def call():
+            try:
+                h.zgemm("N", "N", m, n, k, 1.0, inst["A"], m, inst["B"], k, 0.0, C, m)
+            except ozc.OzcError as e:  # the check failed even at 24 moduli: C holds that result
+                if e.status != 7:
+                    raise
+
+        call()  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        info = h.last_info()
+        h.set_verify(False)
+        return dt, info
+
+    rng = np.random.default_rng(workloads.seed_for(5, 1, "A"))
+    rows, flops, t_fix, t_auto = [], 0.0, 0.0, 0.0
+    for i in range(args.heldout_count):
+        inst = autoN.draw_instance(rng, **kw)
+        lab = autoN.label(h, inst, target)
+        m, n, k = inst["m"], inst["n"], inst["k"]
+        h.set_auto_moduli(fallback=n_fix, margin=0)
+        raw = h.predict_moduli("N", "N", m, n, k, inst["A"], m, inst["B"], k)
+        h.set_auto_moduli(fallback=n_fix, margin=args.margin)
+        ev = autoN.evaluate(h, [inst], target, margin=args.margin)[0]
+        h.set_auto_moduli(fallback=n_fix, margin=args.margin)
+        tf, info_f = timed_call(inst, n_fix)
+        ta, info_a = timed_call(inst, 0)
+        flops += 8.0 * m * n * k
+        t_fix += tf
+        t_auto += ta
+        rows.append(dict(label=lab, raw=raw, N_hat=ev["N_hat"], N_used=ev["N_used"], esc=ev["esc"],
+                         err=ev["err"], status=ev["status"], fix_status_ok=info_f["escalations"] == 0))
+        if (i + 1) % max(1, args.heldout_count // 10) == 0:
+            log(f"[bench] {i + 1}/{args.heldout_count} held-out instances evaluated")
+    H = len(rows)
+    lab = np.array([r["label"] for r in rows])
+    raw = np.array([r["raw"] for r in rows])
+    used = np.array([r["N_used"] for r in rows])
+    acc = {"exact": round(float(np.mean(raw == lab)), 4),
+           "within_1": round(float(np.mean(np.abs(raw - lab) <= 1)), 4),
+           "under": round(float(np.mean(raw < lab)), 4),
+           "over": round(float(np.mean(raw > lab)), 4)}
+    esc_rate = float(np.mean([r["esc"] > 0 for r in rows]))
+    met = int(sum(r["err"] <= target for r in rows))
+    value = flops / t_auto / 1e12
+    log(f"[bench] held-out {H}: raw prediction exact {acc['exact']:.3f}, within 1 "
+        f"{acc['within_1']:.3f}, under {acc['under']:.3f}; with margin {args.margin}: mean N "
+        f"{used.mean():.2f} vs fixed {n_fix}, escalation rate {esc_rate:.3f}, target met {met}/{H}; "
+        f"verified calls {t_auto * 1e3:.1f} ms learned vs {t_fix * 1e3:.1f} ms fixed")
+    out = {
+        "metric": "emulated ZGEMM eff. TFLOPS (sum 8mnk / t), verified single calls, learned moduli count",
+        "value": round(value, 3),
+        "unit": "TFLOPS",
+        "n_gpus": 1,
+        "steps": H,
+        "warmup": 1,
+        "ms_per_step": round(t_auto * 1e3 / H, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"{H} held-out square ZGEMMs, n log-uniform in [256, 1024], k in "
+                               f"[256, 16384], phi uniform in [0, 8], power-of-two skews along k; "
+                               f"predictor trained on {args.train_count} instances of the same "
+                               f"distribution labelled at max err/(|A||B|) <= {target:g}"},
+        "fixed_rule_N": n_fix,
+        "margin": args.margin,
+        "mean_label_N": round(float(lab.mean()), 3),
+        "mean_N_used": round(float(used.mean()), 3),
+        "raw_prediction_accuracy": acc,
+        "escalation_rate": round(esc_rate, 4),
+        "target_met": {"learned": met, "of": H},
+        "verified_ms": {"learned": round(t_auto * 1e3, 3), "fixed": round(t_fix * 1e3, 3)},
+        "speedup_vs_fixed": round(t_fix / t_auto, 3),
     }
     print(json.dumps(out), flush=True)
     h.close()

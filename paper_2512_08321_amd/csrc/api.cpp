@@ -179,16 +179,20 @@ size_t check_scratch_bytes(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64
     return scr;
 }
 
+void check_tolerances(const ozc_context *h, bool single, int64_t n, int64_t k, double *rel,
+                      double *gam) {
+    *rel = h->verify_rel > 0.0 ? h->verify_rel : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
+    *gam = 4.0 * (double)(n + k + 4) * 0x1p-104;  // rounding of the double-double evaluation
+}
+
 ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                            int64_t n, int64_t k, const double alpha[2], const void *A,
                            int64_t lda, const void *B, int64_t ldb, const double beta[2],
                            const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
                            const CheckBufs &b, unsigned long long *word, hipStream_t s) {
     const uint64_t seed = h->verify_seed;
-    const double rel = h->verify_rel > 0.0 ? h->verify_rel
-                                            : 4.0 * (double)k * (single ? 0x1p-24 : 0x1p-53);
-    // rounding of the double-double evaluation itself
-    const double gam = 4.0 * (double)(n + k + 4) * 0x1p-104;
+    double rel, gam;
+    check_tolerances(h, single, n, k, &rel, &gam);
     const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
     // v = C_in x (m), y = op(B) x (k), z = op(A) y (m), w = C x (m)
     if (!beta_zero)

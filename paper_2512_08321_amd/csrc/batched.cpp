@@ -578,36 +578,49 @@ ozc_status_t run_plan(ozc_context *h, BatchState *bs, bool single,
 
 // A batch with the Freivalds check per problem (see ozc_set_verify): problems that fail
 // are rerun as a smaller batch with two more moduli, up to OZC_MAX_MODULI.
+// Workspace of one problem's check: its vectors (carve_check) with scratch for the
+// partial sums of the gemvs that run together (C_in x, op(B) x and C x), later reused
+// by op(A) y.
+size_t problem_check_bytes(const Problem &q, bool has_cin) {
+    size_t first = align_up(gemv_scratch_bytes(q.m, q.n));  // C x
+    if (has_cin) first += align_up(gemv_scratch_bytes(q.m, q.n));
+    if (q.tb == OZC_OP_N) first += align_up(gemv_scratch_bytes(q.k, q.n));
+    const size_t second = q.ta == OZC_OP_N ? gemv_scratch_bytes(q.m, q.k) : 0;
+    return align_up(check_bytes(q.m, q.k, std::max(first, second)));
+}
+
 ozc_status_t run_plan_verified(ozc_context *h, BatchState *bs, bool single,
                                const std::vector<Problem> &probs, std::vector<int> Ns) {
     hipStream_t s = h->stream;
     const size_t es = single ? 8 : 16;
+    auto has_cin = [&](const Problem &q) { return q.beta[0] != 0.0 || q.beta[1] != 0.0; };
     std::vector<size_t> chk;                    // checked problems
     std::vector<size_t> slot(probs.size(), 0);  // their index in chk
-    std::vector<size_t> cin_off(probs.size(), 0);
-    int64_t mmax = 1, kmax = 1;
-    size_t scr = 0, cin_bytes = 0;
+    std::vector<size_t> cin_off(probs.size(), 0), chk_off(probs.size(), 0);
+    size_t cin_bytes = 0, chk_bytes = 0;
     for (size_t p = 0; p < probs.size(); ++p) {
         const Problem &q = probs[p];
         if (q.m == 0 || q.n == 0 || is_degenerate(q)) continue;
         slot[p] = chk.size();
         chk.push_back(p);
-        mmax = std::max(mmax, q.m);
-        kmax = std::max(kmax, q.k);
-        scr = std::max(scr, check_scratch_bytes(q.ta, q.tb, q.m, q.n, q.k));
-        if (q.beta[0] != 0.0 || q.beta[1] != 0.0) {
+        chk_off[p] = chk_bytes;
+        chk_bytes += problem_check_bytes(q, has_cin(q));
+        if (has_cin(q)) {
             cin_off[p] = cin_bytes;
             cin_bytes = align_up(cin_bytes + es * (size_t)q.m * (size_t)q.n);
         }
     }
-    const size_t o_words = check_bytes(mmax, kmax, scr);
-    const size_t o_cin = align_up(o_words + 16 * std::max<size_t>(1, chk.size()));
+    // words (max ratio, failed rows) per checked problem | task descriptors | per-problem
+    // check buffers | saved C_in
+    const size_t nchk = std::max<size_t>(1, chk.size());
+    const size_t o_desc = align_up(16 * nchk);
+    const size_t desc_bytes = align_up(nchk * (4 * sizeof(GemvTask) + sizeof(RowsTask)));
+    const size_t o_chk = o_desc + desc_bytes;
+    const size_t o_cin = o_chk + chk_bytes;
     ozc_status_t st = ensure_vws(h, o_cin + cin_bytes);
     if (st != OZC_STATUS_SUCCESS) return st;
     char *vw = (char *)h->vws;
-    const CheckBufs bufs = carve_check(vw, mmax, kmax);
-    unsigned long long *words = (unsigned long long *)(vw + o_words);
-    auto has_cin = [&](const Problem &q) { return q.beta[0] != 0.0 || q.beta[1] != 0.0; };
+    unsigned long long *words = (unsigned long long *)vw;
     for (size_t p : chk) {  // C_in for the check and for reruns
         const Problem &q = probs[p];
         if (has_cin(q))
@@ -620,14 +633,78 @@ ozc_status_t run_plan_verified(ozc_context *h, BatchState *bs, bool single,
     std::vector<double> ratio(chk.size(), 0.0);
     std::vector<int64_t> failed(chk.size(), 0);
     int rounds = 0;
+    const uint64_t seed = h->verify_seed;
     for (;;) {
+        // The checks of all pending problems in five launches: w = C x, y = op(B) x and
+        // v = C_in x together, then z = op(A) y, then the row tests.
+        std::vector<GemvTask> first, second;
+        std::vector<RowsTask> rows;
+        int64_t nb1[3] = {0, 0, 0}, nb2[3] = {0, 0, 0}, nbr = 0;
         for (size_t p : todo) {
             const Problem &q = probs[p];
-            st = enqueue_check(h, single, q.ta, q.tb, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb,
-                               q.beta, q.C, q.ldc, has_cin(q) ? vw + o_cin + cin_off[p] : nullptr, q.m,
-                               bufs, words + 2 * slot[p], s);
-            if (st != OZC_STATUS_SUCCESS) return st;
+            const CheckBufs b = carve_check(vw + o_chk + chk_off[p], q.m, q.k);
+            char *sc = (char *)b.scratch;
+            first.push_back(make_gemv_task(q.C, 0, q.m, q.n, q.ldc, nullptr, nullptr, nullptr, seed, b.w,
+                                           b.wl, b.wa, sc, nb1));
+            sc += align_up(gemv_scratch_bytes(q.m, q.n));
+            if (has_cin(q)) {
+                first.push_back(make_gemv_task(vw + o_cin + cin_off[p], 0, q.m, q.n, q.m, nullptr, nullptr,
+                                               nullptr, seed, b.v, b.vl, b.va, sc, nb1));
+                sc += align_up(gemv_scratch_bytes(q.m, q.n));
+            }
+            if (q.tb == OZC_OP_N)
+                first.push_back(make_gemv_task(q.B, 0, q.k, q.n, q.ldb, nullptr, nullptr, nullptr, seed,
+                                               b.y, b.yl, b.ya, sc, nb1));
+            else
+                first.push_back(make_gemv_task(q.B, (int)q.tb, q.n, q.k, q.ldb, nullptr, nullptr, nullptr,
+                                               seed, b.y, b.yl, b.ya, nullptr, nb1));
+            if (q.ta == OZC_OP_N)
+                second.push_back(make_gemv_task(q.A, 0, q.m, q.k, q.lda, b.y, b.yl, b.ya, 0, b.z, b.zl,
+                                                b.za, b.scratch, nb2));
+            else
+                second.push_back(make_gemv_task(q.A, (int)q.ta, q.k, q.m, q.lda, b.y, b.yl, b.ya, 0, b.z,
+                                                b.zl, b.za, nullptr, nb2));
+            RowsTask r{};
+            r.w = b.w;
+            r.wl = b.wl;
+            r.wa = b.wa;
+            r.z = b.z;
+            r.zl = b.zl;
+            r.za = b.za;
+            if (has_cin(q)) {
+                r.v = b.v;
+                r.vl = b.vl;
+                r.va = b.va;
+            }
+            r.m = q.m;
+            r.ar = q.alpha[0];
+            r.ai = q.alpha[1];
+            r.br = q.beta[0];
+            r.bi = q.beta[1];
+            check_tolerances(h, single, q.n, q.k, &r.rel, &r.gam);
+            r.worst = words + 2 * slot[p];
+            r.b0 = nbr;
+            nbr += rows_task_blocks(q.m);
+            rows.push_back(r);
         }
+        if (std::max({nb1[0], nb1[1], nb1[2], nb2[0], nb2[1], nb2[2], nbr}) > INT32_MAX)
+            return OZC_STATUS_NOT_SUPPORTED;
+        // descriptors: first | second | rows (the host copy lives until the synchronisation)
+        std::vector<char> desc(first.size() * sizeof(GemvTask) + second.size() * sizeof(GemvTask) +
+                               rows.size() * sizeof(RowsTask));
+        memcpy(desc.data(), first.data(), first.size() * sizeof(GemvTask));
+        memcpy(desc.data() + first.size() * sizeof(GemvTask), second.data(),
+               second.size() * sizeof(GemvTask));
+        memcpy(desc.data() + (first.size() + second.size()) * sizeof(GemvTask), rows.data(),
+               rows.size() * sizeof(RowsTask));
+        const GemvTask *d_first = (const GemvTask *)(vw + o_desc);
+        const GemvTask *d_second = d_first + first.size();
+        const RowsTask *d_rows = (const RowsTask *)(d_second + second.size());
+        OZC_TRY(hipMemcpyAsync(vw + o_desc, desc.data(), desc.size(), hipMemcpyHostToDevice, s));
+        OZC_TRY(launch_fill_u64((uint64_t *)words, 2 * (int64_t)nchk, 0, s));
+        OZC_TRY(launch_batch_gemv(d_first, (int)first.size(), nb1, single, s));
+        OZC_TRY(launch_batch_gemv(d_second, (int)second.size(), nb2, single, s));
+        OZC_TRY(launch_batch_rows(d_rows, (int)rows.size(), nbr, s));
         std::vector<unsigned long long> host(2 * std::max<size_t>(1, chk.size()), 0);
         OZC_TRY(hipMemcpyAsync(host.data(), words, 16 * chk.size(), hipMemcpyDeviceToHost, s));
         OZC_TRY(hipStreamSynchronize(s));

@@ -78,6 +78,10 @@ size_t check_bytes(int64_t rows, int64_t inner, size_t scratch_bytes);
 ozc_status_t ensure_vws(ozc_context *h, size_t bytes);  // the handle's verification buffer
 CheckBufs carve_check(char *base, int64_t rows, int64_t inner);
 size_t check_scratch_bytes(ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k);
+// rel: the tolerance relative to the absolute products (the handle's, else 4 k u);
+// gam: the relative rounding bound of the double-double evaluation
+void check_tolerances(const ozc_context *h, bool single, int64_t n, int64_t k, double *rel,
+                      double *gam);
 // Enqueues the check of C = alpha op(A) op(B) + beta C_in on stream s; C_in (m x n, leading
 // dimension ld_cin) is read only when beta != 0.  word receives (max ratio, failed rows).
 ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,

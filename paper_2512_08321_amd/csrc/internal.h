@@ -267,6 +267,45 @@ hipError_t launch_freivalds_rows(const double2 *w, const double2 *wl, const doub
                                  const double2 *v, const double2 *vl, const double *va, int64_t m,
                                  const double alpha[2], const double beta[2], double rel,
                                  double gam, unsigned long long *worst, hipStream_t s);
+
+// One matrix-vector product of a batched check: y = op(M) x as in launch_gemv, with
+// x the sign vector of seed (xv == nullptr) or a double-double vector.  make_gemv_task
+// fills the column chunking and the partial sums (scratch: gemv_scratch_bytes(rows,
+// cols) for op = N, unused otherwise) and appends the task's blocks to the running
+// block counts nb[] of the three kernels (partial sums, their reduction, op = T / C).
+struct GemvTask {
+    const void *M;
+    int64_t rows, cols, ld, chunk;
+    int32_t op, nchunk;
+    const double2 *xv, *xlo;
+    const double *xa;
+    uint64_t seed;
+    double2 *y, *ylo;
+    double *ya;
+    double2 *ph, *pl;
+    double *pa;
+    int64_t b0[3];  // first block of this task in each of the three kernels
+};
+GemvTask make_gemv_task(const void *M, int op, int64_t rows, int64_t cols, int64_t ld,
+                        const double2 *xv, const double2 *xlo, const double *xa, uint64_t seed,
+                        double2 *y, double2 *ylo, double *ya, void *scratch, int64_t nb[3]);
+// tasks: device copy of n tasks whose block counts are nb[]
+hipError_t launch_batch_gemv(const GemvTask *tasks, int n, const int64_t nb[3], bool single,
+                             hipStream_t s);
+
+// The per-row test of one problem of a batched check (as launch_freivalds_rows; v may
+// be null); b0: first block of the problem in the launch.
+struct RowsTask {
+    const double2 *w, *wl, *z, *zl, *v, *vl;
+    const double *wa, *za, *va;
+    int64_t m;
+    double ar, ai, br, bi, rel, gam;
+    unsigned long long *worst;
+    int64_t b0;
+};
+inline int64_t rows_task_blocks(int64_t m) { return (m + 255) / 256; }
+// worst[] of every task must be cleared beforehand
+hipError_t launch_batch_rows(const RowsTask *tasks, int n, int64_t nblocks, hipStream_t s);
 hipError_t launch_debug_xor_byte(int8_t *p, hipStream_t s);
 hipError_t launch_debug_add_exp(int16_t *mu, int delta, hipStream_t s);
 

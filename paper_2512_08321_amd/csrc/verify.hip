@@ -91,32 +91,40 @@ __device__ __forceinline__ void accum(const VecIn &x, int64_t j, double2 m, dd &
     }
 }
 
-constexpr int kChunk = 1024;  // largest number of columns per partial sum (N case)
-
 // y = op(M) x for M stored column-major (rows x cols, ld) with op = N:
-// y_r = sum_c M[r + c ld] x_c.  Thread per row, block column chunks write
-// partials[chunk][r], reduced in order afterwards.
+// y_r = sum_c M[r + c ld] x_c.  Thread per row; block (bx, cy) sums the columns of
+// chunk cy into partials[cy][r], reduced in order afterwards.
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void gemv_n_partial(const void *M, int64_t rows, int64_t cols,
-                                                      int64_t ld, int64_t chunk, VecIn x,
-                                                      double2 *part_hi, double2 *part_lo,
-                                                      double *part_abs) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void gemv_n_partial_body(const void *M, int64_t rows, int64_t cols,
+                                                    int64_t ld, int64_t chunk, const VecIn &x,
+                                                    double2 *part_hi, double2 *part_lo,
+                                                    double *part_abs, int64_t bx, int64_t cy) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= rows) return;
-    const int64_t c0 = (int64_t)blockIdx.y * chunk, c1 = min(cols, c0 + chunk);
+    const int64_t c0 = cy * chunk, c1 = min(cols, c0 + chunk);
     dd re{0.0, 0.0}, im{0.0, 0.0};
     double ab = 0.0;
     for (int64_t c = c0; c < c1; ++c) accum(x, c, load_c<SINGLE>(M, r + c * ld), re, im, ab);
-    const int64_t o = blockIdx.y * rows + r;
+    const int64_t o = cy * rows + r;
     part_hi[o] = make_double2(re.hi, im.hi);
     part_lo[o] = make_double2(re.lo, im.lo);
     part_abs[o] = ab;
 }
 
-__global__ void reduce_partials(const double2 *part_hi, const double2 *part_lo,
-                                const double *part_abs, int64_t rows, int nchunk, double2 *y,
-                                double2 *ylo, double *ya) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void gemv_n_partial(const void *M, int64_t rows, int64_t cols,
+                                                      int64_t ld, int64_t chunk, VecIn x,
+                                                      double2 *part_hi, double2 *part_lo,
+                                                      double *part_abs) {
+    gemv_n_partial_body<SINGLE>(M, rows, cols, ld, chunk, x, part_hi, part_lo, part_abs,
+                                blockIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ void reduce_partials_body(const double2 *part_hi, const double2 *part_lo,
+                                                     const double *part_abs, int64_t rows,
+                                                     int nchunk, double2 *y, double2 *ylo,
+                                                     double *ya, int64_t bx) {
+    const int64_t r = bx * 256 + threadIdx.x;
     if (r >= rows) return;
     dd re{0.0, 0.0}, im{0.0, 0.0};
     double ab = 0.0;
@@ -131,14 +139,23 @@ __global__ void reduce_partials(const double2 *part_hi, const double2 *part_lo,
     ya[r] = ab;
 }
 
+__global__ __launch_bounds__(256) void reduce_partials(const double2 *part_hi,
+                                                       const double2 *part_lo,
+                                                       const double *part_abs, int64_t rows,
+                                                       int nchunk, double2 *y, double2 *ylo,
+                                                       double *ya) {
+    reduce_partials_body(part_hi, part_lo, part_abs, rows, nchunk, y, ylo, ya, blockIdx.x);
+}
+
 // y = op(M) x for op = T or C: y_c = sum_r M[r + c ld]^(*) x_r.  One wave per
-// output entry, lanes over r, fixed-order butterfly reduction in double-double.
+// output entry (four per block), lanes over r, fixed-order butterfly reduction in
+// double-double.
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void gemv_t(const void *M, int64_t rows, int64_t cols, int64_t ld,
-                                              int conj, VecIn x, double2 *y, double2 *ylo,
-                                              double *ya) {
+__device__ __forceinline__ void gemv_t_body(const void *M, int64_t rows, int64_t cols, int64_t ld,
+                                            int conj, const VecIn &x, double2 *y, double2 *ylo,
+                                            double *ya, int64_t bx) {
     const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c = bx * 4 + (threadIdx.x >> 6);
     if (c >= cols) return;
     dd re{0.0, 0.0}, im{0.0, 0.0};
     double ab = 0.0;
@@ -160,6 +177,13 @@ __global__ __launch_bounds__(256) void gemv_t(const void *M, int64_t rows, int64
     }
 }
 
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void gemv_t(const void *M, int64_t rows, int64_t cols, int64_t ld,
+                                              int conj, VecIn x, double2 *y, double2 *ylo,
+                                              double *ya) {
+    gemv_t_body<SINGLE>(M, rows, cols, ld, conj, x, y, ylo, ya, blockIdx.x);
+}
+
 // (a_r + i a_i) * (z_hi + z_lo) for a double complex a and a double-double complex z
 __device__ __forceinline__ void cmul_dd(double ar, double ai, double2 zh, double2 zl, dd &re, dd &im) {
     re = {0.0, 0.0};
@@ -175,12 +199,11 @@ __device__ __forceinline__ void cmul_dd(double ar, double ai, double2 zh, double
 // Per-row residual test.  worst[0] receives max_i |res_i| / tol_i as the bit
 // pattern of a non-negative double (order-preserving), worst[1] the number of
 // failing rows.
-__global__ void freivalds_rows(const double2 *w, const double2 *wl, const double *wa,
-                               const double2 *z, const double2 *zl, const double *za,
-                               const double2 *v, const double2 *vl, const double *va, int64_t m,
-                               double ar, double ai, double br, double bi, double rel, double gam,
-                               unsigned long long *worst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void freivalds_rows_body(
+    const double2 *w, const double2 *wl, const double *wa, const double2 *z, const double2 *zl,
+    const double *za, const double2 *v, const double2 *vl, const double *va, int64_t m, double ar,
+    double ai, double br, double bi, double rel, double gam, unsigned long long *worst, int64_t bx) {
+    const int64_t i = bx * 256 + threadIdx.x;
     if (i >= m) return;
     dd er{w[i].x, wl[i].x}, ei{w[i].y, wl[i].y}, tr, ti;
     cmul_dd(-ar, -ai, z[i], zl[i], tr, ti);
@@ -201,6 +224,60 @@ __global__ void freivalds_rows(const double2 *w, const double2 *wl, const double
     if (!(ratio == ratio) || !(res == res) || !(tol == tol)) ratio = INFINITY;  // NaN fails
     atomicMax(&worst[0], (unsigned long long)__double_as_longlong(ratio));
     if (ratio > 1.0) atomicAdd(&worst[1], 1ull);
+}
+
+__global__ __launch_bounds__(256) void freivalds_rows(
+    const double2 *w, const double2 *wl, const double *wa, const double2 *z, const double2 *zl,
+    const double *za, const double2 *v, const double2 *vl, const double *va, int64_t m, double ar,
+    double ai, double br, double bi, double rel, double gam, unsigned long long *worst) {
+    freivalds_rows_body(w, wl, wa, z, zl, za, v, vl, va, m, ar, ai, br, bi, rel, gam, worst,
+                        blockIdx.x);
+}
+
+// ---- batched check: one launch per kernel over the blocks of many tasks; a block
+// finds its task by binary search over the tasks' first blocks (tasks with no block
+// in a kernel share their successor's first block and are never selected).
+template <typename First>
+__device__ __forceinline__ int find_task(int n, int64_t b, First first) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void batch_gemv_n_partial(const GemvTask *tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const GemvTask &t = tasks[find_task(n, b, [&](int i) { return tasks[i].b0[0]; })];
+    const int64_t nbx = (t.rows + 255) / 256, local = b - t.b0[0];
+    const VecIn x{t.xv, t.xlo, t.xa, t.seed};
+    gemv_n_partial_body<SINGLE>(t.M, t.rows, t.cols, t.ld, t.chunk, x, t.ph, t.pl, t.pa,
+                                local % nbx, local / nbx);
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_partials(const GemvTask *tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const GemvTask &t = tasks[find_task(n, b, [&](int i) { return tasks[i].b0[1]; })];
+    reduce_partials_body(t.ph, t.pl, t.pa, t.rows, t.nchunk, t.y, t.ylo, t.ya, b - t.b0[1]);
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void batch_gemv_t(const GemvTask *tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const GemvTask &t = tasks[find_task(n, b, [&](int i) { return tasks[i].b0[2]; })];
+    const VecIn x{t.xv, t.xlo, t.xa, t.seed};
+    gemv_t_body<SINGLE>(t.M, t.rows, t.cols, t.ld, t.op == 2 ? 1 : 0, x, t.y, t.ylo, t.ya,
+                        b - t.b0[2]);
+}
+
+__global__ __launch_bounds__(256) void batch_freivalds_rows(const RowsTask *tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const RowsTask &t = tasks[find_task(n, b, [&](int i) { return tasks[i].b0; })];
+    freivalds_rows_body(t.w, t.wl, t.wa, t.z, t.zl, t.za, t.v, t.vl, t.va, t.m, t.ar, t.ai, t.br,
+                        t.bi, t.rel, t.gam, t.worst, b - t.b0);
 }
 
 __global__ void fill_words(unsigned long long *p, int n) {
@@ -225,14 +302,14 @@ hipError_t launch_debug_add_exp(int16_t *mu, int delta, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Columns per partial sum (op = N): kChunk, halved down to 32 while the grid would have
-// fewer than 2048 blocks, so that small products still spread over the chip (a thread
-// accumulates its chunk serially).  A fixed function of the shape: the summation order,
-// and with it the verdict, stays reproducible.
-static int64_t gemv_chunk(int64_t rows, int64_t cols) {
-    const int64_t bx = (rows + 255) / 256;
-    int64_t ch = kChunk;
-    while (ch > 32 && bx * ((cols + ch - 1) / ch) < 2048) ch /= 2;
+// Columns per partial sum (op = N): the smallest power of two in [32, 1024] whose
+// square reaches cols, which balances the serial work of a partial-sum thread (chunk
+// terms) against that of the reduction (cols / chunk terms) and gives small products
+// enough blocks.  A function of the column count alone: a product is summed in the same
+// order in single and batched checks, so their verdicts agree.
+static int64_t gemv_chunk(int64_t cols) {
+    int64_t ch = 32;
+    while (ch < 1024 && ch * ch < cols) ch *= 2;
     return ch;
 }
 
@@ -244,7 +321,7 @@ hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t
     VecIn x{xv, xlo, xa, seed};
     if (op == 0) {
         if (rows <= 0) return hipSuccess;
-        const int64_t chunk = gemv_chunk(rows, cols);
+        const int64_t chunk = gemv_chunk(cols);
         const int nchunk = (int)((cols + chunk - 1) / chunk);
         double2 *ph = (double2 *)scratch;
         double2 *pl = ph + (size_t)nchunk * rows;
@@ -265,8 +342,63 @@ hipError_t launch_gemv(const void *M, bool single, int op, int64_t rows, int64_t
     return hipGetLastError();
 }
 
+GemvTask make_gemv_task(const void *M, int op, int64_t rows, int64_t cols, int64_t ld,
+                        const double2 *xv, const double2 *xlo, const double *xa, uint64_t seed,
+                        double2 *y, double2 *ylo, double *ya, void *scratch, int64_t nb[3]) {
+    GemvTask t{};
+    t.M = M;
+    t.rows = rows;
+    t.cols = cols;
+    t.ld = ld;
+    t.op = op;
+    t.xv = xv;
+    t.xlo = xlo;
+    t.xa = xa;
+    t.seed = seed;
+    t.y = y;
+    t.ylo = ylo;
+    t.ya = ya;
+    for (int i = 0; i < 3; ++i) t.b0[i] = nb[i];
+    if (op == 0) {
+        if (rows <= 0) return t;
+        t.chunk = gemv_chunk(cols);
+        t.nchunk = (int32_t)((cols + t.chunk - 1) / t.chunk);
+        t.ph = (double2 *)scratch;
+        t.pl = t.ph + (size_t)t.nchunk * rows;
+        t.pa = (double *)(t.pl + (size_t)t.nchunk * rows);
+        const int64_t nbx = (rows + 255) / 256;
+        nb[0] += nbx * t.nchunk;
+        nb[1] += nbx;
+    } else {
+        nb[2] += (cols + 3) / 4;
+    }
+    return t;
+}
+
+hipError_t launch_batch_gemv(const GemvTask *tasks, int n, const int64_t nb[3], bool single,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nb[0] > 0) {
+        if (single) hipLaunchKernelGGL(batch_gemv_n_partial<true>, dim3((unsigned)nb[0]), dim3(256), 0, s, tasks, n);
+        else hipLaunchKernelGGL(batch_gemv_n_partial<false>, dim3((unsigned)nb[0]), dim3(256), 0, s, tasks, n);
+    }
+    if (nb[1] > 0)
+        hipLaunchKernelGGL(batch_reduce_partials, dim3((unsigned)nb[1]), dim3(256), 0, s, tasks, n);
+    if (nb[2] > 0) {
+        if (single) hipLaunchKernelGGL(batch_gemv_t<true>, dim3((unsigned)nb[2]), dim3(256), 0, s, tasks, n);
+        else hipLaunchKernelGGL(batch_gemv_t<false>, dim3((unsigned)nb[2]), dim3(256), 0, s, tasks, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(const RowsTask *tasks, int n, int64_t nblocks, hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_freivalds_rows, dim3((unsigned)nblocks), dim3(256), 0, s, tasks, n);
+    return hipGetLastError();
+}
+
 size_t gemv_scratch_bytes(int64_t rows, int64_t cols) {
-    const int64_t chunk = gemv_chunk(rows, cols);
+    const int64_t chunk = gemv_chunk(cols);
     const int64_t nchunk = (cols + chunk - 1) / chunk;
     return (size_t)(nchunk > 0 ? nchunk : 1) * (size_t)(rows > 0 ? rows : 1) * 40;
 }

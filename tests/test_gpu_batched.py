@@ -387,3 +387,40 @@ def test_verified_batch_escalates_like_single_calls(handle):
         assert all(_same(a, b) for a, b in zip(_download(d1), _download(d2)))
     finally:
         h2.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("single", [False, True])
+def test_verified_batch_check_matches_single_checks(handle, single):
+    """The checks of a batch run as one set of launches over all problems, summing each
+    product in the same order as a single call's check: the batch's largest residual
+    ratio equals the largest over the verified single calls bit for bit, and so do the
+    results (all op() forms, alpha/beta, column counts above and below the chunking
+    thresholds)."""
+    import paper_2512_08321_amd as ozc
+
+    h2 = ozc.Handle(0)
+    try:
+        probs = _make_batch(93 + single, 12, 16, 1500, single=single, phi_max=2.0)
+        h2.set_config(9 if single else 14, "fast", "karatsuba")
+        h2.set_verify(True, 0.0, True)
+        dev = _upload(probs)
+        h2.gemm_vbatched(dev, single=single)
+        info = h2.last_info()
+        got = _download(dev)
+        ratios, failed = [], 0
+        ref_dev = _upload(probs)
+        fn = h2.cgemm if single else h2.zgemm
+        for d in ref_dev:
+            fn(d["transa"], d["transb"], d["m"], d["n"], d["k"], d["alpha"], d["A"], d["lda"], d["B"],
+               d["ldb"], d["beta"], d["C"], d["ldc"])
+            si = h2.last_info()
+            ratios.append(si["verify_ratio"])
+            failed += si["verify_failed_rows"]
+        ref = _download(ref_dev)
+        assert info["verified"] == 1
+        assert info["verify_ratio"] == max(ratios) and 0.0 < info["verify_ratio"] <= 1.0
+        assert info["verify_failed_rows"] == failed == 0
+        assert all(_same(a, b) for a, b in zip(got, ref))
+    finally:
+        h2.close()
