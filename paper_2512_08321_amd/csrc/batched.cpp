@@ -357,7 +357,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         c.a.ldc = q.ldc;
         c.a.single = single;
         c.blk0 = cr.blocks;
-        cr.blocks += batch_crt_blocks(d.m_pad, q.n);
+        cr.blocks += batch_crt_blocks(q.m, q.n);
         ++cr.count;
         P.crt.push_back(c);
     }

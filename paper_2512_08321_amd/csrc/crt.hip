@@ -141,10 +141,10 @@ __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double 
 }
 
 // One thread: 4 consecutive rows i of one column j; block bx covers threads
-// 256 bx ... 256 bx + 255 of the (m_pad / 4) x n grid.
+// 256 bx ... 256 bx + 255 of the ceil(m / 4) x n grid (padding rows get no thread).
 template <int L, bool SINGLE>
 __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
-    const int64_t m4 = a.m_pad >> 2;
+    const int64_t m4 = (a.m + 3) >> 2;
     const int64_t t = bx * 256 + threadIdx.x;
     const int64_t i4 = t % m4, j = t / m4;
     const int64_t ib = i4 * 4;
@@ -250,7 +250,7 @@ __global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, doubl
 
 template <int L>
 hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
-    const int64_t threads = (a.m_pad / 4) * a.n;
+    const int64_t threads = ((a.m + 3) / 4) * a.n;
     dim3 grid((unsigned)((threads + 255) / 256));
     if (a.single) hipLaunchKernelGGL((crt_output_kernel<L, true>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((crt_output_kernel<L, false>), grid, dim3(256), 0, s, a);
@@ -287,7 +287,7 @@ hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool singl
     return hipGetLastError();
 }
 
-int64_t batch_crt_blocks(int64_t m_pad, int64_t n) { return ((m_pad / 4) * n + 255) / 256; }
+int64_t batch_crt_blocks(int64_t m, int64_t n) { return (((m + 3) / 4) * n + 255) / 256; }
 
 hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
                             bool single, hipStream_t s) {

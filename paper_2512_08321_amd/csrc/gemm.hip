@@ -58,9 +58,10 @@ struct Plan {
     }
 };
 
-// Symmetric residue of an INT32 accumulator: for odd p the accumulator is
-// bounded by k * 127^2 < 2^31 and koff (a multiple of p >= 2^31) makes it
-// non-negative; for p = 256 the wrap-around modulo 2^32 is harmless.
+// Symmetric residue of an INT32 accumulator, or of an accumulator plus or minus a
+// residue: for odd p the argument is bounded by k * 127^2 + 127 < 2^31 - p
+// (k <= 2^17) and koff (the least multiple of p >= 2^31) makes it non-negative
+// without leaving 32 bits; for p = 256 the wrap-around modulo 2^32 is harmless.
 __device__ __forceinline__ int reduce_acc(int x, const ModConst &mc) {
     uint32_t u = (uint32_t)x + mc.koff;
     uint32_t r = u - __umulhi(u, mc.barrett) * mc.p;
@@ -418,18 +419,23 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                     static_for<4>([&](auto g) {
                         uint32_t *er = eword(ER, bi, bj, g);
                         uint32_t *ei = eword(EI, bi, bj, g);
-                        int v[4], o[4];
-                        static_for<4>([&](auto u) { v[u] = reduce_acc(acc[bi][bj][4 * (int)g + (int)u], mc); });
+                        // The first product of a pair is reduced and carried; the second
+                        // enters the reduction unreduced (accumulator +- carried residue
+                        // stays in range, see reduce_acc): 4 reductions per output for
+                        // Karatsuba, 2 for the expanded form.
+                        int o[4];
+                        auto acc_u = [&](int u) { return acc[bi][bj][4 * (int)g + u]; };
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
-                            if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(v);
-                            else *ei = pack4(v);
+                            static_for<4>([&](auto u) { o[u] = reduce_acc(acc_u(u), mc); });
+                            if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
+                            else *ei = pack4(o);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
                             const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
-                            static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) - v[u], mc); });
+                            static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) - acc_u(u), mc); });
                             *er = pack4(o);
                             if constexpr (karatsuba) {
-                                static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) + v[u], mc); });
+                                static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) + acc_u(u), mc); });
                                 if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
                                 else *ei = pack4(o);
                             }
@@ -437,7 +443,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
                             const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
                             static_for<4>([&](auto u) {
-                                o[u] = reduce_acc(karatsuba ? v[u] - byte_of(w, u) : byte_of(w, u) + v[u], mc);
+                                o[u] = reduce_acc(karatsuba ? acc_u(u) - byte_of(w, u) : byte_of(w, u) + acc_u(u), mc);
                             });
                             *ei = pack4(o);
                         }

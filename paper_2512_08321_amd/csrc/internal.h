@@ -195,7 +195,7 @@ struct BatchCrt {
     CrtArgs a;
     int64_t blk0;
 };
-int64_t batch_crt_blocks(int64_t m_pad, int64_t n);
+int64_t batch_crt_blocks(int64_t m, int64_t n);  // blocks of one problem's reconstruction
 hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
                             bool single, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

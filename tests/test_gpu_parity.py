@@ -237,6 +237,29 @@ def test_k_above_int32_limit_is_chunked(handle, orc, ta, tb):
     assert _same(got, ref)
 
 
+@pytest.mark.parametrize("algo", ["karatsuba", "4m"])
+def test_accumulators_near_int32_limit(handle, orc, algo):
+    """k = 2^17 (the largest unchunked k) with constant operands: every term of a
+    residue product has the same sign, so the INT32 accumulators reach 0.87 * 2^31
+    (Karatsuba; 0.67 * 2^31 expanded) for an odd modulus, and the epilogue adds a carried
+    residue to an unreduced accumulator; bit-exact with the oracle."""
+    import paper_2512_08321_amd as ozc
+
+    k = ozc.MAX_K
+    a, b = 0.9833534339803927 + 0.44735250930159265j, 0.6176876180693398 - 0.6942699537086543j
+    A = np.full((3, k), a)
+    B = np.full((k, 2), b)
+    print(f"int32-limit {algo} k={k}", flush=True)
+    ref = orc.emulate(A, B, 14, algo=algo)
+    ra, rb = np.asarray(ref["resA"]), np.asarray(ref["resB"])
+    pairs = [(0, 0), (1, 1), (2, 2)] if algo == "karatsuba" else [(0, 0), (1, 1), (0, 1), (1, 0)]
+    biggest = max(abs(int(ra[l, pa].flat[0]) * int(rb[l, pb].flat[0])) * k
+                  for l in range(1, 14) for pa, pb in pairs)
+    assert biggest >= (0.85 if algo == "karatsuba" else 0.65) * 2.0 ** 31
+    got = _gemm_call(handle, A, B, np.zeros((3, 2)), 1.0, 0.0, 14, "fast", algo)
+    assert _same(got, ref["out"])
+
+
 def test_config0_workload_bit_exact(handle, orc):
     """256^3 complex128, 14 moduli, 4-GEMM products, alpha = 1, beta = 0, phi = 0.5."""
     A = workloads.complex_matrix(256, 256, 0.5, workloads.seed_for(0, 0, "A"))
