@@ -240,8 +240,8 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         P.sum_k += q.k;
     }
     size_t off = 0;
-    P.counter_off = off;
-    off = align_up(off + 64);
+    P.counter_off = off;  // 8 work-queue counters per product tile size, 1 for the bounds
+    off = align_up(off + 4 * (2 * kBatchQueues + 1));
     P.stats_off = off;
     P.stats_words = stats_words;
     off = align_up(off + 8 * stats_words);
@@ -482,8 +482,9 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
         OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, false, s));
         if (P.accurate) {
             OZC_TRY(launch_batch_ceil7(P.ops_dev, nops, P.blk_ceil7, P.single, s));
-            OZC_TRY(launch_fill_u32(counters + 2, 1, 0, s));
-            OZC_TRY(launch_batch_bound(P.bound_dev, (int)P.bound.size(), P.bound_items, counters + 2, s));
+            uint32_t *bound_counter = counters + 2 * kBatchQueues;
+            OZC_TRY(launch_fill_u32(bound_counter, 1, 0, s));
+            OZC_TRY(launch_batch_bound(P.bound_dev, (int)P.bound.size(), P.bound_items, bound_counter, s));
             OZC_TRY(launch_batch_accu_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
         } else {
             OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
@@ -494,12 +495,12 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
                                        r.param, s));
     }
     if (phases & PH_GEMM) {
-        OZC_TRY(launch_fill_u32(counters, 2, 0, s));
+        OZC_TRY(launch_fill_u32(counters, 2 * kBatchQueues, 0, s));
         const int tiles[2] = {256, 128};
         for (int t = 0; t < 2; ++t) {
             if (P.items[t] == 0) continue;
             OZC_TRY(launch_batch_gemm(P.gm_dev[t], (int)P.gm[t].size(), P.items[t], tiles[t], group,
-                                      P.algo, counters + t, bs->grid[t], s));
+                                      P.algo, counters + kBatchQueues * t, bs->grid[t], s));
         }
     }
     if (phases & PH_CRT) {

@@ -472,29 +472,43 @@ __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, Bo
 template <int KIND, typename C>
 __global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm *probs, int nprob,
                                                                 int64_t items, int group,
-                                                                uint32_t *counter) {
+                                                                uint32_t *counters, int64_t chunk) {
     __shared__ int64_t item_s;
-    for (;;) {
-        if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t w = item_s;
-        __syncthreads();
-        if (w >= items) break;
-        int lo = 0, hi = nprob - 1;  // last problem whose first item is <= w
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (probs[mid].item0 <= w) lo = mid;
-            else hi = mid - 1;
+    // Work-groups are dispatched to the XCDs in turn (block b on XCD b mod 8).  The
+    // item sequence is cut into chunks of `chunk` items (the blocks one XCD holds at a
+    // time), dealt to the XCDs in turn, each XCD with its own counter: the tiles that
+    // run together on an XCD are neighbours of one product and share their operand
+    // panels in that XCD's L2.  A block whose queue is empty takes items from the
+    // other queues.  Any dispatch order gives the same results.
+    const int64_t nchunks = items / chunk, rem = items - nchunks * chunk;
+    const int home = (int)(blockIdx.x % kBatchQueues);
+    for (int qs = 0; qs < kBatchQueues; ++qs) {
+        const int q = (home + qs) % kBatchQueues;
+        const int64_t nq = (nchunks / kBatchQueues + (q < nchunks % kBatchQueues ? 1 : 0)) * chunk +
+                           (nchunks % kBatchQueues == q ? rem : 0);
+        for (;;) {
+            if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(&counters[q], 1u);
+            __syncthreads();
+            const int64_t j = item_s;
+            __syncthreads();
+            if (j >= nq) break;
+            const int64_t w = ((j / chunk) * kBatchQueues + q) * chunk + j % chunk;
+            int lo = 0, hi = nprob - 1;  // last problem whose first item is <= w
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (probs[mid].item0 <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            const BatchGemm &pb = probs[lo];
+            const int64_t T = (int64_t)pb.TR * pb.TC, local = w - pb.item0;
+            const int lg = (int)(local / T);
+            const int64_t t = local - (int64_t)lg * T;
+            const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
+            GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, pb.nmod, KIND == KIND_4M ? 1 : 0,
+                       pb.tab, pb.eprime, nullptr, C::TM};
+            const int l1 = min(pb.nmod, (lg + 1) * group);
+            for (int l = lg * group; l < l1; ++l) gemm_tile<KIND, C, false>(a, BoundArgs{}, l, ti, tj);
         }
-        const BatchGemm &pb = probs[lo];
-        const int64_t T = (int64_t)pb.TR * pb.TC, local = w - pb.item0;
-        const int lg = (int)(local / T);
-        const int64_t t = local - (int64_t)lg * T;
-        const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
-        GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, pb.nmod, KIND == KIND_4M ? 1 : 0, pb.tab,
-                   pb.eprime, nullptr, C::TM};
-        const int l1 = min(pb.nmod, (lg + 1) * group);
-        for (int l = lg * group; l < l1; ++l) gemm_tile<KIND, C, false>(a, BoundArgs{}, l, ti, tj);
     }
 }
 
@@ -524,9 +538,10 @@ __global__ __launch_bounds__(C::THREADS) void batch_bound_kernel(const BatchBoun
 
 template <int KIND, typename C>
 void launch_batch_kind(const BatchGemm *probs, int nprob, int64_t items, int group,
-                       uint32_t *counter, int grid, hipStream_t s) {
+                       uint32_t *counters, int grid, hipStream_t s) {
+    const int64_t chunk = grid >= kBatchQueues ? grid / kBatchQueues : 1;  // resident blocks per XCD
     hipLaunchKernelGGL((batch_gemm_kernel<KIND, C>), dim3((unsigned)grid), dim3(C::THREADS), 0, s,
-                       probs, nprob, items, group, counter);
+                       probs, nprob, items, group, counters, chunk);
 }
 
 template <int KIND, typename C>
@@ -610,7 +625,7 @@ int batch_gemm_blocks_per_cu(int tile) {
 }
 
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile, int group,
-                             int algo, uint32_t *counter, int grid_blocks, hipStream_t s) {
+                             int algo, uint32_t *counters, int grid_blocks, hipStream_t s) {
     if (items <= 0 || nprob <= 0) return hipSuccess;
     if ((tile != 128 && tile != 256) || group < 1) return hipErrorInvalidValue;
     if (grid_blocks <= 0) {
@@ -622,11 +637,11 @@ hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, i
     }
     if ((int64_t)grid_blocks > items) grid_blocks = (int)items;
     if (tile == 256) {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeShortK>(probs, nprob, items, group, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgLargeShortK>(probs, nprob, items, group, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgLargeShortK>(probs, nprob, items, group, counters, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgLargeShortK>(probs, nprob, items, group, counters, grid_blocks, s);
     } else {
-        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);
-        else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, counter, grid_blocks, s);
+        if (algo == 0) launch_batch_kind<KIND_KARATSUBA, CfgSmall>(probs, nprob, items, group, counters, grid_blocks, s);
+        else launch_batch_kind<KIND_4M, CfgSmall>(probs, nprob, items, group, counters, grid_blocks, s);
     }
     return hipGetLastError();
 }

@@ -182,11 +182,12 @@ struct BatchGemm {          // one problem of a batched product launch
     int32_t nmod;           // the problem's moduli count
 };
 // Persistent product kernel over a work queue of (problem, modulus group, tile)
-// items, handed out by an atomic counter that must be zero at launch.  `group`
-// moduli are computed one after another per item.  grid_blocks <= 0 picks one
-// wave of resident blocks.
+// items, handed out by kBatchQueues atomic counters (one queue per XCD) that must
+// be zero at launch.  `group` moduli are computed one after another per item.
+// grid_blocks <= 0 picks one wave of resident blocks.
+constexpr int kBatchQueues = 8;  // XCDs of an MI355X, each with its own L2
 hipError_t launch_batch_gemm(const BatchGemm *probs, int nprob, int64_t items, int tile,
-                             int group, int algo, uint32_t *counter, int grid_blocks,
+                             int group, int algo, uint32_t *counters, int grid_blocks,
                              hipStream_t s);
 // Resident blocks of the persistent product kernel per compute unit, for a tile edge.
 int batch_gemm_blocks_per_cu(int tile);
