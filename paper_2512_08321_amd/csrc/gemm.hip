@@ -421,8 +421,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                         uint32_t *ei = eword(EI, bi, bj, g);
                         // The first product of a pair is reduced and carried; the second
                         // enters the reduction unreduced (accumulator +- carried residue
-                        // stays in range, see reduce_acc): 4 reductions per output for
-                        // Karatsuba, 2 for the expanded form.
+                        // stays in range, see reduce_acc): 4 reductions per output and
+                        // modulus in both forms.
                         int o[4];
                         auto acc_u = [&](int u) { return acc[bi][bj][4 * (int)g + u]; };
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
