@@ -145,10 +145,10 @@ ozc_status_t compute_features(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t
     if (s != OZC_STATUS_SUCCESS) return s;
     hipStream_t str = h->stream;
     uint64_t *mb = (uint64_t *)st->stat;
-    double *s1 = (double *)(st->stat + 8 * (size_t)(m + n));
-    double *s2 = (double *)(st->stat + 16 * (size_t)(m + n));
+    unsigned long long *s1 = (unsigned long long *)(st->stat + 8 * (size_t)(m + n));
+    unsigned long long *s2 = (unsigned long long *)(st->stat + 16 * (size_t)(m + n));
     unsigned long long *zeros = (unsigned long long *)(st->stat + 24 * (size_t)(m + n));
-    OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, s1, s2 (0.0), zeros
+    OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, s1, s2, zeros
     const OperandView vA = view_A(A, ta, m, k, lda), vB = view_B(B, tb, n, k, ldb);
     OZC_TRY(launch_row_maxabs(vA, single, mb, str));
     OZC_TRY(launch_row_maxabs(vB, single, mb + m, str));
@@ -216,7 +216,8 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
     }
     char *buf = st->many;
     uint64_t *mb = (uint64_t *)buf;
-    double *s1 = (double *)(buf + 8 * (size_t)rows), *s2 = (double *)(buf + 16 * (size_t)rows);
+    unsigned long long *s1 = (unsigned long long *)(buf + 8 * (size_t)rows);
+    unsigned long long *s2 = (unsigned long long *)(buf + 16 * (size_t)rows);
     unsigned long long *zeros = (unsigned long long *)(buf + b_rows);
     float *feat = (float *)(buf + b_rows + b_zero);
     char *d = buf + b_rows + b_zero + b_feat;

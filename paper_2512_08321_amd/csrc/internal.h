@@ -225,15 +225,24 @@ inline MlpOffsets mlp_offsets(const MlpDims &d) {
 struct MlpActs {  // device buffers for `rows` rows
     float *a1, *h1, *a2, *h2, *z, *dz, *loss_r, *d2, *d1, *xs;
 };
+// Row sums of the statistics pass in fixed point: s = value * 2^feat_frac_bits(k),
+// accumulated with integer atomics (exact and independent of their order, so the
+// statistics are reproducible).  The sums of a row are below 2k * 4, hence the
+// fraction bits shrink for k >= 2^21 to keep them within 64 bits.
+__host__ __device__ inline int feat_frac_bits(int64_t k) {
+    int b = 0;
+    while (b < 63 && (k >> b) != 0) ++b;
+    return 61 - b < 40 ? 61 - b : 40;
+}
 struct FeatOperand {  // one operand of a batched statistics pass
     OperandView v;
     const uint64_t *maxbits;
-    double *s1, *s2;
+    unsigned long long *s1, *s2;
     unsigned long long *zeros;  // the problem's zero counter
     int64_t blk;                // first block of this operand
 };
 struct FeatProblem {
-    const double *s1a, *s2a, *s1b, *s2b;
+    const unsigned long long *s1a, *s2a, *s1b, *s2b;
     int64_t ra, rb;
     const unsigned long long *zeros;
     double m, n, k;
@@ -243,10 +252,13 @@ int64_t batch_feat_blocks(const OperandView &v);
 hipError_t launch_batch_feat_sums(const FeatOperand *ops, int nops, int64_t blocks, bool single,
                                   hipStream_t s);
 hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStream_t s);
-hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits, double *s1,
-                            double *s2, unsigned long long *zeros, hipStream_t s);
-hipError_t launch_feat_reduce(const double *s1a, const double *s2a, int64_t ra, const double *s1b,
-                              const double *s2b, int64_t rb, const unsigned long long *zeros,
+hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits,
+                            unsigned long long *s1, unsigned long long *s2,
+                            unsigned long long *zeros, hipStream_t s);
+hipError_t launch_feat_reduce(const unsigned long long *s1a, const unsigned long long *s2a,
+                              int64_t ra, const unsigned long long *s1b,
+                              const unsigned long long *s2b, int64_t rb,
+                              const unsigned long long *zeros,
                               int64_t m, int64_t n, int64_t k, float *out, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDims &d, const float *params, const float *X, const int *idx,
                               int rows, MlpActs &a, hipStream_t s);

@@ -10,8 +10,9 @@
 //
 // Network (parameter layout shared with the C-ABI): xs = (x - mu) / sd,
 // h1 = relu(W1 xs + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3; W row-major
-// (out x in).  Every reduction runs in a fixed order, so training is
-// reproducible run to run.
+// (out x in).  Every floating-point reduction runs in a fixed order and the row
+// sums of the statistics are accumulated in fixed point with integer atomics, so
+// statistics, predictions and training are reproducible run to run.
 #include <math.h>
 
 #include "internal.h"
@@ -55,8 +56,8 @@ __host__ __device__ __forceinline__ int64_t feat_grid_y(const OperandView &v) {
 
 template <bool SINGLE>
 __device__ __forceinline__ void feat_sums_body(const OperandView &v, const uint64_t *maxbits,
-                                               double *s1, double *s2, unsigned long long *zeros,
-                                               int64_t bx, int64_t by) {
+                                               unsigned long long *s1, unsigned long long *s2,
+                                               unsigned long long *zeros, int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t r, h0, h1, step;
     if (v.contig_h) {
@@ -91,14 +92,18 @@ __device__ __forceinline__ void feat_sums_body(const OperandView &v, const uint6
         }
         if (lane != 0) return;
     }
-    atomicAdd(&s1[r], a1);
-    atomicAdd(&s2[r], a2);
+    // each partial is rounded to fixed point once; the integer sums do not depend on
+    // the order in which blocks arrive
+    const double fx = ldexp(1.0, feat_frac_bits(v.k));
+    atomicAdd(&s1[r], (unsigned long long)rint(a1 * fx));
+    atomicAdd(&s2[r], (unsigned long long)rint(a2 * fx));
     if (z) atomicAdd(&zeros[0], z);
 }
 
 template <bool SINGLE>
 __global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uint64_t *maxbits,
-                                                        double *s1, double *s2,
+                                                        unsigned long long *s1,
+                                                        unsigned long long *s2,
                                                         unsigned long long *zeros) {
     feat_sums_body<SINGLE>(v, maxbits, s1, s2, zeros, blockIdx.x, blockIdx.y);
 }
@@ -118,21 +123,24 @@ __global__ __launch_bounds__(256) void batch_feat_sums_kernel(const FeatOperand 
 }
 
 // One block: statistics of l2 and l1 over the nonzero rows of both operands.
-__device__ __forceinline__ void feat_reduce_body(const double *s1a, const double *s2a, int64_t ra,
-                                                 const double *s1b, const double *s2b, int64_t rb,
+__device__ __forceinline__ void feat_reduce_body(const unsigned long long *s1a,
+                                                 const unsigned long long *s2a, int64_t ra,
+                                                 const unsigned long long *s1b,
+                                                 const unsigned long long *s2b, int64_t rb,
                                                  const unsigned long long *zeros, double m,
                                                  double n, double k, float *out) {
     __shared__ double red[256][5];
     const int t = threadIdx.x;
+    const int fb = feat_frac_bits((int64_t)k);
     float res[16];
     for (int op = 0; op < 2; ++op) {
-        const double *s1 = op ? s1b : s1a, *s2 = op ? s2b : s2a;
+        const unsigned long long *s1 = op ? s1b : s1a, *s2 = op ? s2b : s2a;
         const int64_t rows = op ? rb : ra;
         for (int q = 0; q < 2; ++q) {  // q = 0: l2, 1: l1
             double mn = INFINITY, mx = -INFINITY, sum = 0.0, sq = 0.0, cnt = 0.0;
             for (int64_t r = t; r < rows; r += 256) {
-                if (!(s2[r] > 0.0)) continue;
-                const double x = q == 0 ? 0.5 * log2(s2[r]) : log2(s1[r]);
+                if (s2[r] == 0) continue;  // zero row (or all entries below the resolution)
+                const double x = q == 0 ? 0.5 * (log2((double)s2[r]) - fb) : log2((double)s1[r]) - fb;
                 mn = fmin(mn, x);
                 mx = fmax(mx, x);
                 sum += x;
@@ -175,9 +183,10 @@ __device__ __forceinline__ void feat_reduce_body(const double *s1a, const double
     }
 }
 
-__global__ __launch_bounds__(256) void feat_reduce_kernel(const double *s1a, const double *s2a,
-                                                          int64_t ra, const double *s1b,
-                                                          const double *s2b, int64_t rb,
+__global__ __launch_bounds__(256) void feat_reduce_kernel(const unsigned long long *s1a,
+                                                          const unsigned long long *s2a,
+                                                          int64_t ra, const unsigned long long *s1b,
+                                                          const unsigned long long *s2b, int64_t rb,
                                                           const unsigned long long *zeros,
                                                           double m, double n, double k,
                                                           float *out) {
@@ -304,8 +313,9 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits, double *s1,
-                            double *s2, unsigned long long *zeros, hipStream_t s) {
+hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits,
+                            unsigned long long *s1, unsigned long long *s2,
+                            unsigned long long *zeros, hipStream_t s) {
     if (v.rows <= 0 || v.k <= 0) return hipSuccess;
     dim3 grid;
     if (v.contig_h) grid = dim3((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kFeatChunk - 1) / kFeatChunk));
@@ -334,8 +344,10 @@ hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_feat_reduce(const double *s1a, const double *s2a, int64_t ra, const double *s1b,
-                              const double *s2b, int64_t rb, const unsigned long long *zeros,
+hipError_t launch_feat_reduce(const unsigned long long *s1a, const unsigned long long *s2a,
+                              int64_t ra, const unsigned long long *s1b,
+                              const unsigned long long *s2b, int64_t rb,
+                              const unsigned long long *zeros,
                               int64_t m, int64_t n, int64_t k, float *out, hipStream_t s) {
     hipLaunchKernelGGL(feat_reduce_kernel, dim3(1), dim3(256), 0, s, s1a, s2a, ra, s1b, s2b, rb, zeros,
                        (double)m, (double)n, (double)k, out);

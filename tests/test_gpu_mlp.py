@@ -68,6 +68,29 @@ def test_features_match_oracle(handle, case):
     assert np.allclose(got, ref, rtol=1e-5, atol=1e-5), np.c_[got, ref]
 
 
+def test_features_reproducible_and_match_oracle_long_k(handle):
+    """Row sums accumulated by many blocks (k = 40000: 20 chunks per row of B, 157 per
+    row of A) in fixed point: repeated calls give identical bits, and the statistics
+    still match the FP64 reference."""
+    import torch
+
+    from oracle import features as ft
+
+    A = workloads.complex_matrix(300, 40000, 3.0, 104)
+    B = workloads.complex_matrix(40000, 33, 3.0, 105)
+    dA, lda = to_device(stored(A, "N"))
+    dB, ldb = to_device(stored(B, "N"))
+    outs = []
+    for _ in range(4):
+        out = torch.empty(20, dtype=torch.float32, device="cuda")
+        handle.features("N", "N", 300, 33, 40000, dA, lda, dB, ldb, out)
+        outs.append(out.cpu().numpy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    ref = ft.features(A, B)
+    got = outs[0].astype(np.float64)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-5), np.c_[got, ref]
+
+
 def test_forward_and_gradient_match_oracle(handle):
     import torch
 
