@@ -187,7 +187,11 @@ typedef struct {
  * C_in is saved first when beta != 0) and finally returns
  * OZC_STATUS_VERIFY_FAILED with C holding the last result.  A verified call
  * synchronises the stream.  Extra device memory: O(m + n + k) vectors, plus
- * m x n elements when beta != 0. */
+ * m x n elements when beta != 0.  Batches (ozc_zgemm_vbatched) check every
+ * problem the same way, all checks in one set of launches with the same sums
+ * as a single call's check, and rerun the failing problems as a smaller batch
+ * with two more moduli each; ozc_last_info then reports the rerun rounds, the
+ * failing rows and the largest ratio over all problems. */
 ozc_status_t ozc_set_verify(ozc_handle_t handle, int enable, double rel, int escalate,
                             uint64_t seed);
 
@@ -230,8 +234,9 @@ ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
  *
  * The whole batch runs as one launch per phase (statistics, exponents,
  * residue split, products, reconstruction); the products run in a
- * persistent kernel that takes (problem, moduli group, tile) items from a
- * device work queue, largest k first.  The launch sequence is recorded once
+ * persistent kernel that takes (problem, moduli group, tile) items from
+ * device work queues (one per XCD, neighbouring tiles on one XCD), largest k
+ * first.  The launch sequence is recorded once
  * into a HIP graph per distinct argument list (pointers included) and
  * replayed when the same list comes again.  The batch owns a workspace of its
  * own (kept until the handle is destroyed or a larger batch needs more).
@@ -243,8 +248,9 @@ ozc_status_t ozc_profile_read(ozc_handle_t handle, ozc_profile_t *out);
  * magnitudes and the bound products of all problems run as batched launches
  * too (the bound products in a persistent kernel over their 128 x 128
  * tiles).  Problems must not overlap in C.  Asynchronous on the handle's
- * stream; non-finite inputs are reported by ozc_last_info as for a single
- * call. */
+ * stream unless the Freivalds check is enabled (see ozc_set_verify: the
+ * call then synchronises); non-finite inputs are reported by ozc_last_info
+ * as for a single call. */
 ozc_status_t ozc_zgemm_vbatched(ozc_handle_t handle, int count, const ozc_op_t *transa,
                                 const ozc_op_t *transb, const int64_t *m, const int64_t *n,
                                 const int64_t *k, const double *alpha, const void *const *A,
