@@ -49,8 +49,17 @@ constexpr int kFeatChunk = 2048;
 __host__ __device__ __forceinline__ int64_t feat_grid_x(const OperandView &v) {
     return v.contig_h ? (v.rows + 3) / 4 : (v.rows + 255) / 256;
 }
+// k chunk of a block: kFeatChunk (k contiguous) or kFeatChunk / 8, halved while the
+// grid would have fewer than 1024 blocks (down to 64 and 16), so that small operands
+// still spread over the chip.  A function of the operand's shape only.
+__host__ __device__ __forceinline__ int64_t feat_chunk(const OperandView &v) {
+    const int64_t gx = feat_grid_x(v), lo = v.contig_h ? 64 : 16;
+    int64_t c = v.contig_h ? kFeatChunk : kFeatChunk / 8;
+    while (c > lo && gx * ((v.k + c - 1) / c) < 1024) c /= 2;
+    return c;
+}
 __host__ __device__ __forceinline__ int64_t feat_grid_y(const OperandView &v) {
-    const int64_t c = v.contig_h ? kFeatChunk : kFeatChunk / 8;
+    const int64_t c = feat_chunk(v);
     return (v.k + c - 1) / c;
 }
 
@@ -59,17 +68,18 @@ __device__ __forceinline__ void feat_sums_body(const OperandView &v, const uint6
                                                unsigned long long *s1, unsigned long long *s2,
                                                unsigned long long *zeros, int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t r, h0, h1, step;
+    const int64_t c = feat_chunk(v);
+    int64_t r, h0, step;
     if (v.contig_h) {
         r = bx * 4 + wave;
-        h0 = by * kFeatChunk + lane;
+        h0 = by * c + lane;
         step = 64;
     } else {
         r = bx * 256 + threadIdx.x;
-        h0 = by * (kFeatChunk / 8);
+        h0 = by * c;
         step = 1;
     }
-    h1 = min(v.k, v.contig_h ? by * kFeatChunk + kFeatChunk : by * (kFeatChunk / 8) + kFeatChunk / 8);
+    const int64_t h1 = min(v.k, by * c + c);
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
     const double sc = (mb != 0 && mb < 0x7ff0000000000000ull) ? inv_pow2_of(mb) : 0.0;
@@ -317,9 +327,7 @@ hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *m
                             unsigned long long *s1, unsigned long long *s2,
                             unsigned long long *zeros, hipStream_t s) {
     if (v.rows <= 0 || v.k <= 0) return hipSuccess;
-    dim3 grid;
-    if (v.contig_h) grid = dim3((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kFeatChunk - 1) / kFeatChunk));
-    else grid = dim3((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + kFeatChunk / 8 - 1) / (kFeatChunk / 8)));
+    const dim3 grid((unsigned)feat_grid_x(v), (unsigned)feat_grid_y(v));
     if (single) hipLaunchKernelGGL(feat_sums_kernel<true>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
     else hipLaunchKernelGGL(feat_sums_kernel<false>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
     return hipGetLastError();
