@@ -390,8 +390,8 @@ def test_verified_batch_escalates_like_single_calls(handle):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("single", [False, True])
-def test_verified_batch_check_matches_single_checks(handle, single):
+@pytest.mark.parametrize("single,mode", [(False, "fast"), (True, "fast"), (False, "accurate")])
+def test_verified_batch_check_matches_single_checks(handle, single, mode):
     """The checks of a batch run as one set of launches over all problems, summing each
     product in the same order as a single call's check: the batch's largest residual
     ratio equals the largest over the verified single calls bit for bit, and so do the
@@ -401,8 +401,9 @@ def test_verified_batch_check_matches_single_checks(handle, single):
 
     h2 = ozc.Handle(0)
     try:
+        print(f"verified batch single={single} mode={mode}", flush=True)
         probs = _make_batch(93 + single, 12, 16, 1500, single=single, phi_max=2.0)
-        h2.set_config(9 if single else 14, "fast", "karatsuba")
+        h2.set_config(9 if single else 14, mode, "karatsuba")
         h2.set_verify(True, 0.0, True)
         dev = _upload(probs)
         h2.gemm_vbatched(dev, single=single)
