@@ -59,16 +59,17 @@ struct Plan {
 };
 
 // Symmetric residue of an INT32 accumulator, or of an accumulator plus or minus a
-// residue: for odd p the argument is bounded by k * 127^2 + 127 < 2^31 - p
-// (k <= 2^17) and koff (the least multiple of p >= 2^31) makes it non-negative
-// without leaving 32 bits; for p = 256 the wrap-around modulo 2^32 is harmless.
-__device__ __forceinline__ int reduce_acc(int x, const ModConst &mc) {
-    uint32_t u = (uint32_t)x + mc.koff;
-    uint32_t r = u - __umulhi(u, mc.barrett) * mc.p;
-    if (r >= mc.p) r -= mc.p;
-    int s = (int)r;
-    if (r >= mc.half) s -= (int)mc.p;
-    return s;
+// residue, in FP64: q = rint(x (1/p)) is the nearest integer to x / p (|x| < 2^31, so
+// the rounded product is off by less than 2^-22, and x / p lies at least 1/(2p) from a
+// half-integer unless p = 256, where 1/p is exact), and x - q p is exact.  For p = 256
+// a tie gives +128 instead of -128: the same byte.  The argument stays in INT32: an
+// accumulator is bounded by k 127^2 (odd p; k <= 2^17) and a residue adds at most 127,
+// below 2^31 - p; for p = 256 the wrap-around modulo 2^32 leaves the residue unchanged.
+// Five FP64 instructions, against two quarter-rate integer multiplies and fix-ups for
+// a Barrett reduction (2.5% faster batches, 1.5% at 4096^3).
+__device__ __forceinline__ int reduce_fp(int x, double pd, double ipd) {
+    const double xd = (double)x;
+    return (int)fma(-rint(xd * ipd), pd, xd);
 }
 
 __device__ __forceinline__ uint32_t pack4(const int (&v)[4]) {
@@ -203,6 +204,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
 
     ModConst mc;
     if constexpr (!bound) mc = a.tab->mod[l];
+    const double pd = bound ? 1.0 : (double)mc.p, ipd = 1.0 / pd;
     const int64_t planeC = bound ? 0 : a.n_pad * a.m_pad;
 
     // Each wave fills whole 1 KB chunks (16 rows) of the A and B slabs: lane i of a
@@ -421,21 +423,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                         uint32_t *ei = eword(EI, bi, bj, g);
                         // The first product of a pair is reduced and carried; the second
                         // enters the reduction unreduced (accumulator +- carried residue
-                        // stays in range, see reduce_acc): 4 reductions per output and
+                        // stays in range, see reduce_fp): 4 reductions per output and
                         // modulus in both forms.
                         int o[4];
                         auto acc_u = [&](int u) { return acc[bi][bj][4 * (int)g + u]; };
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
-                            static_for<4>([&](auto u) { o[u] = reduce_acc(acc_u(u), mc); });
+                            static_for<4>([&](auto u) { o[u] = reduce_fp(acc_u(u), pd, ipd); });
                             if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
                             else *ei = pack4(o);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
                             const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
-                            static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) - acc_u(u), mc); });
+                            static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) - acc_u(u), pd, ipd); });
                             *er = pack4(o);
                             if constexpr (karatsuba) {
-                                static_for<4>([&](auto u) { o[u] = reduce_acc(byte_of(w, u) + acc_u(u), mc); });
+                                static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) + acc_u(u), pd, ipd); });
                                 if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
                                 else *ei = pack4(o);
                             }
@@ -443,7 +445,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
                             const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
                             static_for<4>([&](auto u) {
-                                o[u] = reduce_acc(karatsuba ? acc_u(u) - byte_of(w, u) : byte_of(w, u) + acc_u(u), mc);
+                                o[u] = reduce_fp(karatsuba ? acc_u(u) - byte_of(w, u) : byte_of(w, u) + acc_u(u), pd, ipd);
                             });
                             *ei = pack4(o);
                         }

@@ -21,8 +21,6 @@ constexpr int16_t kExpNonfinite = 32767;
 struct ModConst {
     uint32_t p;                  // modulus
     uint32_t half;               // ceil(p / 2): residues >= half map to r - p
-    uint32_t barrett;            // floor(2^32 / p)
-    uint32_t koff;               // multiple of p >= 2^31 (odd p), 0 for p = 256
     int32_t slimb[kMaxLimbs];    // 19-bit limbs of s_l = (P / p_l) q_l
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float

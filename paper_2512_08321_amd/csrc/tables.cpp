@@ -159,8 +159,6 @@ void build_tables(NTable *tables) {
             const uint32_t p = (uint32_t)all[l];
             mc.p = p;
             mc.half = (p + 1) / 2;
-            mc.barrett = (uint32_t)((1ull << 32) / p);
-            mc.koff = (p & 1u) ? (uint32_t)(((1ull << 31) + p - 1) / p * p) : 0u;
             mc.pf = (float)p;
             mc.ipf = 1.0f / (float)p;  // correctly rounded single division
             uint64_t pw = 1;
