@@ -1,7 +1,8 @@
 // Moduli-count predictor: input statistics and a small FP32 perceptron with its
 // training step (forward, softmax cross-entropy, backward, Adam).  Not part of
-// the paper; it chooses N before the emulation runs (the scheme's accuracy grows
-// by about 2^-7.8 per added modulus, Section II).
+// the paper; it chooses N before the emulation runs (each added modulus multiplies
+// P by about 2^7.8, Section II, and the scaling shares those bits between the two
+// operands, so the error falls by about 2^-4 per modulus).
 //
 // Statistics: per row of op(A) / column of op(B) (2k reals), with e = floor(log2
 // max|x|), l2 = 0.5 log2 sum (|x| 2^-e)^2 and l1 = log2 sum |x| 2^-e; the feature
