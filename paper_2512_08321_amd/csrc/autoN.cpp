@@ -170,10 +170,8 @@ ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t t
         return OZC_STATUS_SUCCESS;
     }
     ozc_status_t s = compute_features(h, single, ta, tb, m, n, k, A, lda, B, ldb, st->feat);
-    if (s == OZC_STATUS_SUCCESS) s = ensure_acts(st, 1);
     if (s != OZC_STATUS_SUCCESS) return s;
-    OZC_TRY(launch_mlp_forward(kDims, st->params, st->feat, nullptr, 1, st->a, h->stream));
-    OZC_TRY(launch_argmax(st->a.z, 1, kDims.C, st->pred, h->stream));
+    OZC_TRY(launch_mlp_infer(kDims, st->params, st->feat, 1, st->pred, h->stream));
     int cls = 0;
     OZC_TRY(hipMemcpyAsync(&cls, st->pred, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     OZC_TRY(hipStreamSynchronize(h->stream));
@@ -267,10 +265,7 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
     OZC_TRY(launch_batch_scan(scan_dev, (int)(2 * P), blk_scan, single, false, s));
     OZC_TRY(launch_batch_feat_sums(fops_dev, (int)(2 * P), blk_feat, single, s));
     OZC_TRY(launch_batch_feat_reduce(fprob_dev, (int)P, s));
-    ozc_status_t r = ensure_acts(st, (int)P);
-    if (r != OZC_STATUS_SUCCESS) return r;
-    OZC_TRY(launch_mlp_forward(kDims, st->params, feat, nullptr, (int)P, st->a, s));
-    OZC_TRY(launch_argmax(st->a.z, (int)P, kDims.C, pred, s));
+    OZC_TRY(launch_mlp_infer(kDims, st->params, feat, (int)P, pred, s));
     std::vector<int> cls(P);
     OZC_TRY(hipMemcpyAsync(cls.data(), pred, sizeof(int) * P, hipMemcpyDeviceToHost, s));
     OZC_TRY(hipStreamSynchronize(s));

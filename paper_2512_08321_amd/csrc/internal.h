@@ -206,7 +206,7 @@ struct MlpDims {
 struct MlpOffsets {
     int W1, b1, W2, b2, W3, b3, mu, sd, total, trainable;
 };
-inline MlpOffsets mlp_offsets(const MlpDims &d) {
+__host__ __device__ inline MlpOffsets mlp_offsets(const MlpDims &d) {
     MlpOffsets o{};
     o.W1 = 0;
     o.b1 = o.W1 + d.H * d.F;
@@ -266,6 +266,10 @@ hipError_t launch_mlp_grad(const MlpDims &d, const float *params, const float *X
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t s);
 hipError_t launch_argmax(const float *z, int rows, int C, int *out, hipStream_t s);
+// class (argmax of the logits) of each of `rows` feature rows, one fused launch;
+// equal to launch_mlp_forward followed by launch_argmax
+hipError_t launch_mlp_infer(const MlpDims &d, const float *params, const float *X, int rows,
+                            int *cls, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int n, float v, hipStream_t s);
 
 // Verification (Freivalds) and test hooks.

@@ -230,6 +230,45 @@ __global__ void dense_fwd_kernel(const float *in, const int *idx, int rows, int 
     out[(int64_t)r * dout + o] = relu ? fmaxf(acc, 0.f) : acc;
 }
 
+// Inference: the three layers of the forward pass and the argmax for one row per
+// block (H threads), with every output computed by the same operations in the same
+// order as dense_fwd_kernel, so the class equals that of the layered forward pass.
+constexpr int kInferMax = 256;  // widest layer the fused kernel holds in LDS
+__global__ __launch_bounds__(kInferMax) void mlp_infer_kernel(MlpDims d, const float *params,
+                                                              const float *X, int rows, int *cls) {
+    const int r = blockIdx.x, t = threadIdx.x;
+    if (r >= rows) return;
+    __shared__ float h1[kInferMax], h2[kInferMax], z[kInferMax];
+    const MlpOffsets o = mlp_offsets(d);
+    const float *W1 = params + o.W1, *b1 = params + o.b1, *W2 = params + o.W2, *b2 = params + o.b2,
+                *W3 = params + o.W3, *b3 = params + o.b3, *mu = params + o.mu, *sd = params + o.sd;
+    const float *x = X + (int64_t)r * d.F;
+    if (t < d.H) {
+        float acc = b1[t];
+        for (int i = 0; i < d.F; ++i) acc = fmaf(W1[t * d.F + i], (x[i] - mu[i]) / sd[i], acc);
+        h1[t] = fmaxf(acc, 0.f);
+    }
+    __syncthreads();
+    if (t < d.H) {
+        float acc = b2[t];
+        for (int i = 0; i < d.H; ++i) acc = fmaf(W2[t * d.H + i], h1[i], acc);
+        h2[t] = fmaxf(acc, 0.f);
+    }
+    __syncthreads();
+    if (t < d.C) {
+        float acc = b3[t];
+        for (int i = 0; i < d.H; ++i) acc = fmaf(W3[t * d.H + i], h2[i], acc);
+        z[t] = acc;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int best = 0;
+        for (int c = 1; c < d.C; ++c)
+            if (z[c] > z[best]) best = c;
+        cls[r] = best;
+    }
+}
+
 // standardised copy of the gathered batch (input of the first layer's weight gradient)
 __global__ void standardize_kernel(const float *in, const int *idx, int rows, int din,
                                    const float *mu, const float *sd, float *out) {
@@ -374,6 +413,16 @@ hipError_t launch_mlp_forward(const MlpDims &d, const float *params, const float
                        nullptr, rows, d.H, d.H, W2, b2, nullptr, nullptr, 1, a.a2, a.h2);
     hipLaunchKernelGGL(dense_fwd_kernel, dim3(blocks_for((int64_t)rows * d.C)), dim3(256), 0, s, a.h2,
                        nullptr, rows, d.H, d.C, W3, b3, nullptr, nullptr, 0, nullptr, a.z);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const MlpDims &d, const float *params, const float *X, int rows,
+                            int *cls, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (d.H > kInferMax || d.C > kInferMax || d.F < 1) return hipErrorInvalidValue;
+    const int threads = (d.H > d.C ? d.H : d.C) < 64 ? 64 : ((d.H > d.C ? d.H : d.C) + 63) / 64 * 64;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)rows), dim3((unsigned)threads), 0, s, d, params, X,
+                       rows, cls);
     return hipGetLastError();
 }
 

@@ -179,6 +179,12 @@ def test_auto_moduli_runs_the_predicted_count(handle):
         h2.mlp_set_params(p)
         N = h2.predict_moduli("N", "N", 96, 64, 200, dA, lda, dB, ldb)
         assert 6 <= N <= 24
+        # the fused inference launch picks the class of the layered forward pass
+        feat = torch.empty(20, dtype=torch.float32, device="cuda")
+        h2.features("N", "N", 96, 64, 200, dA, lda, dB, ldb, feat)
+        logits = torch.empty(ozc.MLP_CLASSES, dtype=torch.float32, device="cuda")
+        h2.mlp_forward(feat, 1, logits)
+        assert N == min(24, ozc.MLP_MIN_N + int(torch.argmax(logits).item()))
         h2.zgemm("N", "N", 96, 64, 200, 1.0, dA, lda, dB, ldb, 0.0, dC, ldc)
         torch.cuda.synchronize()
         assert h2.last_info()["num_moduli"] == N
