@@ -140,50 +140,60 @@ __device__ __forceinline__ void feat_reduce_body(const unsigned long long *s1a,
                                                  const unsigned long long *s2b, int64_t rb,
                                                  const unsigned long long *zeros, double m,
                                                  double n, double k, float *out) {
-    __shared__ double red[256][5];
+    __shared__ double red[256][10];  // l2 statistics in 0..4, l1 statistics in 5..9
     const int t = threadIdx.x;
     const int fb = feat_frac_bits((int64_t)k);
     float res[16];
     for (int op = 0; op < 2; ++op) {
         const unsigned long long *s1 = op ? s1b : s1a, *s2 = op ? s2b : s2a;
         const int64_t rows = op ? rb : ra;
-        for (int q = 0; q < 2; ++q) {  // q = 0: l2, 1: l1
-            double mn = INFINITY, mx = -INFINITY, sum = 0.0, sq = 0.0, cnt = 0.0;
-            for (int64_t r = t; r < rows; r += 256) {
-                if (s2[r] == 0) continue;  // zero row (or all entries below the resolution)
-                const double x = q == 0 ? 0.5 * (log2((double)s2[r]) - fb) : log2((double)s1[r]) - fb;
-                mn = fmin(mn, x);
-                mx = fmax(mx, x);
-                sum += x;
-                sq += x * x;
-                cnt += 1.0;
+        double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
+        double sum[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0}, cnt = 0.0;
+        for (int64_t r = t; r < rows; r += 256) {
+            if (s2[r] == 0) continue;  // zero row (or all entries below the resolution)
+            const double x[2] = {0.5 * (log2((double)s2[r]) - fb), log2((double)s1[r]) - fb};
+            for (int q = 0; q < 2; ++q) {  // q = 0: l2, 1: l1
+                mn[q] = fmin(mn[q], x[q]);
+                mx[q] = fmax(mx[q], x[q]);
+                sum[q] += x[q];
+                sq[q] += x[q] * x[q];
             }
-            red[t][0] = mn;
-            red[t][1] = mx;
-            red[t][2] = sum;
-            red[t][3] = sq;
-            red[t][4] = cnt;
-            __syncthreads();
-            for (int w = 128; w >= 1; w >>= 1) {
-                if (t < w) {
-                    red[t][0] = fmin(red[t][0], red[t + w][0]);
-                    red[t][1] = fmax(red[t][1], red[t + w][1]);
-                    red[t][2] += red[t + w][2];
-                    red[t][3] += red[t + w][3];
-                    red[t][4] += red[t + w][4];
+            cnt += 1.0;
+        }
+        for (int q = 0; q < 2; ++q) {
+            red[t][5 * q + 0] = mn[q];
+            red[t][5 * q + 1] = mx[q];
+            red[t][5 * q + 2] = sum[q];
+            red[t][5 * q + 3] = sq[q];
+            red[t][5 * q + 4] = cnt;
+        }
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) {
+                for (int q = 0; q < 2; ++q) {
+                    double *a = red[t] + 5 * q;
+                    const double *b = red[t + w] + 5 * q;
+                    a[0] = fmin(a[0], b[0]);
+                    a[1] = fmax(a[1], b[1]);
+                    a[2] += b[2];
+                    a[3] += b[3];
+                    a[4] += b[4];
                 }
-                __syncthreads();
             }
-            const double c = red[0][4];
-            const double mean = c > 0 ? red[0][2] / c : 0.0;
-            const double var = c > 0 ? fmax(0.0, red[0][3] / c - mean * mean) : 0.0;
-            float *o = res + op * 8 + q * 4;
-            o[0] = c > 0 ? (float)red[0][0] : 0.f;
-            o[1] = c > 0 ? (float)red[0][1] : 0.f;
-            o[2] = (float)mean;
-            o[3] = (float)sqrt(var);
             __syncthreads();
         }
+        for (int q = 0; q < 2; ++q) {
+            const double *a = red[0] + 5 * q;
+            const double c = a[4];
+            const double mean = c > 0 ? a[2] / c : 0.0;
+            const double var = c > 0 ? fmax(0.0, a[3] / c - mean * mean) : 0.0;
+            float *o = res + op * 8 + q * 4;
+            o[0] = c > 0 ? (float)a[0] : 0.f;
+            o[1] = c > 0 ? (float)a[1] : 0.f;
+            o[2] = (float)mean;
+            o[3] = (float)sqrt(var);
+        }
+        __syncthreads();
     }
     if (t == 0) {
         out[0] = (float)log2(m);
