@@ -36,6 +36,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def gemm_source_hash() -> str:
     with open(GEMM_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -199,11 +210,12 @@ def main():
     hi, lo = core.dd_gemm(A_rows, B_cols)
     absab = core.abs_product(A_rows, B_cols)
     err = core.err_nc(C_smp, hi, lo, absab)
+    err_cw = core.err_cw(C_smp, hi, lo)
     # Bit-exact parity on the sample: fast-mode exponents depend only on their own row or
     # column; accurate-mode ones on the whole bound product (checked at full size in tests).
     if args.mode == "fast":
         log(f"[bench] CPU oracle on a {len(sr)}x{len(sc)} sample of the output (k={k})")
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = core.max_threads()
         tc0 = time.perf_counter()
         ref = core.emulate(A_rows, B_cols, N, args.mode, args.algo, single=args.single)["out"]
         tc1 = time.perf_counter()
@@ -211,10 +223,23 @@ def main():
         parity = {"entries": int(ref.size), "bit_exact": bool(same),
                   "mismatches": int(np.sum(ref != C_smp))}
         if not args.no_cpu_baseline:
+            # one core on a smaller block of the same sample (the work is linear in its rows)
+            r1 = max(1, len(sr) // 16)
+            prev = core.set_threads(1)
+            t10 = time.perf_counter()
+            ref1 = core.emulate(A_rows[:r1], B_cols, N, args.mode, args.algo,
+                                single=args.single)["out"]
+            t11 = time.perf_counter()
+            core.set_threads(prev)
+            assert np.array_equal(ref1, ref[:r1])
             cpu = {"value": 8.0 * len(sr) * len(sc) * k / (tc1 - tc0) / 1e12, "unit": "TFLOPS",
                    "cores": threads, "kind": "oracle",
+                   "cpu_model": cpu_model(),
                    "sample": f"{len(sr)} rows x {len(sc)} columns of the {m}x{n}x{k} output "
-                             f"(full k, same inputs), {tc1 - tc0:.1f} s"}
+                             f"(full k, same inputs), {tc1 - tc0:.1f} s on {threads} threads",
+                   "value_1core": 8.0 * r1 * len(sc) * k / (t11 - t10) / 1e12,
+                   "sample_1core": f"the first {r1} of those rows x {len(sc)} columns, "
+                                   f"{t11 - t10:.1f} s on 1 thread"}
     bound = 4 * k * 2.0 ** -53 if not args.single else 4 * k * 2.0 ** -24
 
     workload_key = f"{kind} {m}x{n}x{k} N={N} {args.mode} {args.algo}"
@@ -238,6 +263,7 @@ def main():
         "int8_mfma_util": {"gemm_kernel": round(achieved / INT8_PEAK_TOPS, 4),
                            "end_to_end": round(util_e2e, 4)},
         "err_nc_sample": err,
+        "err_cw_sample": err_cw if np.isfinite(err_cw) else "inf",
         "err_bound": bound,
         "err_ok": (err is not None and err <= bound),
         "parity_sample": parity,

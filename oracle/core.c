@@ -27,6 +27,7 @@
  * exact big integers.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -453,3 +454,7 @@ void orc_abs_product(const double *Are, const double *Aim, int64_t m, const doub
             out[i * n + j] = acc;
         }
 }
+
+/* Threads of the OpenMP loops above (for timing the oracle on a stated core count). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

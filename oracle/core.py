@@ -254,6 +254,18 @@ def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, 
     return dict(mu=mu, nu=nu, fa=fa, fb=fb, resA=resA, resB=resB, Ep=Ep, raw=raw, Cp=cp, out=out)
 
 
+def set_threads(n: int) -> int:
+    """Run the C loops on n OpenMP threads; returns the previous count."""
+    lib = _load()
+    old = lib.orc_max_threads()
+    lib.orc_set_threads(ctypes.c_int(int(n)))
+    return old
+
+
+def max_threads() -> int:
+    return _load().orc_max_threads()
+
+
 # ---------------------------------------------------------------- yardsticks
 
 def dd_gemm(A, B):
