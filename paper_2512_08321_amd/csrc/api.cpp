@@ -288,6 +288,14 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         const size_t es = single ? 8 : 16;
         const double one[2] = {1.0, 0.0};
         double ops = 0.0;
+        // the non-finite flag is cleared once here and then collects every chunk's
+        struct KeepStatus {
+            ozc_context *h;
+            ~KeepStatus() { h->keep_status = false; }
+        } keep{h};
+        OZC_TRY(hipSetDevice(h->device));
+        OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, h->stream));
+        h->keep_status = true;
         for (int64_t c = 0; c < nc; ++c) {
             const int64_t h0 = k * c / nc, h1 = k * (c + 1) / nc;
             const char *Ac = (const char *)A + es * (size_t)(ta == OZC_OP_N ? h0 * lda : h0);
@@ -310,7 +318,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     h->last.m = m;
     h->last.n = n;
     h->last.k = k;
-    OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
+    if (!h->keep_status) OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
     if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
     const bool alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0;
     if ((alpha_zero || k == 0) && ins == nullptr) {

@@ -25,6 +25,7 @@ struct ozc_context {
     ozc::NTable *tab_dev = nullptr;          // kMaxModuli tables, index N - 1
     std::vector<ozc::NTable> tab_host;
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
+    bool keep_status = false;           // k-chunks after the first: keep the flag of earlier chunks
     ozc_info_t last{};
     bool profiling = false;
     // verification

@@ -200,18 +200,29 @@ def test_nonfinite_inputs(handle, orc):
 
 
 def test_argument_errors(handle):
+    """Rejected before any work.  The operands are real device buffers of the declared
+    shapes, so that a regression in the checks would compute on valid memory and fail
+    an assertion instead of touching unowned addresses."""
+    import torch
+
     import paper_2512_08321_amd as ozc
 
+    kbig = ozc.MAX_K + 1
+    A = torch.zeros(4 * kbig, dtype=torch.complex128, device="cuda")  # 4 x kbig, lda 4
+    B = torch.zeros(kbig * 4, dtype=torch.complex128, device="cuda")  # kbig x 4, ldb kbig
+    C = torch.zeros(16, dtype=torch.complex128, device="cuda")        # 4 x 4, ldc 4
     with pytest.raises(ozc.OzcError) as e:
-        handle.zgemm("N", "N", 4, 4, 4, 1.0, 1, 3, 1, 4, 0.0, 1, 4)  # lda < m
+        handle.zgemm("N", "N", 4, 4, 4, 1.0, A, 3, B, 4, 0.0, C, 4)  # lda < m
     assert e.value.status == 1
-    with pytest.raises(ozc.OzcError) as e:  # checked before any work: no memory is touched
-        handle.inspect(False, "N", "N", 4, 4, ozc.MAX_K + 1, 1, 4, 1, ozc.MAX_K + 1, ldc=4)
+    with pytest.raises(ozc.OzcError) as e:  # k above the INT32 limit: inspect does not chunk
+        handle.inspect(False, "N", "N", 4, 4, kbig, A, 4, B, kbig, C=C, ldc=4)
     assert e.value.status == 2
     with pytest.raises(ozc.OzcError) as e:
-        handle.gemm_vbatched([dict(transa="N", transb="N", m=4, n=4, k=ozc.MAX_K + 1, alpha=1.0,
-                                   beta=0.0, A=1, lda=4, B=1, ldb=ozc.MAX_K + 1, C=1, ldc=4)])
+        handle.gemm_vbatched([dict(transa="N", transb="N", m=4, n=4, k=kbig, alpha=1.0,
+                                   beta=0.0, A=A, lda=4, B=B, ldb=kbig, C=C, ldc=4)])
     assert e.value.status == 2
+    torch.cuda.synchronize()
+    assert not bool(torch.any(C != 0))
     with pytest.raises(ozc.OzcError):
         handle.set_config(25)
     handle.set_config(14)
@@ -235,6 +246,32 @@ def test_k_above_int32_limit_is_chunked(handle, orc, ta, tb):
     ref = orc.emulate(A[:, :half], B[:half], 14, alpha=alpha, beta=beta, C=C)["out"]
     ref = orc.emulate(A[:, half:], B[half:], 14, alpha=alpha, beta=1.0, C=ref)["out"]
     assert _same(got, ref)
+
+
+def test_k_chunks_keep_nonfinite_status(handle, orc):
+    """An inf in the first k-chunk (k = 2^17 + 1000: two chunks) still reports the
+    non-finite status after the last chunk, and the NaN rows and columns equal the
+    oracle's chunked result."""
+    import paper_2512_08321_amd as ozc
+
+    k = ozc.MAX_K + 1000
+    m, n = 6, 5
+    print(f"k-chunk nonfinite k={k}", flush=True)
+    A = workloads.complex_matrix(m, k, 0.5, 151)
+    B = workloads.complex_matrix(k, n, 0.5, 152)
+    A[2, 10] = complex(np.inf, 0.0)   # first chunk, row 2
+    B[20, 3] = complex(0.0, np.nan)   # first chunk, column 3
+    got = _gemm_call(handle, A, B, np.zeros((m, n)), 1.0, 0.0, 14)
+    info = handle.last_info()
+    assert info["nonfinite"] == 1
+    half = k // 2
+    ref = orc.emulate(A[:, :half], B[:half], 14)["out"]
+    ref = orc.emulate(A[:, half:], B[half:], 14, alpha=1.0, beta=1.0, C=ref)["out"]
+    assert _same(got, ref)
+    assert np.isnan(got[2, :].real).all() and np.isnan(got[:, 3].real).all()
+    # a clean call afterwards clears the flag
+    got = _gemm_call(handle, A[:, 100:], B[100:], np.zeros((m, n)), 1.0, 0.0, 14)
+    assert handle.last_info()["nonfinite"] == 0
 
 
 @pytest.mark.parametrize("algo", ["karatsuba", "4m"])
