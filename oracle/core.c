@@ -21,6 +21,8 @@
  *                       and the reduced E'_R, E'_I (Step V-iii/iv)
  *   orc_crt_output      S = sum_l s_l E'_l, C' = mod(S, P) exactly (Step V-v/vi),
  *                       C = ldexp(RNE(C'), -(mu+nu)) (Step VI), alpha/beta
+ *   orc_real_products,  the same two steps for real matrices (Algorithm 1 as
+ *   orc_real_crt_output stated): one product per modulus, one E' plane
  *   orc_dd_gemm         double-double complex product (the accuracy yardstick
  *                       of Section IV-A)
  * Thresholds for the exponent rules are evaluated by the Python layer with
@@ -256,6 +258,25 @@ void orc_products(const int8_t *resA, int64_t m, const int8_t *resB, int64_t n, 
     }
 }
 
+/* Real products (Algorithm 1 as stated for real A, B): resA [l][m][len] and resB [l][n][len]
+ * (the residues of A'_l and of the columns of B'_l) -> Ep [l][m][n] = mod(A'_l B'_l, p_l)
+ * (Step V-iii/iv); raw (optional) [l][m][n]: the integer products D'_l. */
+void orc_real_products(const int8_t *resA, int64_t m, const int8_t *resB, int64_t n, int64_t len,
+                       int nmod, const int32_t *p, int8_t *Ep, int64_t *raw) {
+    const int64_t pa = m * len, pb = n * len, pc = m * n;
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int l = 0; l < nmod; ++l) {
+        for (int64_t i = 0; i < m; ++i) {
+            const int8_t *a = resA + (int64_t)l * pa + i * len;
+            for (int64_t j = 0; j < n; ++j) {
+                const int64_t d = dot8(a, resB + (int64_t)l * pb + j * len, len);
+                Ep[(int64_t)l * pc + i * n + j] = (int8_t)smod64(d, p[l]);
+                if (raw) raw[(int64_t)l * pc + i * n + j] = d;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------ CRT (256-bit) */
 
 typedef struct { uint64_t w[4]; } u256; /* two's complement when used as signed */
@@ -388,6 +409,39 @@ void orc_crt_output(const int8_t *Ep, int64_t m, int64_t n, int nmod, const uint
             }
             out[2 * (i * n + j)] = orr;
             out[2 * (i * n + j) + 1] = oi;
+        }
+    }
+}
+
+/* Real output (Step V-v/vi, VI): Ep [l][m][n]; x = alpha * ldexp(RNE(C'), -(mu+nu)) (one
+ * rounding), out = x if beta == 0, else fma(beta, Cin, x).  Cin: m x n row-major or NULL;
+ * out: m x n row-major; Cp_out (optional): RNE(C'). */
+void orc_real_crt_output(const int8_t *Ep, int64_t m, int64_t n, int nmod, const uint64_t *s_words,
+                         const uint64_t *P_words, const int32_t *mu, const uint8_t *rowflag,
+                         const int32_t *nu, const uint8_t *colflag, double alpha, double beta,
+                         const double *Cin, double *out, double *Cp_out) {
+    u256 s[32], P;
+    for (int l = 0; l < nmod; ++l) memcpy(s[l].w, s_words + 4 * l, 32);
+    memcpy(P.w, P_words, 32);
+    long double Pld = u256_to_ld_signed(&P);
+    const int64_t pc = m * n;
+#pragma omp parallel for
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double c = 0.0;
+            if (rowflag[i] == 2 || colflag[j] == 2) {
+                c = NAN;
+            } else if (rowflag[i] == 1 && colflag[j] == 1) {
+                const int8_t *pl[32];
+                for (int l = 0; l < nmod; ++l) pl[l] = Ep + (int64_t)l * pc + i * n + j;
+                u256 R = crt_reduce(pl, nmod, s, &P, Pld);
+                double d = u256_to_double_rne(&R);
+                if (Cp_out) Cp_out[i * n + j] = d;
+                c = ldexp(d, -(mu[i] + nu[j]));
+            }
+            if (alpha == 0.0) c = 0.0;
+            double x = alpha * c;
+            out[i * n + j] = beta == 0.0 ? x : fma(beta, Cin[i * n + j], x);
         }
     }
 }

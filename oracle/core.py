@@ -254,6 +254,63 @@ def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, 
     return dict(mu=mu, nu=nu, fa=fa, fb=fb, resA=resA, resB=resB, Ep=Ep, raw=raw, Cp=cp, out=out)
 
 
+def emulate_real(A, B, n_moduli, mode="fast", alpha=1.0, beta=0.0, C=None, single=False,
+                 want_raw=False, exponents=None):
+    """alpha * A @ B + beta * C for real A (m, k), B (k, n) by Algorithm 1, computed exactly.
+
+    Scaling (Step III): a real row is scaled by the rule of Section III-B for a
+    row of k reals (the complex rule reads a row as its 2k reals; with no
+    imaginary parts both coincide), so the exponent routines run on the rows
+    with zero imaginary parts.  Steps IV-VI: a' = trunc(a 2^mu), one residue
+    plane per modulus, D'_l = A'_l B'_l, E'_l = mod(D'_l, p_l), C' = mod(sum_l
+    s_l E'_l, P) exactly, ldexp(RNE(C'), -(mu_i + nu_j)), then x = alpha c
+    (one rounding) and out = x (beta = 0) or fma(beta, C_in, x).  ``single``:
+    float32 inputs promoted exactly, the float64 result rounded once to float32.
+    """
+    lib = _load()
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    Are = np.ascontiguousarray(A)
+    Bre = np.ascontiguousarray(B.T)
+    Aim = np.zeros_like(Are)
+    Bim = np.zeros_like(Bre)
+    if exponents is not None:
+        mu, fa, nu, fb = exponents
+    elif mode == "fast":
+        mu, fa, _, _ = fast_exponents(Are, Aim, n_moduli)
+        nu, fb, _, _ = fast_exponents(Bre, Bim, n_moduli)
+    elif mode == "accurate":
+        mu, nu, fa, fb, _, _ = accurate_exponents(Are, Aim, Bre, Bim, n_moduli)
+    else:
+        raise ValueError(mode)
+    c = constants(n_moduli)
+    resA = np.ascontiguousarray(residues(Are, Aim, mu, fa, n_moduli)[:, 0])   # the real plane
+    resB = np.ascontiguousarray(residues(Bre, Bim, nu, fb, n_moduli)[:, 0])
+    m, ln = Are.shape
+    n = Bre.shape[0]
+    Ep = np.zeros((n_moduli, m, n), np.int8)
+    raw = np.zeros((n_moduli, m, n), np.int64) if want_raw else None
+    lib.orc_real_products(_p(resA), I64(m), _p(resB), I64(n), I64(ln), ctypes.c_int(n_moduli),
+                          _p(c["p_arr"]), _p(Ep), _p(raw) if raw is not None else None)
+    al, be = float(alpha), float(beta)
+    if single:
+        al, be = float(np.float32(al)), float(np.float32(be))
+    cin = None
+    if be != 0.0:
+        if C is None:
+            raise ValueError("beta != 0 needs C")
+        cin = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    out = np.zeros((m, n), np.float64)
+    lib.orc_real_crt_output(_p(Ep), I64(m), I64(n), ctypes.c_int(n_moduli), _p(c["s_words"]),
+                            _p(c["P_words"]), _p(mu.astype(np.int32)), _p(fa.astype(np.uint8)),
+                            _p(nu.astype(np.int32)), _p(fb.astype(np.uint8)), ctypes.c_double(al),
+                            ctypes.c_double(be), _p(cin) if cin is not None else None, _p(out),
+                            None)
+    if single:
+        out = out.astype(np.float32)
+    return dict(mu=mu, nu=nu, fa=fa, fb=fb, resA=resA, resB=resB, Ep=Ep, raw=raw, out=out)
+
+
 def set_threads(n: int) -> int:
     """Run the C loops on n OpenMP threads; returns the previous count."""
     lib = _load()

@@ -297,6 +297,67 @@ def emulate(A, B, n_moduli: int, mode: str = "fast", algo: str = "karatsuba",
                 prods=prods, Ep=Ep, Cp=(CpR, CpI), out=out)
 
 
+def emulate_real(A, B, n_moduli: int, mode: str = "fast", alpha: float = 1.0, beta: float = 0.0,
+                 C=None):
+    """C = alpha * A @ B + beta * C for real matrices by Algorithm 1, exactly.
+
+    A: m lists of k floats; B: k lists of n floats.  Step I/II: moduli and CRT
+    constants; Step III: fast mode by the Cauchy-Schwarz rule on the k reals of a
+    row (Section II; Section III-B states the same rule for the 2k reals of a
+    complex row), accurate mode with the bound Abar Bbar of the 7-bit ceilings;
+    Step IV: a' = trunc(a 2^mu); Step V: residues, D'_l = A'_l B'_l,
+    E'_l = mod(D'_l, p_l), S = sum_l s_l E'_l, C' = mod(S, P); Step VI:
+    ldexp(C', -(mu_i + nu_j)) rounded to nearest, x = alpha c, and
+    out = x (beta = 0) or fma(beta, C_in, x).
+    """
+    m, k = len(A), len(B)
+    n = len(B[0]) if B else 0
+    p, P, q, s = crt_constants(n_moduli)
+    if mode == "fast":
+        mu = [fast_exponent(list(A[i]), P)[0] for i in range(m)]
+        nu = [fast_exponent([B[h][j] for h in range(k)], P)[0] for j in range(n)]
+    elif mode == "accurate":
+        def row_exp(vals):
+            nz = [v for v in vals if v != 0.0]
+            return max(ufp_exponent(v) for v in nz) if nz else None
+        eA = [row_exp(list(A[i])) for i in range(m)]
+        eB = [row_exp([B[h][j] for h in range(k)]) for j in range(n)]
+        Ab = [[ceil7(A[i][h], eA[i]) if eA[i] is not None else 0 for h in range(k)] for i in range(m)]
+        Bb = [[ceil7(B[h][j], eB[j]) if eB[j] is not None else 0 for j in range(n)] for h in range(k)]
+        Cb = [[sum(Ab[i][h] * Bb[h][j] for h in range(k)) for j in range(n)] for i in range(m)]
+        X = [max(Cb[i], default=0) for i in range(m)]
+        Y = [max([Cb[i][j] for i in range(m)], default=0) for j in range(n)]
+        base = ACCU_INT_BITS - 1
+        mu = [None if (eA[i] is None or X[i] == 0) else base - eA[i] + accurate_t(X[i], P)
+              for i in range(m)]
+        nu = [None if (eB[j] is None or Y[j] == 0) else base - eB[j] + accurate_t(Y[j], P)
+              for j in range(n)]
+    else:
+        raise ValueError(mode)
+    Ai = [[trunc_scaled(A[i][h], mu[i]) for h in range(k)] for i in range(m)]
+    Bi = [[trunc_scaled(B[h][j], nu[j]) for j in range(n)] for h in range(k)]
+    Ep, prods = [], []
+    for pl in p:
+        Al = [[smod(Ai[i][h], pl) for h in range(k)] for i in range(m)]
+        Bl = [[smod(Bi[h][j], pl) for j in range(n)] for h in range(k)]
+        D = [[sum(Al[i][h] * Bl[h][j] for h in range(k)) for j in range(n)] for i in range(m)]
+        prods.append(D)
+        Ep.append([[smod(D[i][j], pl) for j in range(n)] for i in range(m)])
+    Cp = [[smod(sum(s[l] * Ep[l][i][j] for l in range(n_moduli)), P) for j in range(n)]
+          for i in range(m)]
+    out = []
+    for i in range(m):
+        row = []
+        for j in range(n):
+            c = 0.0
+            if mu[i] is not None and nu[j] is not None:
+                c = math.ldexp(float(Cp[i][j]), -(mu[i] + nu[j]))
+            x = float(alpha) * c
+            row.append(x if beta == 0 else fma(float(beta), float(C[i][j]), x))
+        out.append(row)
+    return dict(p=p, P=P, mu=mu, nu=nu, Ai=Ai, Bi=Bi, prods=prods, Ep=Ep, Cp=Cp, out=out)
+
+
 def exact_product(A, B):
     """Exact rational complex product A @ B (brute force, for tiny matrices)."""
     m, k = len(A), len(B)
