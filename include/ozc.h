@@ -141,6 +141,28 @@ ozc_status_t ozc_cgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, in
                        int64_t lda, const void *B, int64_t ldb, const float beta[2],
                        void *C, int64_t ldc);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): ozc_zgemm with the workspace
+ * taken from a fixed array of OZC_NOALLOC_WORKSPACE bytes that the library holds
+ * in device memory, one per device, from the first ozc_create on that device until
+ * the process ends.  Same arguments, semantics and results (bit for bit) as
+ * ozc_zgemm with the handle's fixed moduli count, mode and algorithm; the call
+ * allocates nothing and enqueues only kernels on the handle's stream.
+ * Errors: those of ozc_zgemm's argument checks; NOT_SUPPORTED, before any work,
+ * when the shape needs more workspace than the array holds (ozc_workspace_size
+ * above OZC_NOALLOC_WORKSPACE: e.g. m = n = k = 700 at 14 moduli, Karatsuba, fits)
+ * or when the handle has the Freivalds check or the learned moduli count
+ * configured (both need buffers of their own); HIP_ERROR when the array's device
+ * address could not be looked up.  Phase timing is not recorded.  Every call on a
+ * device shares that device's array and leaves its contents behind (nothing in it
+ * is assumed zero at entry): calls that overlap in time on one device, from any
+ * handle or stream, race and give wrong results. */
+#define OZC_NOALLOC_WORKSPACE ((size_t)64 << 20)
+ozc_status_t ozc_zgemm_noalloc(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb,
+                               int64_t m, int64_t n, int64_t k, const double alpha[2],
+                               const void *A, int64_t lda, const void *B, int64_t ldb,
+                               const double beta[2], void *C, int64_t ldc);
+
 /* Intermediates of the pipeline for alpha = 1, beta = 0, for verification.
  * `single` = 0: complex128 inputs, 1: complex64.  Output buffers are device
  * memory owned by the caller; any of them may be NULL.  Layouts (dense):

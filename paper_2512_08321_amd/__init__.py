@@ -16,8 +16,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Handle", "OzcError", "gemm", "lib", "OP", "MODE", "ALGO", "MAX_K", "MIN_MODULI",
-           "MAX_MODULI", "EXP_ZERO", "EXP_NONFINITE", "library_path"]
+__all__ = ["Handle", "OzcError", "gemm", "lib", "OP", "MODE", "ALGO", "MAX_K", "NOALLOC_WORKSPACE",
+           "MIN_MODULI", "MAX_MODULI", "EXP_ZERO", "EXP_NONFINITE", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.environ.get("OZC_LIBRARY") or os.path.join(_HERE, "libozc.so")
@@ -26,6 +26,7 @@ OP = {"N": 0, "T": 1, "C": 2}
 MODE = {"fast": 0, "accurate": 1}
 ALGO = {"karatsuba": 0, "4m": 1}
 MAX_K = 131072
+NOALLOC_WORKSPACE = 64 << 20   # bytes of the fixed workspace of ozc_zgemm_noalloc
 MIN_MODULI, MAX_MODULI = 2, 24
 EXP_ZERO, EXP_NONFINITE = -32768, 32767
 
@@ -71,6 +72,8 @@ EXPORTS = {
     "ozc_set_workspace": [_VP, _VP, ctypes.c_size_t],
     "ozc_zgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _D2, _VP, _I64, _VP, _I64, _D2, _VP, _I64],
     "ozc_cgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _F2, _VP, _I64, _VP, _I64, _F2, _VP, _I64],
+    "ozc_zgemm_noalloc": [_VP, _INT, _INT, _I64, _I64, _I64, _D2, _VP, _I64, _VP, _I64, _D2, _VP,
+                          _I64],
     "ozc_inspect": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _VP,
                     _VP, _VP, _VP, _VP, _I64],
     "ozc_last_info": [_VP, ctypes.POINTER(Info)],
@@ -182,6 +185,15 @@ class Handle:
         _check(lib().ozc_zgemm(self._h, OP[transa], OP[transb], m, n, k, _D2(a.real, a.imag),
                                _ptr(A), lda, _ptr(B), ldb, _D2(b.real, b.imag), _ptr(C), ldc),
                "ozc_zgemm")
+
+    def zgemm_noalloc(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                      stream=None):
+        """ozc_zgemm_noalloc: ozc_zgemm on the library's fixed device workspace."""
+        self.set_stream(stream)
+        a, b = complex(alpha), complex(beta)
+        _check(lib().ozc_zgemm_noalloc(self._h, OP[transa], OP[transb], m, n, k,
+                                       _D2(a.real, a.imag), _ptr(A), lda, _ptr(B), ldb,
+                                       _D2(b.real, b.imag), _ptr(C), ldc), "ozc_zgemm_noalloc")
 
     def cgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
         self.set_stream(stream)

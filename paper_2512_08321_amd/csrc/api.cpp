@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,6 +14,35 @@
 using namespace ozc;
 
 namespace {
+
+// Workspace of ozc_zgemm_noalloc: a fixed array in device memory, one copy per device,
+// loaded with the code object and held until the process ends.  Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device (with that device current) when the
+// first handle on it is created.
+static __device__ __align__(256) unsigned char scratch[OZC_NOALLOC_WORKSPACE];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+
+// The calling thread's current device is `device`.
+hipError_t fixed_workspace(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        }
+        g_fixed_ptr[device] = p;
+    }
+    *out = g_fixed_ptr[device];
+    return hipSuccess;
+}
 
 
 struct Layout {
@@ -59,6 +89,11 @@ Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool w
 
 
 ozc_status_t ensure_workspace(ozc_context *h, size_t bytes, char **ws) {
+    if (h->use_fixed) {  // checked against the size before any work was enqueued
+        if (!h->ws_fixed || bytes > (size_t)OZC_NOALLOC_WORKSPACE) return OZC_STATUS_NOT_SUPPORTED;
+        *ws = (char *)h->ws_fixed;
+        return OZC_STATUS_SUCCESS;
+    }
     if (h->ws_user) {
         if (bytes > h->ws_user_bytes) return OZC_STATUS_ALLOC_FAILED;
         *ws = (char *)h->ws_user;
@@ -242,7 +277,7 @@ struct PhaseEvents {
     ozc_context *h;
     std::array<hipEvent_t, 5> ev{};
     bool on;
-    PhaseEvents(ozc_context *ctx) : h(ctx), on(ctx->profiling) {
+    PhaseEvents(ozc_context *ctx) : h(ctx), on(ctx->profiling && !ctx->use_fixed) {
         if (!on) return;
         for (auto &e : ev) {
             if (!h->event_pool.empty()) {
@@ -583,6 +618,8 @@ ozc_status_t ozc_create(ozc_handle_t *handle, int device) {
         delete h;
         return OZC_STATUS_HIP_ERROR;
     }
+    // The fixed workspace of ozc_zgemm_noalloc; a failed lookup only disables that call.
+    if (fixed_workspace(device, &h->ws_fixed) != hipSuccess) h->ws_fixed = nullptr;
     *handle = h;
     return OZC_STATUS_SUCCESS;
 }
@@ -648,6 +685,29 @@ ozc_status_t ozc_zgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int6
                        int64_t ldb, const double beta[2], void *C, int64_t ldc) {
     if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
     return run_verified(h, false, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+ozc_status_t ozc_zgemm_noalloc(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
+                               int64_t k, const double alpha[2], const void *A, int64_t lda,
+                               const void *B, int64_t ldb, const double beta[2], void *C,
+                               int64_t ldc) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
+    ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    // the check and the learned count need buffers of their own
+    if (h->verify || h->auto_n) return OZC_STATUS_NOT_SUPPORTED;
+    if (!h->ws_fixed) return OZC_STATUS_HIP_ERROR;
+    size_t need = 0;
+    st = ozc_workspace_size(h, ta, tb, m, n, k, &need);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    if (need > (size_t)OZC_NOALLOC_WORKSPACE) return OZC_STATUS_NOT_SUPPORTED;
+    struct UseFixed {
+        ozc_context *h;
+        ~UseFixed() { h->use_fixed = false; }
+    } restore{h};
+    h->use_fixed = true;
+    return run(h, false, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
 }
 
 ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,

@@ -22,6 +22,8 @@ struct ozc_context {
     size_t ws_own_bytes = 0;
     void *ws_user = nullptr;
     size_t ws_user_bytes = 0;
+    void *ws_fixed = nullptr;           // this device's fixed workspace array (ozc_zgemm_noalloc)
+    bool use_fixed = false;             // set only while ozc_zgemm_noalloc runs
     ozc::NTable *tab_dev = nullptr;          // kMaxModuli tables, index N - 1
     std::vector<ozc::NTable> tab_host;
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met

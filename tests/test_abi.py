@@ -39,3 +39,12 @@ def test_status_strings_and_no_device_errors():
     assert lib.ozc_last_info(None, None) == 6
     h = ctypes.c_void_p()
     assert lib.ozc_create(None, 0) == 1
+
+
+def test_header_constants_match_binding():
+    import paper_2512_08321_amd as ozc
+
+    text = open(os.path.join(ROOT, "include", "ozc.h")).read()
+    m = re.search(r"#define OZC_NOALLOC_WORKSPACE \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == ozc.NOALLOC_WORKSPACE
+    assert re.search(r"#define OZC_MAX_K (\d+)", text).group(1) == str(ozc.MAX_K)
