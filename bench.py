@@ -87,17 +87,24 @@ def main():
     ap.add_argument("--verify", action="store_true",
                     help="enable the Freivalds check on every call (its cost shows in ms/step)")
     ap.add_argument("--workload", default="zgemm",
-                    choices=["zgemm", "batch", "batch-auto", "learned-n", "vendor-int8",
-                             "vendor-complex"],
+                    choices=["zgemm", "dgemm", "batch", "batch-auto", "learned-n", "vendor-int8",
+                             "vendor-complex", "vendor-real"],
                     help="zgemm: one large product (default); batch: 512 uneven products; "
                          "batch-auto: the same with the learned moduli count; learned-n: "
                          "held-out evaluation of the moduli-count predictor on square "
                          "products (n up to 1024, k up to 16384); vendor-int8: the "
                          "vendor's INT8 GEMM (torch._int_mm) on size^3 int8 operands, for "
-                         "comparison with one residue product")
+                         "comparison with one residue product; dgemm: real products "
+                         "(ozc_dgemm, or ozc_sgemm with --single); vendor-real: the vendor's "
+                         "DGEMM / SGEMM on the same shape")
     ap.add_argument("--train-count", type=int, default=2000,
                     help="batch-auto, learned-n: training instances")
     ap.add_argument("--heldout-count", type=int, default=200, help="learned-n: held-out instances")
+    ap.add_argument("--n-range", type=int, nargs=2, default=[256, 1024],
+                    help="learned-n: m = n log-uniform in this range (the full learned-N "
+                         "workload: 256 4096)")
+    ap.add_argument("--k-range", type=int, nargs=2, default=[256, 16384],
+                    help="learned-n: k log-uniform in this range (full workload: 256 65536)")
     ap.add_argument("--margin", type=int, default=2,
                     help="batch-auto: moduli added to each prediction (2 meets the target on "
                          "every problem of the batch, as the fixed count does)")
@@ -124,6 +131,10 @@ def main():
         return bench_vendor_complex(args)
     if args.workload == "vendor-int8":
         return bench_vendor_int8(args)
+    if args.workload == "dgemm":
+        return bench_real(args)
+    if args.workload == "vendor-real":
+        return bench_vendor_real(args)
 
     import numpy as np
     import torch
@@ -432,6 +443,132 @@ def bench_vendor_complex(args):
                       "config": {"workload": f"{name} {m}x{n}x{k} (torch.matmul)"}}), flush=True)
 
 
+def real_matrix_torch(rows, cols, phi, seed, dtype):
+    """Column-major rows x cols real matrix (held as a (cols, rows) tensor) with entries
+    (u - 0.5) exp(phi g): the real parts of the complex generator's draw."""
+    import workloads
+
+    z = workloads.complex_matrix_torch(rows, cols, phi, seed)
+    out = z.real.to(dtype).contiguous()
+    del z
+    return out
+
+
+def bench_real(args):
+    """Real products (Algorithm 1 for real matrices): one ozc_dgemm (ozc_sgemm with
+    --single) call per step, 2mnk/t, the residue-product kernel's roofline (2 N m n k INT8
+    operations per launch) and a bit-exact sample against the oracle's real path."""
+    import numpy as np
+    import torch
+
+    import paper_2512_08321_amd as ozc
+    import workloads
+
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    N = args.moduli
+    dt = torch.float32 if args.single else torch.float64
+    kind = "SGEMM" if args.single else "DGEMM"
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {kind} {m}x{n}x{k} inputs (phi={args.phi}) on the device")
+    A = real_matrix_torch(m, k, args.phi, workloads.seed_for(6, 0, "A"), dt)
+    B = real_matrix_torch(k, n, args.phi, workloads.seed_for(6, 0, "B"), dt)
+    C = torch.zeros((n, m), dtype=dt, device="cuda")
+    torch.cuda.synchronize()
+    h = ozc.Handle(0, num_moduli=N, mode=args.mode)
+    call = h.sgemm if args.single else h.dgemm
+
+    def step():
+        call("N", "N", m, n, k, 1.0, A, m, B, k, 0.0, C, m)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_read()
+    h.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = h.profile_read()
+    h.set_profiling(False)
+    value = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+    ops_launch = 2.0 * N * m * n * k
+    gemm_ms = prof["gemm_ms"] / max(1, prof["calls"])
+    achieved = ops_launch / (gemm_ms * 1e-3) / 1e12
+    log(f"[bench] {kind}: {ms:.2f} ms/step, {value:.1f} TFLOPS, products {gemm_ms:.2f} ms "
+        f"({achieved:.0f} TOPS)")
+
+    rng = np.random.default_rng(54321)
+    sr = np.unique(np.concatenate([[0, m - 1], rng.choice(m, size=min(m, 256) - 2, replace=False)]))
+    sc = np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=min(n, 256) - 2, replace=False)]))
+    A_rows = A[:, torch.from_numpy(sr).cuda()].T.cpu().numpy().astype(np.float64)
+    B_cols = B[torch.from_numpy(sc).cuda(), :].T.cpu().numpy().astype(np.float64)
+    C_smp = C[torch.from_numpy(sc).cuda()][:, torch.from_numpy(sr).cuda()].T.cpu().numpy()
+    from oracle import core
+
+    hi, lo = core.dd_gemm(A_rows.astype(np.complex128), B_cols.astype(np.complex128))
+    absab = core.abs_product(A_rows.astype(np.complex128), B_cols.astype(np.complex128))
+    err = core.err_nc(C_smp.astype(np.complex128), hi, lo, absab)
+    parity = None
+    if args.mode == "fast":
+        ref = core.emulate_real(A_rows, B_cols, N, single=args.single)["out"]
+        parity = {"entries": int(ref.size), "bit_exact": bool(np.array_equal(ref, C_smp)),
+                  "mismatches": int(np.sum(ref != C_smp))}
+    bound = 4 * k * (2.0 ** -24 if args.single else 2.0 ** -53)
+    print(json.dumps({
+        "metric": f"emulated {kind} eff. TFLOPS (2mnk/t) at err<=bound; INT8 MFMA util %",
+        "value": round(value, 3), "unit": "TFLOPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": f"{kind} {m}x{n}x{k}, {N} moduli, {args.mode} mode, "
+                               f"phi={args.phi}, alpha=1, beta=0", "m": m, "n": n, "k": k,
+                   "moduli": N, "mode": args.mode, "phi": args.phi},
+        "err_nc_sample": err, "err_bound": bound, "err_ok": err <= bound,
+        "parity_sample": parity,
+        "phase_ms": {key: round(prof[key] / max(1, prof["calls"]), 4)
+                     for key in ("scale_ms", "split_ms", "gemm_ms", "crt_ms", "total_ms")},
+        "roofline": {"bound": "mfma", "kernel": "residue_gemm_kernel", "achieved": round(achieved, 2),
+                     "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None},
+    }), flush=True)
+    h.close()
+
+
+def bench_vendor_real(args):
+    """The vendor DGEMM (SGEMM with --single) through torch.matmul on the same shape."""
+    import torch
+
+    torch.cuda.set_device(0)
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    dt = torch.float32 if args.single else torch.float64
+    A = real_matrix_torch(m, k, args.phi, 6000, dt)
+    B = real_matrix_torch(k, n, args.phi, 6001, dt)
+    At, Bt = A.t(), B.t()
+    for _ in range(args.warmup):
+        C = torch.matmul(At, Bt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C = torch.matmul(At, Bt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tflops = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+    name = "SGEMM" if args.single else "DGEMM"
+    log(f"[bench] vendor {name} {m}x{n}x{k}: {ms:.3f} ms, {tflops:.1f} TFLOPS")
+    del C
+    print(json.dumps({"metric": f"vendor {name} TFLOPS (2mnk/t)", "value": round(tflops, 3),
+                      "unit": "TFLOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32" if args.single else "f64",
+                      "data": "synthetic",
+                      "config": {"workload": f"{name} {m}x{n}x{k} (torch.matmul)"}}), flush=True)
+
+
 def uneven_batch(count, seed_base):
     """The 512-problem workload: m, n, k log-uniform in [64, 2048], phi uniform in [0, 4]."""
     import math
@@ -458,10 +595,10 @@ def uneven_batch(count, seed_base):
 
 def bench_batch_auto(args):
     """Learned moduli count plus batching against the plain fixed-count path on the
-    512-problem uneven batch: training instances from the same distribution are
-    labelled by the emulation itself (smallest N meeting the target), the fixed
-    count is the 99.9% quantile of those labels, and every output's error against
-    the 24-moduli result is measured."""
+    512-problem uneven batch: training instances from the same distribution get
+    certified labels (smallest N whose error bound meets the target), the fixed
+    count is the 99.9% quantile of those labels, and every output's certified error
+    bound is measured."""
     import numpy as np
     import torch
 
@@ -511,21 +648,14 @@ def bench_batch_auto(args):
     for q in probs:
         Ns.append(h.predict_moduli("N", "N", q["m"], q["n"], q["k"], q["A"], q["lda"], q["B"],
                                    q["ldb"]))
-    log("[bench] measuring errors against the 24-moduli results")
+    log("[bench] measuring certified errors (24-moduli reference and its bound)")
     met_fixed = met_auto = 0
     worst_auto = 0.0
     for q, cf, ca in zip(probs, out_fixed, out_auto):
         inst = dict(m=q["m"], n=q["n"], k=q["k"], A=q["A"], B=q["B"])
-        ref = torch.empty_like(cf)
-        autoN._emulate(h, inst, autoN.MAX_N, ref)
-        absA = torch.complex(q["A"].abs(), torch.zeros_like(q["A"].real))
-        absB = torch.complex(q["B"].abs(), torch.zeros_like(q["B"].real))
-        den = torch.empty_like(cf)
-        h.set_config(16, "fast", "karatsuba")
-        h.zgemm("N", "N", q["m"], q["n"], q["k"], 1.0, absA, q["m"], absB, q["k"], 0.0, den, q["m"])
-        d = den.real.clamp_min(torch.finfo(torch.float64).tiny)
-        ef = float(((cf - ref).abs() / d).max())
-        ea = float(((ca - ref).abs() / d).max())
+        ref = autoN.Reference(h, inst)
+        ef = ref.error(cf)
+        ea = ref.error(ca)
         met_fixed += ef <= target
         met_auto += ea <= target
         worst_auto = max(worst_auto, ea)
@@ -585,11 +715,12 @@ def bench_batch_auto(args):
 
 def bench_learned_n(args):
     """The moduli-count predictor on held-out instances of the learned-N workload
-    (square products, n log-uniform in [256, 1024], k in [256, 16384], phi uniform in
-    [0, 8], power-of-two skews along k): label accuracy, escalation rate and the
-    verified throughput of single calls with the learned count against the fixed
-    count.  Labels and errors come from the emulation itself (smallest N meeting the
-    target against the 24-moduli result)."""
+    (square products, n log-uniform in --n-range, k in --k-range, phi uniform in
+    [0, 8], power-of-two skews along k up to 2^40): label accuracy, escalation rate and
+    the verified throughput of single calls with the learned count against the fixed
+    count.  Labels and errors are certified by the library (24-moduli reference plus
+    the bound of its own error); every held-out result is also compared on a sampled
+    8 x 8 block with the oracle's double-double product."""
     import numpy as np
     import torch
 
@@ -600,7 +731,20 @@ def bench_learned_n(args):
     torch.cuda.set_device(0)
     h = ozc.Handle(0)
     target = args.target
-    kw = dict(lo=256, hi=1024, klo=256, khi=16384, phi_max=8.0, skew_max=40, square=True)
+    kw = dict(lo=args.n_range[0], hi=args.n_range[1], klo=args.k_range[0], khi=args.k_range[1],
+              phi_max=8.0, skew_max=40, square=True)
+    from oracle import core
+
+    def dd_check(inst, C):
+        """max err/(|A||B|) of the result on a sampled 8 x 8 block against double-double."""
+        srng = np.random.default_rng(inst["m"] * 7919 + inst["k"])
+        r = np.sort(srng.choice(inst["m"], size=min(8, inst["m"]), replace=False))
+        c = np.sort(srng.choice(inst["n"], size=min(8, inst["n"]), replace=False))
+        A_rows = inst["A"][:, torch.from_numpy(r).cuda()].T.cpu().numpy()
+        B_cols = inst["B"][torch.from_numpy(c).cuda(), :].T.cpu().numpy()
+        got = C[torch.from_numpy(c).cuda()][:, torch.from_numpy(r).cuda()].T.cpu().numpy()
+        hi, lo = core.dd_gemm(A_rows, B_cols)
+        return core.err_nc(got, hi, lo, core.abs_product(A_rows, B_cols))
     log(f"[bench] labelling {args.train_count} training instances (target {target:g})")
     t0 = time.perf_counter()
     X, y, meta = autoN.generate(h, args.train_count, seed=workloads.seed_for(5, 0, "A"),
@@ -643,7 +787,7 @@ def bench_learned_n(args):
         h.set_auto_moduli(fallback=n_fix, margin=0)
         raw = h.predict_moduli("N", "N", m, n, k, inst["A"], m, inst["B"], k)
         h.set_auto_moduli(fallback=n_fix, margin=args.margin)
-        ev = autoN.evaluate(h, [inst], target, margin=args.margin)[0]
+        ev = autoN.evaluate(h, [inst], target, margin=args.margin, check=dd_check)[0]
         h.set_auto_moduli(fallback=n_fix, margin=args.margin)
         tf, info_f = timed_call(inst, n_fix)
         ta, info_a = timed_call(inst, 0)
@@ -651,7 +795,8 @@ def bench_learned_n(args):
         t_fix += tf
         t_auto += ta
         rows.append(dict(label=lab, raw=raw, N_hat=ev["N_hat"], N_used=ev["N_used"], esc=ev["esc"],
-                         err=ev["err"], status=ev["status"], fix_status_ok=info_f["escalations"] == 0))
+                         err=ev["err"], err_dd=ev["check"], status=ev["status"],
+                         fix_status_ok=info_f["escalations"] == 0))
         if (i + 1) % max(1, args.heldout_count // 10) == 0:
             log(f"[bench] {i + 1}/{args.heldout_count} held-out instances evaluated")
     H = len(rows)
@@ -664,6 +809,8 @@ def bench_learned_n(args):
            "over": round(float(np.mean(raw > lab)), 4)}
     esc_rate = float(np.mean([r["esc"] > 0 for r in rows]))
     met = int(sum(r["err"] <= target for r in rows))
+    met_dd = int(sum(r["err_dd"] <= target for r in rows))
+    under = [r for r in rows if r["N_used"] < r["label"]]
     value = flops / t_auto / 1e12
     log(f"[bench] held-out {H}: raw prediction exact {acc['exact']:.3f}, within 1 "
         f"{acc['within_1']:.3f}, under {acc['under']:.3f}; with margin {args.margin}: mean N "
@@ -682,17 +829,26 @@ def bench_learned_n(args):
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
-        "config": {"workload": f"{H} held-out square ZGEMMs, n log-uniform in [256, 1024], k in "
-                               f"[256, 16384], phi uniform in [0, 8], power-of-two skews along k; "
+        "config": {"workload": f"{H} held-out square ZGEMMs, n log-uniform in "
+                               f"[{kw['lo']}, {kw['hi']}], k in [{kw['klo']}, {kw['khi']}], phi "
+                               f"uniform in [0, 8], power-of-two skews along k up to 2^40; "
                                f"predictor trained on {args.train_count} instances of the same "
-                               f"distribution labelled at max err/(|A||B|) <= {target:g}"},
+                               f"distribution with certified labels at max err/(|A||B|) <= "
+                               f"{target:g}"},
         "fixed_rule_N": n_fix,
         "margin": args.margin,
         "mean_label_N": round(float(lab.mean()), 3),
         "mean_N_used": round(float(used.mean()), 3),
         "raw_prediction_accuracy": acc,
         "escalation_rate": round(esc_rate, 4),
-        "target_met": {"learned": met, "of": H},
+        "target_met": {"learned": met, "of": H,
+                       "measure": "certified bound of max_ij err/(|A||B|)_ij over all entries"},
+        "per_entry_miss_rate": round(1.0 - met / H, 4),
+        "target_met_dd_sample": {"learned": met_dd, "of": H,
+                                 "measure": "max err/(|A||B|) on a sampled 8 x 8 block against "
+                                            "the oracle's double-double product"},
+        "under_predicted": {"count": len(under),
+                            "missed_target": int(sum(r["err"] > target for r in under))},
         "verified_ms": {"learned": round(t_auto * 1e3, 3), "fixed": round(t_fix * 1e3, 3)},
         "speedup_vs_fixed": round(t_fix / t_auto, 3),
     }

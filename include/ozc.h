@@ -141,6 +141,26 @@ ozc_status_t ozc_cgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, in
                        int64_t lda, const void *B, int64_t ldb, const float beta[2],
                        void *C, int64_t ldc);
 
+/* Real products, C := alpha op(A) op(B) + beta C for float64 (dgemm) and float32
+ * (sgemm) matrices: Algorithm 1 as the paper states it for real A and B
+ * (Section II), with the scaling rules of Section III-B applied to rows of k
+ * reals and one INT8 product per modulus (2 N m n k INT8 operations),
+ * E'_l = mod(A'_l B'_l, p_l), exact reconstruction as for complex products.
+ * Same layout, argument checks, k-chunking, quick returns and non-finite
+ * handling as ozc_zgemm; op C is op T.  alpha, beta: host pointers to one
+ * value.  Result: c_ij = ldexp(RNE(C'_ij), -(mu_i + nu_j)); x = alpha c (one
+ * rounding); out = x if beta == 0, else fma(beta, C_ij, x).  sgemm promotes the
+ * inputs exactly to double, computes this in double and rounds once to float.
+ * Uses the handle's fixed moduli count and scaling mode (the product-form
+ * setting does not apply); the Freivalds check and the learned moduli count are
+ * not run for real products. */
+ozc_status_t ozc_dgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, int64_t m,
+                       int64_t n, int64_t k, const double *alpha, const void *A, int64_t lda,
+                       const void *B, int64_t ldb, const double *beta, void *C, int64_t ldc);
+ozc_status_t ozc_sgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, int64_t m,
+                       int64_t n, int64_t k, const float *alpha, const void *A, int64_t lda,
+                       const void *B, int64_t ldb, const float *beta, void *C, int64_t ldc);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): ozc_zgemm with the workspace
  * taken from a fixed array of OZC_NOALLOC_WORKSPACE bytes that the library holds
@@ -164,16 +184,18 @@ ozc_status_t ozc_zgemm_noalloc(ozc_handle_t handle, ozc_op_t transa, ozc_op_t tr
                                const double beta[2], void *C, int64_t ldc);
 
 /* Intermediates of the pipeline for alpha = 1, beta = 0, for verification.
- * `single` = 0: complex128 inputs, 1: complex64.  Output buffers are device
+ * `single` = element kind of A, B and C: 0 complex128, 1 complex64, 2 float64,
+ * 3 float32 (2 and 3 as ozc_dgemm / ozc_sgemm).  Output buffers are device
  * memory owned by the caller; any of them may be NULL.  Layouts (dense):
  *   mu     int16[m]   nu int16[n]   (exponents or the OZC_EXP_* sentinels)
  *   resA   int8[N][planes][m][k]    residues of the rows of op(A)
  *   resB   int8[N][planes][n][k]    residues of the columns of op(B)
- *          planes: Karatsuba 3 (re, im, re+im reduced), 4M 2 (re, im)
+ *          planes: Karatsuba 3 (re, im, re+im reduced), 4M 2 (re, im), real 1
  *   prods  int32[N][nprod][n][m]    raw INT32 products per modulus, each
- *          plane column-major: Karatsuba (D, E, F) = (RR, II, SS); 4M (RR, II, RI, IR)
- *   eprime int8[N][2][n][m]         E'_R, E'_I per modulus, column-major
- *   C      m x n output (ldc) as ozc_zgemm/ozc_cgemm would write it.
+ *          plane column-major: Karatsuba (D, E, F) = (RR, II, SS); 4M (RR, II, RI, IR);
+ *          real 1 (A'_l B'_l)
+ *   eprime int8[N][eplanes][n][m]   E'_R, E'_I per modulus (real: E'), column-major
+ *   C      m x n output (ldc) as ozc_zgemm/ozc_cgemm/ozc_dgemm/ozc_sgemm would write it.
  * Same validity rules and errors as ozc_zgemm. */
 ozc_status_t ozc_inspect(ozc_handle_t handle, int single, ozc_op_t transa, ozc_op_t transb,
                          int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
@@ -329,11 +351,16 @@ ozc_status_t ozc_batch_tune(ozc_handle_t handle, int single, int count, const oz
                         OZC_MLP_CLASSES * OZC_MLP_HIDDEN + OZC_MLP_CLASSES + 2 * OZC_MLP_FEATURES)
 
 /* Statistics of op(A) (m x k) and op(B) (k x n) into `features` (device, 20
- * floats): log2 m, log2 n, log2 k; min, max, mean, std over the nonzero rows
- * of op(A) of l2 = 0.5 log2 sum (|x| 2^-e)^2 and of l1 = log2 sum |x| 2^-e
- * (the 2k reals of a row, e = floor(log2 max |x|), as in the scaling step of
- * Section III-B); the same over the columns of op(B); the fraction of zero
- * reals.  m, n, k >= 1.  Asynchronous. */
+ * floats), taken from the integer sums of the fast-mode scaling step (Section
+ * III-B): for a row (the 2k reals of a row of op(A) or a column of op(B)) with
+ * e = floor(log2 max |x|), sigma = sum ceil(|x| 2^(20-e))^2 and tau = sum
+ * ceil(|x| 2^(20-e)), l2 = 0.5 log2 sigma - 20 and l1 = log2 tau - 20.
+ * Features: log2 m, log2 n, log2 k; min, max, mean, std of l2 and of l1 over the
+ * nonzero finite rows of op(A); the same over the columns of op(B); the
+ * fraction of zero reals.  k above OZC_MAX_K: the statistics of the first
+ * k-chunk of the call (log2 k is that chunk's).  m, n, k >= 1.  Asynchronous.
+ * A call with the learned moduli count computes these in its own scaling pass
+ * and reuses that pass's maxima and sums for the product itself. */
 ozc_status_t ozc_features(ozc_handle_t handle, int single, ozc_op_t transa, ozc_op_t transb,
                           int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
                           const void *B, int64_t ldb, float *features);
@@ -346,6 +373,12 @@ ozc_status_t ozc_mlp_get_params(ozc_handle_t handle, float *params, int count);
 /* Logits (device, rows x OZC_MLP_CLASSES) for feature rows X (device, rows x
  * OZC_MLP_FEATURES).  Asynchronous. */
 ozc_status_t ozc_mlp_forward(ozc_handle_t handle, const float *X, int rows, float *logits);
+
+/* Classes (device int, rows) of feature rows X (device, rows x OZC_MLP_FEATURES): the
+ * argmax of the logits ozc_mlp_forward computes (lowest class on ties), in one fused
+ * launch that runs the same operations in the same order (the launch the per-call
+ * prediction uses).  Asynchronous. */
+ozc_status_t ozc_mlp_predict(ozc_handle_t handle, const float *X, int rows, int *classes);
 
 /* Gradient (device, OZC_MLP_PARAMS floats; zero for mu, sd) of the mean softmax
  * cross-entropy over rows X with labels y (device int, classes) at the current

@@ -1,15 +1,20 @@
-"""CPU reference of the statistics fed to the moduli-count predictor (FP64).
+"""CPU reference of the statistics fed to the moduli-count predictor.
 
-TEST INFRASTRUCTURE ONLY (compared with the library's feature kernel).
+TEST INFRASTRUCTURE ONLY (compared with the library's feature kernels).
 
-The statistics come from the same per-row quantities the scaling step of the
-paper uses (Section III-B: the row maximum and a sum of squares), so they
-are cheap to collect next to it.  A "row" is a row of op(A) or a column of
-op(B), taken as its 2k real numbers (real and imaginary parts).  For a
-nonzero row with largest magnitude M, e = floor(log2 M),
-    l2 = 0.5 log2 sum (|x| / 2^e)^2,   l1 = log2 sum |x| / 2^e,
-both independent of a power-of-two scaling of the row.  Zero rows are left
-out of the statistics (all-zero operand: zeros).
+The statistics are the integer sums of the fast-mode scaling step (Section
+III-B: a row's largest magnitude and a sum of squares) plus the matching sum
+of magnitudes, so the library collects them in the pass that computes the
+scaling exponents.  A "row" is a row of op(A) or a column of op(B), taken as
+its 2k real numbers (real and imaginary parts).  For a nonzero finite row with
+largest magnitude M, e = floor(log2 M) and, with F = 20 fraction bits,
+
+    sigma = sum ceil(|x| 2^(F - e))^2,   tau = sum ceil(|x| 2^(F - e)),
+    l2 = 0.5 log2 sigma - F,             l1 = log2 tau - F,
+
+integers computed exactly (every nonzero |x| contributes at least 1 to tau),
+independent of a power-of-two scaling of the row.  Zero rows and rows holding
+inf or NaN are left out of the statistics; zero reals are counted in all rows.
 
 Feature vector (20 entries):
   0 log2 m, 1 log2 n, 2 log2 k,
@@ -26,22 +31,34 @@ import math
 import numpy as np
 
 N_FEATURES = 20
+F = 20  # fraction bits of the scaling statistics
+
+
+def _ceil_scaled(row, e):
+    """ceil(|x| 2^(F - e)) for the magnitudes of one row, as exact integers: a scaled
+    value >= 1 is an exact double (a power-of-two scaling of x below 2^(F + 1)); a
+    nonzero value below 1 has ceiling 1, also when the scaling underflows."""
+    scaled = np.ldexp(row, F - int(e))
+    return np.where(row > 0, np.maximum(np.ceil(scaled), 1.0), 0.0).astype(np.uint64)
 
 
 def _row_stats(rows):
-    """rows: (r, k) complex array -> (l2, l1) arrays over the nonzero rows, zero count."""
-    re = np.abs(np.asarray(rows).real).astype(np.float64)
-    im = np.abs(np.asarray(rows).imag).astype(np.float64)
-    mags = np.concatenate([re, im], axis=1)
+    """rows: (r, k) complex array -> (l2, l1) over the nonzero finite rows, zero count."""
+    rows = np.asarray(rows)
+    mags = np.concatenate([np.abs(rows.real), np.abs(rows.imag)], axis=1).astype(np.float64)
     zeros = int(np.count_nonzero(mags == 0))
-    mx = mags.max(axis=1) if mags.shape[1] else np.zeros(mags.shape[0])
-    nz = mx > 0
-    e = np.floor(np.log2(mx[nz]))
-    # exact power-of-two normalisation
-    scaled = mags[nz] * np.ldexp(1.0, -e.astype(int))[:, None]
-    l2 = 0.5 * np.log2(np.sum(scaled * scaled, axis=1))
-    l1 = np.log2(np.sum(scaled, axis=1))
-    return l2, l1, zeros
+    l2, l1 = [], []
+    for r in range(mags.shape[0]):
+        row = mags[r]
+        if not np.all(np.isfinite(row)) or not np.any(row > 0):
+            continue
+        e = math.frexp(float(row.max()))[1] - 1   # floor(log2 max)
+        c = _ceil_scaled(row, e)
+        sigma = int(np.sum(c * c, dtype=np.uint64))
+        tau = int(np.sum(c, dtype=np.uint64))
+        l2.append(0.5 * math.log2(sigma) - F)
+        l1.append(math.log2(tau) - F)
+    return np.array(l2), np.array(l1), zeros
 
 
 def _four(v):

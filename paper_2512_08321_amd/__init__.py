@@ -74,6 +74,10 @@ EXPORTS = {
     "ozc_cgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _F2, _VP, _I64, _VP, _I64, _F2, _VP, _I64],
     "ozc_zgemm_noalloc": [_VP, _INT, _INT, _I64, _I64, _I64, _D2, _VP, _I64, _VP, _I64, _D2, _VP,
                           _I64],
+    "ozc_dgemm": [_VP, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_double), _VP, _I64,
+                  _VP, _I64, ctypes.POINTER(ctypes.c_double), _VP, _I64],
+    "ozc_sgemm": [_VP, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_float), _VP, _I64,
+                  _VP, _I64, ctypes.POINTER(ctypes.c_float), _VP, _I64],
     "ozc_inspect": [_VP, _INT, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _VP,
                     _VP, _VP, _VP, _VP, _I64],
     "ozc_last_info": [_VP, ctypes.POINTER(Info)],
@@ -95,6 +99,7 @@ EXPORTS = {
     "ozc_mlp_save": [_VP, ctypes.c_char_p],
     "ozc_mlp_load": [_VP, ctypes.c_char_p],
     "ozc_mlp_forward": [_VP, _VP, _INT, _VP],
+    "ozc_mlp_predict": [_VP, _VP, _INT, _VP],
     "ozc_mlp_grad": [_VP, _VP, _VP, _INT, _VP, _VP],
     "ozc_mlp_train": [_VP, _VP, _VP, _INT, _INT, _INT, ctypes.c_float, ctypes.c_uint64, _INT, _VP],
     "ozc_set_auto_moduli": [_VP, _INT, _INT],
@@ -202,10 +207,26 @@ class Handle:
                                _ptr(A), lda, _ptr(B), ldb, _F2(b.real, b.imag), _ptr(C), ldc),
                "ozc_cgemm")
 
+    def dgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+        """ozc_dgemm (real float64 operands)."""
+        self.set_stream(stream)
+        a, b = ctypes.c_double(float(alpha)), ctypes.c_double(float(beta))
+        _check(lib().ozc_dgemm(self._h, OP[transa], OP[transb], m, n, k, ctypes.byref(a), _ptr(A),
+                               lda, _ptr(B), ldb, ctypes.byref(b), _ptr(C), ldc), "ozc_dgemm")
+
+    def sgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+        """ozc_sgemm (real float32 operands)."""
+        self.set_stream(stream)
+        a, b = ctypes.c_float(float(alpha)), ctypes.c_float(float(beta))
+        _check(lib().ozc_sgemm(self._h, OP[transa], OP[transb], m, n, k, ctypes.byref(a), _ptr(A),
+                               lda, _ptr(B), ldb, ctypes.byref(b), _ptr(C), ldc), "ozc_sgemm")
+
     def inspect(self, single, transa, transb, m, n, k, A, lda, B, ldb, mu=None, nu=None,
                 resA=None, resB=None, prods=None, eprime=None, C=None, ldc=1, stream=None):
+        """ozc_inspect; ``single``: element kind (False/0 complex128, True/1 complex64,
+        2 float64, 3 float32)."""
         self.set_stream(stream)
-        _check(lib().ozc_inspect(self._h, int(bool(single)), OP[transa], OP[transb], m, n, k,
+        _check(lib().ozc_inspect(self._h, int(single), OP[transa], OP[transb], m, n, k,
                                  _ptr(A), lda, _ptr(B), ldb, _ptr(mu), _ptr(nu), _ptr(resA),
                                  _ptr(resB), _ptr(prods), _ptr(eprime), _ptr(C), ldc),
                "ozc_inspect")
@@ -276,6 +297,11 @@ class Handle:
     def mlp_forward(self, X, rows, logits, stream=None):
         self.set_stream(stream)
         _check(lib().ozc_mlp_forward(self._h, _ptr(X), int(rows), _ptr(logits)), "ozc_mlp_forward")
+
+    def mlp_predict(self, X, rows, classes, stream=None):
+        """ozc_mlp_predict: classes (device int32, rows) of feature rows X."""
+        self.set_stream(stream)
+        _check(lib().ozc_mlp_predict(self._h, _ptr(X), int(rows), _ptr(classes)), "ozc_mlp_predict")
 
     def mlp_grad(self, X, y, rows, grad, stream=None) -> float:
         self.set_stream(stream)
@@ -371,17 +397,20 @@ def default_handle(device: int = 0) -> Handle:
 
 def gemm(A, B, C=None, alpha=1.0, beta=0.0, num_moduli: int = 14, mode: str = "fast",
          algo: str = "karatsuba", handle: Handle | None = None):
-    """alpha * A @ B + beta * C for row-major complex torch tensors on the GPU.
+    """alpha * A @ B + beta * C for row-major torch tensors on the GPU.
 
-    complex128 -> ozc_zgemm, complex64 -> ozc_cgemm.  Row-major C = A B is
+    complex128 -> ozc_zgemm, complex64 -> ozc_cgemm, float64 -> ozc_dgemm,
+    float32 -> ozc_sgemm (real: real alpha and beta).  Row-major C = A B is
     computed as the column-major product C^T = B^T A^T (no copies); the
     scheme treats rows of A and columns of B symmetrically, so the result is
     the same bit for bit.
     """
     import torch
 
-    if A.dtype != B.dtype or A.dtype not in (torch.complex128, torch.complex64):
-        raise TypeError("A and B must both be complex128 or complex64")
+    calls = {torch.complex128: "zgemm", torch.complex64: "cgemm", torch.float64: "dgemm",
+             torch.float32: "sgemm"}
+    if A.dtype != B.dtype or A.dtype not in calls:
+        raise TypeError("A and B must both be complex128, complex64, float64 or float32")
     if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
         raise ValueError("shape mismatch")
     m, k = A.shape
@@ -396,6 +425,6 @@ def gemm(A, B, C=None, alpha=1.0, beta=0.0, num_moduli: int = 14, mode: str = "f
     h = handle or default_handle(A.device.index or 0)
     if (h.num_moduli, h.mode, h.algo) != (num_moduli, mode, algo):
         h.set_config(num_moduli, mode, algo)
-    call = h.zgemm if A.dtype == torch.complex128 else h.cgemm
+    call = getattr(h, calls[A.dtype])
     call("N", "N", n, m, k, alpha, B, max(1, n), A, max(1, k), beta, C, max(1, n))
     return C

@@ -3,12 +3,25 @@
 Instances follow the paper's generator (Section IV-A: entries (u - 0.5)
 exp(phi g), u uniform, g standard normal) with uneven shapes, phi up to 8 and
 power-of-two skews along k (skews of whole rows or columns do not change the
-required N, since the exponent rules of Section III-B absorb them).  The label
-of an instance is the smallest N in [6, 24] whose result meets the target
-max_ij |C_N - C_ref|_ij / (|A||B|)_ij <= target, with C_ref the N = 24 result
-and |A||B| the product of the moduli (both computed by the library itself);
-instances that need more than 24 get the extra class.  Everything runs
-through the C-ABI (statistics, emulation, training, prediction).
+required N, since the exponent rules of Section III-B absorb them).
+
+Labels are certified: the label of an instance is the smallest N in [6, 24] with
+
+    max_ij (|C_N - C_24|_ij + b_ij) / (|A||B|)_ij <= target,
+
+where C_24 is the 24-moduli result and b_ij bounds its own error against the
+exact product: the reconstruction is exact, so C_24 differs from AB only by the
+truncation of the scaled inputs (each real part of a 2^mu_i and b 2^nu_j is cut by
+less than 1) and the final rounding,
+
+    |C_24 - AB|_ij <= sqrt(2) (2^-mu_i ||b_j||_1 + 2^-nu_j ||a_i||_1) + 2^-53 |C_24|_ij
+
+(complex moduli in the norms).  The left side is therefore an upper bound of the
+true error of C_N, and an instance whose bound at 24 moduli already misses the
+target gets the extra class.  |A||B| comes from the emulation at 16 moduli on the
+moduli of the entries (a product of nonnegative matrices, relative error far below
+the margin 2^-30 taken off it).  Everything runs through the C-ABI (statistics,
+emulation, exponents, training, prediction); torch only adds and compares.
 """
 from __future__ import annotations
 
@@ -58,36 +71,66 @@ def _emulate(h, inst, N, C):
     h.zgemm("N", "N", m, n, k, 1.0, inst["A"], m, inst["B"], k, 0.0, C, m)
 
 
-def error_profile(h, inst, Ns):
-    """max relative error (against |A||B|) of the N-moduli results, N in Ns."""
+class Reference:
+    """The 24-moduli result of an instance with the bound of its own error, and |A||B|."""
+
+    def __init__(self, h, inst):
+        import torch
+
+        m, n, k = inst["m"], inst["n"], inst["k"]
+        self.inst = inst
+        h.set_config(MAX_N, "fast", "karatsuba")
+        self.C = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+        mu = torch.empty(m, dtype=torch.int16, device="cuda")
+        nu = torch.empty(n, dtype=torch.int16, device="cuda")
+        h.inspect(False, "N", "N", m, n, k, inst["A"], m, inst["B"], k, mu=mu, nu=nu, C=self.C,
+                  ldc=m)
+        absA, absB = inst["A"].abs(), inst["B"].abs()   # (k, m) and (n, k) views
+        na = absA.sum(dim=0)                             # ||a_i||_1, rows of A
+        nb = absB.sum(dim=1)                             # ||b_j||_1, columns of B
+        zero = -32768                                    # rows without scaling contribute 0
+        sa = torch.where(mu == zero, torch.zeros_like(na),
+                         torch.exp2(-mu.to(torch.float64)))
+        sb = torch.where(nu == zero, torch.zeros_like(nb),
+                         torch.exp2(-nu.to(torch.float64)))
+        # C is held as (n, m): entry (i, j) at [j, i]
+        self.bound = (math.sqrt(2.0) * (sb[:, None] * na[None, :] + nb[:, None] * sa[None, :])
+                      + 2.0 ** -53 * self.C.abs())
+        cA = torch.complex(absA, torch.zeros_like(absA))
+        cB = torch.complex(absB, torch.zeros_like(absB))
+        absAB = torch.empty((n, m), dtype=torch.complex128, device="cuda")
+        h.set_config(16, "fast", "karatsuba")
+        h.zgemm("N", "N", m, n, k, 1.0, cA, m, cB, k, 0.0, absAB, m)
+        self.den = (absAB.real * (1.0 - 2.0 ** -30)).clamp_min(torch.finfo(torch.float64).tiny)
+
+    def error(self, C):
+        """Certified bound of max_ij |C - AB|_ij / (|A||B|)_ij."""
+        return float((((C - self.C).abs() + self.bound) / self.den).max())
+
+
+def error_profile(h, inst, Ns, ref=None):
+    """Certified relative errors (against |A||B|) of the N-moduli results, N in Ns."""
     import torch
 
-    m, n, k = inst["m"], inst["n"], inst["k"]
-    Cref = torch.empty((n, m), dtype=torch.complex128, device="cuda")
-    _emulate(h, inst, MAX_N, Cref)
-    absA = torch.complex(inst["A"].abs(), torch.zeros_like(inst["A"].real))
-    absB = torch.complex(inst["B"].abs(), torch.zeros_like(inst["B"].real))
-    absAB = torch.empty((n, m), dtype=torch.complex128, device="cuda")
-    h.set_config(16, "fast", "karatsuba")
-    h.zgemm("N", "N", m, n, k, 1.0, absA, m, absB, k, 0.0, absAB, m)
-    den = absAB.real.clamp_min(torch.finfo(torch.float64).tiny)
-    C = torch.empty_like(Cref)
+    ref = ref or Reference(h, inst)
+    C = torch.empty_like(ref.C)
     out = {}
     for N in Ns:
         _emulate(h, inst, N, C)
-        out[N] = float(((C - Cref).abs() / den).max())
+        out[N] = ref.error(C)
     return out
 
 
 def label(h, inst, target):
-    """Smallest N in [6, 24] meeting the target, by bisection (error falls with N);
-    MAX_N + 1 if even 24 misses it."""
+    """Smallest N in [6, 24] whose certified error meets the target, by bisection
+    (the error falls with N); MAX_N + 1 if even the bound at 24 misses it."""
     lo, hi = MLP_MIN_N, MAX_N
     cache = {}
+    ref = Reference(h, inst)
 
     def ok(N):
         if N not in cache:
-            cache.update(error_profile(h, inst, [N]))
+            cache.update(error_profile(h, inst, [N], ref))
         return cache[N] <= target
 
     if not ok(hi):
@@ -138,9 +181,12 @@ def fixed_rule(labels_N, quantile=0.999):
     return int(min(MAX_N, Ns[idx]))
 
 
-def evaluate(h, insts, target, margin=0):
+def evaluate(h, insts, target, margin=0, check=None):
     """Run every instance with the learned N (Freivalds check at the target, escalation
-    by 2): returns per-instance (predicted N, N used, escalations, error)."""
+    by 2): returns per instance the predicted N, the N used, the escalations, the
+    certified error bound of the result and the call's status.  check(inst, C), when
+    given, sees each result (C column-major as an (n, m) tensor) and its return value is
+    kept under "check"."""
     import torch
 
     res = []
@@ -158,8 +204,10 @@ def evaluate(h, insts, target, margin=0):
             status = getattr(e, "status", -1)
         info = h.last_info()
         h.set_verify(False)
-        prof = error_profile(h, inst, [info["num_moduli"]])
-        res.append(dict(N_hat=N_hat, N_used=info["num_moduli"], esc=info["escalations"],
-                        err=prof[info["num_moduli"]], status=status))
+        r = dict(N_hat=N_hat, N_used=info["num_moduli"], esc=info["escalations"],
+                 err=Reference(h, inst).error(C), status=status)
+        if check is not None:
+            r["check"] = check(inst, C)
+        res.append(r)
     h.set_config(14, "fast", "karatsuba")
     return res

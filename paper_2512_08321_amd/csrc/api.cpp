@@ -48,18 +48,21 @@ hipError_t fixed_workspace(int device, void **out) {
 struct Layout {
     int tile;
     int64_t m_pad, n_pad, k_pad;
-    int planes, nprod;
+    int planes, nprod, eplanes;
     size_t maxA, maxB, sigA, sigB, XA, YB, muA, nuB, barA, barB, resA, resB, ep, prods, total;
 };
 
-Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool with_prods) {
+// real: real operands (one residue plane, one product and one E' plane per modulus)
+Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool with_prods,
+                   bool real) {
     Layout L{};
     L.tile = gemm_tile_for(m, n);
     L.m_pad = round_up(m > 0 ? m : 1, gemm_tile_rows(L.tile));
     L.n_pad = round_up(n > 0 ? n : 1, gemm_tile_cols(L.tile));
     L.k_pad = round_up(k > 0 ? k : 1, gemm_kstep_for(L.tile));
-    L.planes = h->algo == OZC_ALGO_KARATSUBA ? 3 : 2;
-    L.nprod = h->algo == OZC_ALGO_KARATSUBA ? 3 : 4;
+    L.planes = real ? 1 : (h->algo == OZC_ALGO_KARATSUBA ? 3 : 2);
+    L.nprod = real ? 1 : (h->algo == OZC_ALGO_KARATSUBA ? 3 : 4);
+    L.eplanes = real ? 1 : 2;
     const size_t N = (size_t)h->nmod;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -77,11 +80,12 @@ Layout make_layout(const ozc_context *h, int64_t m, int64_t n, int64_t k, bool w
     L.muA = take(2 * (size_t)L.m_pad);
     L.nuB = take(2 * (size_t)L.n_pad);
     const bool accu = h->mode == OZC_MODE_ACCURATE;
-    L.barA = take(accu ? 3 * (size_t)L.m_pad * L.k_pad : 0);
-    L.barB = take(accu ? 3 * (size_t)L.n_pad * L.k_pad : 0);
+    const size_t barp = real ? 1 : 3;  // magnitude planes of the bound product
+    L.barA = take(accu ? barp * (size_t)L.m_pad * L.k_pad : 0);
+    L.barB = take(accu ? barp * (size_t)L.n_pad * L.k_pad : 0);
     L.resA = take(N * L.planes * (size_t)L.m_pad * L.k_pad);
     L.resB = take(N * L.planes * (size_t)L.n_pad * L.k_pad);
-    L.ep = take(N * 2 * (size_t)L.m_pad * L.n_pad);
+    L.ep = take(N * L.eplanes * (size_t)L.m_pad * L.n_pad);
     L.prods = take(with_prods ? N * L.nprod * 4 * (size_t)L.m_pad * L.n_pad : 0);
     L.total = off;
     return L;
@@ -307,10 +311,18 @@ struct InspectOut {
     int8_t *eprime;
 };
 
-ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
+// ek: ElemKind of A, B and C (a bool `single` selects complex64 over complex128); real
+// kinds take real alpha/beta (imaginary parts zero) and treat op C as op T.
+ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
                  int64_t k, const double alpha[2], const void *A, int64_t lda, const void *B,
                  int64_t ldb, const double beta[2], void *C, int64_t ldc, const InspectOut *ins) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (ek < kElemZ || ek > kElemS) return OZC_STATUS_INVALID_VALUE;
+    const bool real = elem_real(ek);
+    if (real) {
+        if (ta == OZC_OP_C) ta = OZC_OP_T;
+        if (tb == OZC_OP_C) tb = OZC_OP_T;
+    }
     ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, ins != nullptr);
     if (st != OZC_STATUS_SUCCESS) return st;
     if (k > OZC_MAX_K) {
@@ -320,7 +332,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         if (ins) return OZC_STATUS_NOT_SUPPORTED;
         if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
         const int64_t nc = (k + OZC_MAX_K - 1) / OZC_MAX_K;
-        const size_t es = single ? 8 : 16;
+        const size_t es = ek == kElemZ ? 16 : (ek == kElemS ? 4 : 8);
         const double one[2] = {1.0, 0.0};
         double ops = 0.0;
         // the non-finite flag is cleared once here and then collects every chunk's
@@ -335,7 +347,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
             const int64_t h0 = k * c / nc, h1 = k * (c + 1) / nc;
             const char *Ac = (const char *)A + es * (size_t)(ta == OZC_OP_N ? h0 * lda : h0);
             const char *Bc = (const char *)B + es * (size_t)(tb == OZC_OP_N ? h0 : h0 * ldb);
-            st = run(h, single, ta, tb, m, n, h1 - h0, alpha, Ac, lda, Bc, ldb, c == 0 ? beta : one,
+            st = run(h, ek, ta, tb, m, n, h1 - h0, alpha, Ac, lda, Bc, ldb, c == 0 ? beta : one,
                      C, ldc, nullptr);
             if (st != OZC_STATUS_SUCCESS) return st;
             ops += h->last.int8_ops;
@@ -349,7 +361,7 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     h->last = ozc_info_t{};
     h->last.num_moduli = h->nmod;
     h->last.mode = h->mode;
-    h->last.algo = h->algo;
+    h->last.algo = real ? -1 : h->algo;
     h->last.m = m;
     h->last.n = n;
     h->last.k = k;
@@ -357,12 +369,12 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
     const bool alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0;
     if ((alpha_zero || k == 0) && ins == nullptr) {
-        OZC_TRY(launch_scale_c(C, m, n, ldc, single, alpha[0], alpha[1], beta[0], beta[1], s));
+        OZC_TRY(launch_scale_c(C, m, n, ldc, ek, alpha[0], alpha[1], beta[0], beta[1], s));
         return OZC_STATUS_SUCCESS;
     }
     if (k == 0) return OZC_STATUS_INVALID_VALUE;  // nothing to inspect
 
-    const Layout L = make_layout(h, m, n, k, ins && ins->prods);
+    const Layout L = make_layout(h, m, n, k, ins && ins->prods, real);
     char *ws = nullptr;
     st = ensure_workspace(h, L.total, &ws);
     if (st != OZC_STATUS_SUCCESS) return st;
@@ -388,25 +400,36 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
     const int fault = h->fault;
     // Step III: scaling exponents
     OZC_TRY(pe.mark(0));
-    // one fill zeroes the row statistics maxA, maxB, sigA, sigB, XA, YB (adjacent in the layout)
-    OZC_TRY(launch_fill_u64(maxA, (int64_t)(L.muA - L.maxA) / 8, 0, s));
-    OZC_TRY(launch_row_maxabs(vA, single, maxA, s));
-    OZC_TRY(launch_row_maxabs(vB, single, maxB, s));
+    // Statistics computed by the moduli-count prediction of this call (same operands,
+    // same k) are taken over; otherwise one fill zeroes maxA, maxB, sigA, sigB, XA, YB
+    // (adjacent in the layout) and the scans run.
+    const bool pre = h->pre.maxA != nullptr && ins == nullptr && !real;
+    const uint64_t *cmaxA = pre ? h->pre.maxA : maxA, *cmaxB = pre ? h->pre.maxB : maxB;
+    const uint64_t *csigA = pre ? h->pre.sigA : sigA, *csigB = pre ? h->pre.sigB : sigB;
+    if (pre) {
+        OZC_TRY(launch_fill_u64((uint64_t *)XA, (int64_t)(L.muA - L.XA) / 8, 0, s));
+    } else {
+        OZC_TRY(launch_fill_u64(maxA, (int64_t)(L.muA - L.maxA) / 8, 0, s));
+        OZC_TRY(launch_row_maxabs(vA, ek, maxA, s));
+        OZC_TRY(launch_row_maxabs(vB, ek, maxB, s));
+    }
     int abits;
     if (h->mode == OZC_MODE_FAST) {
-        OZC_TRY(launch_row_sigma(vA, single, maxA, sigA, s));
-        OZC_TRY(launch_row_sigma(vB, single, maxB, sigB, s));
-        OZC_TRY(launch_fast_exponents(maxA, sigA, m, L.m_pad, tab, muA, status, s));
-        OZC_TRY(launch_fast_exponents(maxB, sigB, n, L.n_pad, tab, nuB, status, s));
+        if (!pre) {
+            OZC_TRY(launch_row_sigma(vA, ek, maxA, sigA, s));
+            OZC_TRY(launch_row_sigma(vB, ek, maxB, sigB, s));
+        }
+        OZC_TRY(launch_fast_exponents(cmaxA, csigA, m, L.m_pad, tab, muA, status, s));
+        OZC_TRY(launch_fast_exponents(cmaxB, csigB, n, L.n_pad, tab, nuB, status, s));
         abits = th.max_abits_fast;
     } else {
         int8_t *barA = (int8_t *)(ws + L.barA), *barB = (int8_t *)(ws + L.barB);
-        OZC_TRY(launch_ceil7(vA, single, maxA, barA, L.m_pad, L.k_pad, s));
-        OZC_TRY(launch_ceil7(vB, single, maxB, barB, L.n_pad, L.k_pad, s));
-        BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB, L.tile};
+        OZC_TRY(launch_ceil7(vA, ek, cmaxA, barA, L.m_pad, L.k_pad, s));
+        OZC_TRY(launch_ceil7(vB, ek, cmaxB, barB, L.n_pad, L.k_pad, s));
+        BoundArgs ba{barA, barB, L.m_pad, L.n_pad, L.k_pad, XA, YB, L.tile, real ? 1 : 0};
         OZC_TRY(launch_bound_gemm(ba, s));
-        OZC_TRY(launch_accu_exponents(maxA, XA, m, L.m_pad, tab, muA, status, s));
-        OZC_TRY(launch_accu_exponents(maxB, YB, n, L.n_pad, tab, nuB, status, s));
+        OZC_TRY(launch_accu_exponents(cmaxA, XA, m, L.m_pad, tab, muA, status, s));
+        OZC_TRY(launch_accu_exponents(cmaxB, YB, n, L.n_pad, tab, nuB, status, s));
         abits = th.max_abits_accu;
     }
     if (fault == 2) OZC_TRY(launch_debug_add_exp(muA, 12, s));
@@ -414,13 +437,13 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
 
     // Steps IV, V-i/ii: truncation and residues
     OZC_TRY(pe.mark(1));
-    OZC_TRY(launch_split(vA, single, muA, tab, h->nmod, L.planes, abits, resA, L.m_pad, L.k_pad, s));
-    OZC_TRY(launch_split(vB, single, nuB, tab, h->nmod, L.planes, abits, resB, L.n_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vA, ek, muA, tab, h->nmod, L.planes, abits, resA, L.m_pad, L.k_pad, s));
+    OZC_TRY(launch_split(vB, ek, nuB, tab, h->nmod, L.planes, abits, resB, L.n_pad, L.k_pad, s));
 
     // Step V-iii/iv: INT8 products and their residues
     OZC_TRY(pe.mark(2));
-    GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, h->algo == OZC_ALGO_KARATSUBA ? 0 : 1,
-                tab, ep, prods, L.tile};
+    const int galgo = real ? 2 : (h->algo == OZC_ALGO_KARATSUBA ? 0 : 1);
+    GemmArgs ga{resA, resB, L.m_pad, L.n_pad, L.k_pad, h->nmod, galgo, tab, ep, prods, L.tile};
     OZC_TRY(launch_residue_gemm(ga, s));
     if (fault == 1 && h->attempt == 0) OZC_TRY(launch_debug_xor_byte(ep, s));
     OZC_TRY(pe.mark(3));
@@ -444,7 +467,8 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         ca.beta_i = beta[1];
         ca.C = C;
         ca.ldc = ldc;
-        ca.single = single;
+        ca.single = ek == kElemC;
+        ca.ek = ek;
         OZC_TRY(launch_crt_output(ca, s));
     }
     OZC_TRY(pe.mark(4));
@@ -483,7 +507,8 @@ ozc_status_t run(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t 
         };
         if (ins->resA) OZC_TRY(slab_planes(ins->resA, resA, m, L.m_pad, N * L.planes));
         if (ins->resB) OZC_TRY(slab_planes(ins->resB, resB, n, L.n_pad, N * L.planes));
-        if (ins->eprime) OZC_TRY(planes(ins->eprime, ep, (size_t)m, (size_t)L.m_pad, n, L.n_pad, N * 2));
+        if (ins->eprime)
+            OZC_TRY(planes(ins->eprime, ep, (size_t)m, (size_t)L.m_pad, n, L.n_pad, N * L.eplanes));
         if (ins->prods)
             OZC_TRY(planes(ins->prods, prods, 4 * (size_t)m, 4 * (size_t)L.m_pad, n, L.n_pad, N * L.nprod));
     }
@@ -497,10 +522,14 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
                           int64_t lda, const void *B, int64_t ldb, const double beta[2], void *C,
                           int64_t ldc) {
     h->attempt = 0;
+    // restores the configured N and drops the prediction's statistics on every exit
     struct RestoreN0 {
         ozc_context *h;
         int n0;
-        ~RestoreN0() { h->nmod = n0; }
+        ~RestoreN0() {
+            h->nmod = n0;
+            h->pre = PreStats{};
+        }
     } restore0{h, h->nmod};
     if (h->auto_n) {
         ozc_status_t sa = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
@@ -508,7 +537,8 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
         int N = 9;  // complex64: the fixed count (single-precision level)
         if (!single) {
             OZC_TRY(hipSetDevice(h->device));
-            sa = predict_moduli(h, single, ta, tb, m, n, k, A, lda, B, ldb, &N);
+            // the prediction's scaling statistics serve every attempt of this call
+            sa = predict_moduli(h, single, ta, tb, m, n, k, A, lda, B, ldb, &N, &h->pre);
             if (sa != OZC_STATUS_SUCCESS) return sa;
         }
         h->nmod = N;
@@ -668,7 +698,7 @@ ozc_status_t ozc_workspace_size(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_
     const int64_t kc = k > OZC_MAX_K ? (k + (k + OZC_MAX_K - 1) / OZC_MAX_K - 1) /
                                            ((k + OZC_MAX_K - 1) / OZC_MAX_K)
                                      : k;  // largest k chunk
-    *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(h, m, n, kc, false).total;
+    *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(h, m, n, kc, false, false).total;
     return OZC_STATUS_SUCCESS;
 }
 
@@ -718,6 +748,29 @@ ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int6
     return run_verified(h, true, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
 }
 
+// Real products: the handle's fixed moduli count and scaling mode; no check, no learned count.
+static ozc_status_t run_real(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                             int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+                             const void *B, int64_t ldb, double beta, void *C, int64_t ldc) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+    return run(h, ek, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc, nullptr);
+}
+
+ozc_status_t ozc_dgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,
+                       const double *alpha, const void *A, int64_t lda, const void *B,
+                       int64_t ldb, const double *beta, void *C, int64_t ldc) {
+    if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
+    return run_real(h, kElemD, ta, tb, m, n, k, *alpha, A, lda, B, ldb, *beta, C, ldc);
+}
+
+ozc_status_t ozc_sgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n, int64_t k,
+                       const float *alpha, const void *A, int64_t lda, const void *B,
+                       int64_t ldb, const float *beta, void *C, int64_t ldc) {
+    if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
+    return run_real(h, kElemS, ta, tb, m, n, k, *alpha, A, lda, B, ldb, *beta, C, ldc);
+}
+
 ozc_status_t ozc_set_verify(ozc_handle_t h, int enable, double rel, int escalate, uint64_t seed) {
     if (!h) return OZC_STATUS_INVALID_HANDLE;
     if (!(rel == rel)) return OZC_STATUS_INVALID_VALUE;
@@ -741,7 +794,8 @@ ozc_status_t ozc_inspect(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, i
                          int32_t *prods, int8_t *eprime, void *C, int64_t ldc) {
     const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
     InspectOut ins{mu, nu, resA, resB, prods, eprime};
-    return run(h, single != 0, ta, tb, m, n, k, one, A, lda, B, ldb, zero, C, ldc, &ins);
+    if (single < kElemZ || single > kElemS) return OZC_STATUS_INVALID_VALUE;
+    return run(h, single, ta, tb, m, n, k, one, A, lda, B, ldb, zero, C, ldc, &ins);
 }
 
 ozc_status_t ozc_set_profiling(ozc_handle_t h, int enable) {

@@ -115,7 +115,7 @@ ozc_status_t ensure_stats(MlpState *st, int64_t rows) {
     if (st->stat) (void)hipFree(st->stat);
     st->stat = nullptr;
     st->stat_rows = 0;
-    // per row: maxbits (8), s1 (8), s2 (8); plus one zero counter
+    // per row: maxbits (8), sigma (8), tau (8); plus one zero counter
     if (dev_alloc(&st->stat, (size_t)rows * 24 + 256) != hipSuccess) {
         (void)hipGetLastError();
         return OZC_STATUS_ALLOC_FAILED;
@@ -135,41 +135,63 @@ double uniform01(uint64_t seed, uint64_t i) { return (double)(splitmix64(seed, i
 
 }  // namespace
 
-// Statistics of op(A) (m x k) and op(B) (k x n) into st->feat (device, F floats).
+// k of the statistics: a call above the INT32 limit runs in k-chunks (api.cpp), and
+// its count is predicted from the first chunk (the relative error of the whole call is
+// at most the largest of its chunks').
+int64_t feature_k(int64_t k) {
+    if (k <= OZC_MAX_K) return k;
+    const int64_t nc = (k + OZC_MAX_K - 1) / OZC_MAX_K;
+    return k / nc;
+}
+
+// Statistics of op(A) (m x k) and op(B) (k x n) into `out` (device, F floats): the
+// scaling pass's row maxima and sums (sigma, with tau and the zero count), then the
+// reduction.  The maxima and sigma stay in st->stat for the call that follows
+// (PreStats: that call skips its own scaling statistics).
 ozc_status_t compute_features(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                               int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
-                              int64_t ldb, float *out) {
+                              int64_t ldb, float *out, PreStats *pre) {
     MlpState *st = mlp_state(h);
     if (!st) return OZC_STATUS_ALLOC_FAILED;
     ozc_status_t s = ensure_stats(st, m + n);
     if (s != OZC_STATUS_SUCCESS) return s;
     hipStream_t str = h->stream;
+    const int64_t kf = feature_k(k);
     uint64_t *mb = (uint64_t *)st->stat;
-    unsigned long long *s1 = (unsigned long long *)(st->stat + 8 * (size_t)(m + n));
-    unsigned long long *s2 = (unsigned long long *)(st->stat + 16 * (size_t)(m + n));
-    unsigned long long *zeros = (unsigned long long *)(st->stat + 24 * (size_t)(m + n));
-    OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, s1, s2, zeros
-    const OperandView vA = view_A(A, ta, m, k, lda), vB = view_B(B, tb, n, k, ldb);
+    uint64_t *sig = (uint64_t *)(st->stat + 8 * (size_t)(m + n));
+    uint64_t *tau = (uint64_t *)(st->stat + 16 * (size_t)(m + n));
+    uint64_t *zeros = (uint64_t *)(st->stat + 24 * (size_t)(m + n));
+    OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, sigma, tau, zeros
+    const OperandView vA = view_A(A, ta, m, kf, lda), vB = view_B(B, tb, n, kf, ldb);
     OZC_TRY(launch_row_maxabs(vA, single, mb, str));
     OZC_TRY(launch_row_maxabs(vB, single, mb + m, str));
-    OZC_TRY(launch_feat_sums(vA, single, mb, s1, s2, zeros, str));
-    OZC_TRY(launch_feat_sums(vB, single, mb + m, s1 + m, s2 + m, zeros, str));
-    OZC_TRY(launch_feat_reduce(s1, s2, m, s1 + m, s2 + m, n, zeros, m, n, k, out, str));
+    OZC_TRY(launch_row_sigma(vA, single, mb, sig, str, tau, zeros));
+    OZC_TRY(launch_row_sigma(vB, single, mb + m, sig + m, str, tau + m, zeros));
+    OZC_TRY(launch_feat_reduce((const unsigned long long *)tau, (const unsigned long long *)sig, m,
+                               (const unsigned long long *)(tau + m),
+                               (const unsigned long long *)(sig + m), n,
+                               (const unsigned long long *)zeros, m, n, kf, out, str));
+    if (pre) {
+        *pre = PreStats{};
+        if (kf == k) *pre = PreStats{mb, mb + m, sig, sig + m};
+    }
     return OZC_STATUS_SUCCESS;
 }
 
 // Predicted N for one product (synchronises the stream).  Without parameters:
-// the fixed fallback count.
+// the fixed fallback count.  pre (may be null) receives the scaling statistics the
+// prediction computed, for the call that follows.
 ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                             int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
-                            int64_t ldb, int *N) {
+                            int64_t ldb, int *N, PreStats *pre) {
+    if (pre) *pre = PreStats{};
     MlpState *st = mlp_state(h);
     if (!st) return OZC_STATUS_ALLOC_FAILED;
     if (!st->have_params || m == 0 || n == 0 || k == 0) {
         *N = st->n_fix;
         return OZC_STATUS_SUCCESS;
     }
-    ozc_status_t s = compute_features(h, single, ta, tb, m, n, k, A, lda, B, ldb, st->feat);
+    ozc_status_t s = compute_features(h, single, ta, tb, m, n, k, A, lda, B, ldb, st->feat, pre);
     if (s != OZC_STATUS_SUCCESS) return s;
     OZC_TRY(launch_mlp_infer(kDims, st->params, st->feat, 1, st->pred, h->stream));
     int cls = 0;
@@ -191,15 +213,13 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
     hipStream_t s = h->stream;
     int64_t rows = 0;
     for (size_t p = 0; p < P; ++p) rows += va[p].rows + vb[p].rows;
-    // device scratch: maxbits, s1, s2 per row; zero counters; features; descriptors
+    // device scratch: maxbits, sigma, tau per row; zero counters; features; descriptors
     std::vector<BatchOperand> scan(2 * P);
-    std::vector<FeatOperand> fops(2 * P);
     std::vector<FeatProblem> fprob(P);
     const size_t b_rows = align_up(24 * (size_t)rows), b_zero = align_up(8 * P),
                  b_feat = align_up(4 * P * kDims.F), b_scan = align_up(sizeof(BatchOperand) * 2 * P),
-                 b_fops = align_up(sizeof(FeatOperand) * 2 * P),
                  b_fprob = align_up(sizeof(FeatProblem) * P), b_pred = align_up(4 * P);
-    const size_t total = b_rows + b_zero + b_feat + b_scan + b_fops + b_fprob + b_pred;
+    const size_t total = b_rows + b_zero + b_feat + b_scan + b_fprob + b_pred;
     if (total > st->many_bytes) {
         OZC_TRY(hipStreamSynchronize(s));
         if (st->many) (void)hipFree(st->many);
@@ -214,16 +234,15 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
     }
     char *buf = st->many;
     uint64_t *mb = (uint64_t *)buf;
-    unsigned long long *s1 = (unsigned long long *)(buf + 8 * (size_t)rows);
-    unsigned long long *s2 = (unsigned long long *)(buf + 16 * (size_t)rows);
-    unsigned long long *zeros = (unsigned long long *)(buf + b_rows);
+    uint64_t *sig = (uint64_t *)(buf + 8 * (size_t)rows);
+    uint64_t *tau = (uint64_t *)(buf + 16 * (size_t)rows);
+    uint64_t *zeros = (uint64_t *)(buf + b_rows);
     float *feat = (float *)(buf + b_rows + b_zero);
     char *d = buf + b_rows + b_zero + b_feat;
     BatchOperand *scan_dev = (BatchOperand *)d;
-    FeatOperand *fops_dev = (FeatOperand *)(d + b_scan);
-    FeatProblem *fprob_dev = (FeatProblem *)(d + b_scan + b_fops);
-    int *pred = (int *)(d + b_scan + b_fops + b_fprob);
-    int64_t r0 = 0, blk_scan = 0, blk_feat = 0;
+    FeatProblem *fprob_dev = (FeatProblem *)(d + b_scan);
+    int *pred = (int *)(d + b_scan + b_fprob);
+    int64_t r0 = 0, blk_scan = 0;
     for (size_t p = 0; p < P; ++p) {
         const OperandView *v2[2] = {&va[p], &vb[p]};
         const int64_t rbase[2] = {r0, r0 + va[p].rows};
@@ -232,25 +251,20 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
             b = BatchOperand{};
             b.v = *v2[q];
             b.maxbits = mb + rbase[q];
+            b.sigma = sig + rbase[q];
+            b.tau = tau + rbase[q];
+            b.zeros = zeros + p;
             b.blk_scan = blk_scan;
             blk_scan += batch_scan_blocks(b.v);
-            FeatOperand &f = fops[2 * p + q];
-            f.v = *v2[q];
-            f.maxbits = mb + rbase[q];
-            f.s1 = s1 + rbase[q];
-            f.s2 = s2 + rbase[q];
-            f.zeros = zeros + p;
-            f.blk = blk_feat;
-            blk_feat += batch_feat_blocks(f.v);
         }
         FeatProblem &fp = fprob[p];
-        fp.s1a = s1 + rbase[0];
-        fp.s2a = s2 + rbase[0];
+        fp.s1a = (const unsigned long long *)(tau + rbase[0]);
+        fp.s2a = (const unsigned long long *)(sig + rbase[0]);
         fp.ra = va[p].rows;
-        fp.s1b = s1 + rbase[1];
-        fp.s2b = s2 + rbase[1];
+        fp.s1b = (const unsigned long long *)(tau + rbase[1]);
+        fp.s2b = (const unsigned long long *)(sig + rbase[1]);
         fp.rb = vb[p].rows;
-        fp.zeros = zeros + p;
+        fp.zeros = (const unsigned long long *)(zeros + p);
         fp.m = (double)va[p].rows;
         fp.n = (double)vb[p].rows;
         fp.k = (double)va[p].k;
@@ -258,12 +272,11 @@ ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<
         r0 += va[p].rows + vb[p].rows;
     }
     OZC_TRY(hipMemcpyAsync(scan_dev, scan.data(), sizeof(BatchOperand) * 2 * P, hipMemcpyHostToDevice, s));
-    OZC_TRY(hipMemcpyAsync(fops_dev, fops.data(), sizeof(FeatOperand) * 2 * P, hipMemcpyHostToDevice, s));
     OZC_TRY(hipMemcpyAsync(fprob_dev, fprob.data(), sizeof(FeatProblem) * P, hipMemcpyHostToDevice, s));
     OZC_TRY(launch_fill_u64(mb, 3 * rows, 0, s));
-    OZC_TRY(launch_fill_u64((uint64_t *)zeros, (int64_t)P, 0, s));
-    OZC_TRY(launch_batch_scan(scan_dev, (int)(2 * P), blk_scan, single, false, s));
-    OZC_TRY(launch_batch_feat_sums(fops_dev, (int)(2 * P), blk_feat, single, s));
+    OZC_TRY(launch_fill_u64(zeros, (int64_t)P, 0, s));
+    OZC_TRY(launch_batch_scan(scan_dev, (int)(2 * P), blk_scan, single, 0, s));
+    OZC_TRY(launch_batch_scan(scan_dev, (int)(2 * P), blk_scan, single, 2, s));
     OZC_TRY(launch_batch_feat_reduce(fprob_dev, (int)P, s));
     OZC_TRY(launch_mlp_infer(kDims, st->params, feat, (int)P, pred, s));
     std::vector<int> cls(P);
@@ -288,7 +301,7 @@ ozc_status_t ozc_features(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_t tb, 
     if (s != OZC_STATUS_SUCCESS) return s;
     if (m == 0 || n == 0 || k == 0 || !features) return OZC_STATUS_INVALID_VALUE;
     OZC_TRY(hipSetDevice(h->device));
-    return compute_features(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, features);
+    return compute_features(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, features, nullptr);
 }
 
 ozc_status_t ozc_mlp_set_params(ozc_handle_t h, const float *params, int count) {
@@ -379,6 +392,18 @@ ozc_status_t ozc_mlp_forward(ozc_handle_t h, const float *X, int rows, float *lo
     MlpActs a = st->a;
     a.z = logits;
     OZC_TRY(launch_mlp_forward(kDims, st->params, X, nullptr, rows, a, h->stream));
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t ozc_mlp_predict(ozc_handle_t h, const float *X, int rows, int *classes) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    if (rows < 0 || (rows > 0 && (!X || !classes))) return OZC_STATUS_INVALID_VALUE;
+    MlpState *st = mlp_state(h);
+    if (!st) return OZC_STATUS_ALLOC_FAILED;
+    if (!st->have_params) return OZC_STATUS_INVALID_VALUE;
+    if (rows == 0) return OZC_STATUS_SUCCESS;
+    OZC_TRY(hipSetDevice(h->device));
+    OZC_TRY(launch_mlp_infer(kDims, st->params, X, rows, classes, h->stream));
     return OZC_STATUS_SUCCESS;
 }
 
@@ -506,7 +531,7 @@ ozc_status_t ozc_predict_moduli(ozc_handle_t h, int single, ozc_op_t ta, ozc_op_
     ozc_status_t s = check_args(ta, tb, m, n, k, A, lda, B, ldb, nullptr, m > 1 ? m : 1, true);
     if (s != OZC_STATUS_SUCCESS) return s;
     OZC_TRY(hipSetDevice(h->device));
-    return predict_moduli(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, num_moduli);
+    return predict_moduli(h, single != 0, ta, tb, m, n, k, A, lda, B, ldb, num_moduli, nullptr);
 }
 
 }  // extern "C"

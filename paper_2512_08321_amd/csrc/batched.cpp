@@ -479,7 +479,7 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
     if (phases & PH_PREP) {
         OZC_TRY(launch_fill_u64(h->status_dev, 1, 0, s));
         OZC_TRY(launch_fill_u64((uint64_t *)(ws + P.stats_off), (int64_t)P.stats_words, 0, s));
-        OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, false, s));
+        OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, 0, s));
         if (P.accurate) {
             OZC_TRY(launch_batch_ceil7(P.ops_dev, nops, P.blk_ceil7, P.single, s));
             uint32_t *bound_counter = counters + 2 * kBatchQueues;
@@ -487,7 +487,7 @@ ozc_status_t launch_batch(ozc_context *h, BatchState *bs, const BatchPlan &P, ch
             OZC_TRY(launch_batch_bound(P.bound_dev, (int)P.bound.size(), P.bound_items, bound_counter, s));
             OZC_TRY(launch_batch_accu_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
         } else {
-            OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, true, s));
+            OZC_TRY(launch_batch_scan(P.ops_dev, nops, P.blk_scan, P.single, 1, s));
             OZC_TRY(launch_batch_fast_exponents(P.ops_dev, nops, P.blk_exp, (uint32_t *)h->status_dev, s));
         }
         for (const BatchPlan::Range &r : P.splits)

@@ -10,6 +10,11 @@
 namespace ozc {
 struct BatchState;  // batched-call plans and tuning (batched.cpp)
 struct MlpState;    // moduli-count predictor (autoN.cpp)
+// Scaling statistics a call may take over instead of computing them (row maxima and
+// fast-mode sums of squares of op(A) and op(B), the layout of the workspace's own).
+struct PreStats {
+    const uint64_t *maxA = nullptr, *maxB = nullptr, *sigA = nullptr, *sigB = nullptr;
+};
 }
 
 struct ozc_context {
@@ -28,6 +33,7 @@ struct ozc_context {
     std::vector<ozc::NTable> tab_host;
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
     bool keep_status = false;           // k-chunks after the first: keep the flag of earlier chunks
+    ozc::PreStats pre{};                // statistics of the predicted-N call in progress (or none)
     ozc_info_t last{};
     bool profiling = false;
     // verification
@@ -66,7 +72,7 @@ void batch_release(ozc_context *h);
 void mlp_release(ozc_context *h);
 ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                             int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
-                            int64_t ldb, int *N);
+                            int64_t ldb, int *N, PreStats *pre);
 ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<OperandView> &va,
                                  const std::vector<OperandView> &vb, std::vector<int> &N);
 

@@ -121,29 +121,43 @@ __device__ __forceinline__ void alpha_beta(double cr, double ci, double ar, doub
     }
 }
 
-template <bool SINGLE>
+// C elements of kind EK (ElemKind); real elements carry no imaginary part.
+template <int EK>
 __device__ __forceinline__ void load_c(const void *C, int64_t idx, double &re, double &im) {
-    if constexpr (SINGLE) {
+    if constexpr (EK == kElemC) {
         const float2 v = reinterpret_cast<const float2 *>(C)[idx];
         re = v.x;
         im = v.y;
-    } else {
+    } else if constexpr (EK == kElemZ) {
         const double2 v = reinterpret_cast<const double2 *>(C)[idx];
         re = v.x;
         im = v.y;
+    } else if constexpr (EK == kElemD) {
+        re = reinterpret_cast<const double *>(C)[idx];
+        im = 0.0;
+    } else {
+        re = reinterpret_cast<const float *>(C)[idx];
+        im = 0.0;
     }
 }
 
-template <bool SINGLE>
+template <int EK>
 __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double im) {
-    if constexpr (SINGLE) reinterpret_cast<float2 *>(C)[idx] = make_float2((float)re, (float)im);
-    else reinterpret_cast<double2 *>(C)[idx] = make_double2(re, im);
+    if constexpr (EK == kElemC) reinterpret_cast<float2 *>(C)[idx] = make_float2((float)re, (float)im);
+    else if constexpr (EK == kElemZ) reinterpret_cast<double2 *>(C)[idx] = make_double2(re, im);
+    else if constexpr (EK == kElemD) reinterpret_cast<double *>(C)[idx] = re;
+    else reinterpret_cast<float *>(C)[idx] = (float)re;
 }
 
 // One thread: 4 consecutive rows i of one column j; block bx covers threads
 // 256 bx ... 256 bx + 255 of the ceil(m / 4) x n grid (padding rows get no thread).
-template <int L, bool SINGLE>
+// Real outputs (EK real) reconstruct the one E' plane of each modulus; alpha and beta
+// are real then (imaginary parts zero), so the fused multiply-add order below reduces
+// to x = alpha c, out = fma(beta, C, x).
+template <int L, int EK>
 __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
+    constexpr bool REAL = elem_real(EK);
+    constexpr int EPL = REAL ? 1 : 2;  // E' planes per modulus
     const int64_t m4 = (a.m + 3) >> 2;
     const int64_t t = bx * 256 + threadIdx.x;
     const int64_t i4 = t % m4, j = t / m4;
@@ -160,8 +174,9 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     const int8_t *E = a.eprime + j * a.m_pad + ib;
 #pragma unroll 4
     for (int l = 0; l < a.nmod; ++l) {
-        const uint32_t wr = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l) * planeC);
-        const uint32_t wi = *reinterpret_cast<const uint32_t *>(E + (int64_t)(2 * l + 1) * planeC);
+        const uint32_t wr = *reinterpret_cast<const uint32_t *>(E + (int64_t)(EPL * l) * planeC);
+        const uint32_t wi =
+            REAL ? 0u : *reinterpret_cast<const uint32_t *>(E + (int64_t)(EPL * l + 1) * planeC);
         int er[4], ei[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -175,7 +190,7 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 accR[u][q] += __mul24(s, er[u]);
-                accI[u][q] += __mul24(s, ei[u]);
+                if constexpr (!REAL) accI[u][q] += __mul24(s, ei[u]);
             }
         }
     }
@@ -193,24 +208,24 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         } else if (mui == kExpZero || nuj == kExpZero) {
             cr = ci = 0.0;
         } else {
-            int shr, shi;
+            int shr, shi = 0;
             const double dr = reconstruct<L>(accR[u], a.tab, shr);
-            const double di = reconstruct<L>(accI[u], a.tab, shi);
+            const double di = REAL ? 0.0 : reconstruct<L>(accI[u], a.tab, shi);
             cr = ldexp(dr, shr - (mui + nuj));
-            ci = ldexp(di, shi - (mui + nuj));
+            ci = REAL ? 0.0 : ldexp(di, shi - (mui + nuj));
         }
         double Cr = 0.0, Ci = 0.0;
         const int64_t idx = j * a.ldc + i;
-        if (!beta_zero) load_c<SINGLE>(a.C, idx, Cr, Ci);
+        if (!beta_zero) load_c<EK>(a.C, idx, Cr, Ci);
         double orr, oi;
         alpha_beta(cr, ci, a.alpha_r, a.alpha_i, a.beta_r, a.beta_i, beta_zero, Cr, Ci, orr, oi);
-        store_c<SINGLE>(a.C, idx, orr, oi);
+        store_c<EK>(a.C, idx, orr, oi);
     }
 }
 
-template <int L, bool SINGLE>
+template <int L, int EK>
 __global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
-    crt_output_body<L, SINGLE>(a, blockIdx.x);
+    crt_output_body<L, EK>(a, blockIdx.x);
 }
 
 template <int L, bool SINGLE>
@@ -234,7 +249,7 @@ hipError_t launch_batch_L(const BatchCrt *probs, int nprob, int64_t blocks, bool
 }
 
 // C := alpha * 0 + beta * C (alpha == 0 or k == 0), with the same operation order.
-template <bool SINGLE>
+template <int EK>
 __global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, double ar, double ai,
                                double br, double bi) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,18 +257,23 @@ __global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, doubl
     const int64_t i = t % m, j = t / m;
     const bool beta_zero = br == 0.0 && bi == 0.0;
     double Cr = 0.0, Ci = 0.0;
-    if (!beta_zero) load_c<SINGLE>(C, j * ldc + i, Cr, Ci);
+    if (!beta_zero) load_c<EK>(C, j * ldc + i, Cr, Ci);
     double orr, oi;
     alpha_beta(0.0, 0.0, ar, ai, br, bi, beta_zero, Cr, Ci, orr, oi);
-    store_c<SINGLE>(C, j * ldc + i, orr, oi);
+    store_c<EK>(C, j * ldc + i, orr, oi);
 }
 
 template <int L>
 hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
     const int64_t threads = ((a.m + 3) / 4) * a.n;
     dim3 grid((unsigned)((threads + 255) / 256));
-    if (a.single) hipLaunchKernelGGL((crt_output_kernel<L, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((crt_output_kernel<L, false>), grid, dim3(256), 0, s, a);
+    switch (a.ek) {
+        case kElemZ: hipLaunchKernelGGL((crt_output_kernel<L, kElemZ>), grid, dim3(256), 0, s, a); break;
+        case kElemC: hipLaunchKernelGGL((crt_output_kernel<L, kElemC>), grid, dim3(256), 0, s, a); break;
+        case kElemD: hipLaunchKernelGGL((crt_output_kernel<L, kElemD>), grid, dim3(256), 0, s, a); break;
+        case kElemS: hipLaunchKernelGGL((crt_output_kernel<L, kElemS>), grid, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -278,12 +298,17 @@ hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s) {
     }
 }
 
-hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
+hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, int ek, double ar,
                           double ai, double br, double bi, hipStream_t s) {
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid((unsigned)((m * n + 255) / 256));
-    if (single) hipLaunchKernelGGL(scale_c_kernel<true>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
-    else hipLaunchKernelGGL(scale_c_kernel<false>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi);
+    switch (ek) {
+        case kElemZ: hipLaunchKernelGGL(scale_c_kernel<kElemZ>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi); break;
+        case kElemC: hipLaunchKernelGGL(scale_c_kernel<kElemC>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi); break;
+        case kElemD: hipLaunchKernelGGL(scale_c_kernel<kElemD>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi); break;
+        case kElemS: hipLaunchKernelGGL(scale_c_kernel<kElemS>, grid, dim3(256), 0, s, C, m, n, ldc, ar, ai, br, bi); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@
 // A third plan computes the accurate-mode bound product (Section III-B):
 //   Cbar_I = Abar_I Bbar_R + Abar_R Bbar_I, Cbar_R = Cbar_I + (Abar_R - Abar_I)(Bbar_R - Bbar_I),
 // folded on the fly into row and column maxima (Cbar is never stored).
+// Real matrices (Algorithm 1 as stated for real A, B) take one product per
+// modulus, E' = mod(A'_l B'_l), and one real bound product Abar Bbar.
 //
 // Block order: block ids are dealt round-robin to the 8 XCDs; ids are
 // remapped so that each XCD walks its own contiguous part of the
@@ -42,14 +44,18 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int BK = 64;
 
-enum { KIND_KARATSUBA = 0, KIND_4M = 1, KIND_BOUND = 2 };
+enum { KIND_KARATSUBA = 0, KIND_4M = 1, KIND_BOUND = 2, KIND_REAL = 3, KIND_BOUND_REAL = 4 };
 
 // Products of each plan as (A plane, B plane) pairs, in execution order.
 template <int KIND>
 struct Plan {
-    static constexpr int nseg = KIND == KIND_4M ? 4 : 3;
-    static constexpr int nplanes = KIND == KIND_4M ? 2 : 3;
+    static constexpr bool real = KIND == KIND_REAL || KIND == KIND_BOUND_REAL;
+    static constexpr bool bound = KIND == KIND_BOUND || KIND == KIND_BOUND_REAL;
+    static constexpr int nseg = real ? 1 : (KIND == KIND_4M ? 4 : 3);
+    static constexpr int nplanes = real ? 1 : (KIND == KIND_4M ? 2 : 3);
+    static constexpr int eplanes = real ? 1 : 2;  // E' planes per modulus
     // Karatsuba: RR, II, SS.  Expanded: RR, II, RI, IR.  Bound: I.R, R.I, D.D (D = R - I).
+    // Real products and the real bound: the one product R.R.
     __device__ static constexpr int pa(int s) {
         return KIND == KIND_BOUND ? (s == 0 ? 1 : (s == 1 ? 0 : 2)) : (KIND == KIND_4M ? (s & 1) : s);
     }
@@ -188,7 +194,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % C::WM, wn = wave / C::WM;
 
-    const bool bound = KIND == KIND_BOUND;
+    constexpr bool bound = P::bound;
     const int64_t m_pad = bound ? b.m_pad : a.m_pad;
     const int64_t n_pad = bound ? b.n_pad : a.n_pad;
     const int64_t k_pad = bound ? b.k_pad : a.k_pad;
@@ -368,8 +374,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
         };
         int8_t *ER = nullptr, *EI = nullptr;
         if constexpr (!bound) {
-            ER = a.eprime + (int64_t)l * 2 * planeC;
-            EI = ER + planeC;
+            ER = a.eprime + (int64_t)l * P::eplanes * planeC;
+            EI = ER + planeC;  // not used by real products
             if (C::PREFETCH && !C::REG_CARRY && sgi >= 1 && (karatsuba || sgi != 2)) {
                 static_for<BM>([&](auto bi) {
                     static_for<BN>([&](auto bj) {
@@ -395,7 +401,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
             });
         }
         if constexpr (bound) {
-            if (sgi >= 1) {  // acc holds Cbar_I after the second product, Cbar_R after the third
+            // complex: acc holds Cbar_I after the second product, Cbar_R after the third;
+            // real: Abar Bbar after the one product
+            if (P::real || sgi >= 1) {
                 static_for<BM>([&](auto bi) {
                     static_for<16>([&](auto r) {
                         int x = acc[bi][0][(int)r];
@@ -415,6 +423,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                     if (lane < 32 && y > 0) atomicMax(&b.Y[j0 + wn * WTN + bj * 32 + lane], y);
                 });
             }
+        } else if constexpr (P::real) {
+            // E' = mod(A'_l B'_l): one reduction per output (Algorithm 1 Step V-iv)
+            static_for<BM>([&](auto bi) {
+                static_for<BN>([&](auto bj) {
+                    static_for<4>([&](auto g) {
+                        int o[4];
+                        static_for<4>([&](auto u) { o[u] = reduce_fp(acc[bi][bj][4 * (int)g + u], pd, ipd); });
+                        *eword(ER, bi, bj, g) = pack4(o);
+                    });
+                });
+            });
         } else {
             static_for<BM>([&](auto bi) {
                 static_for<BN>([&](auto bj) {
@@ -458,7 +477,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
 
 template <int KIND, typename C, bool DUMP>
 __global__ __launch_bounds__(C::THREADS) void residue_gemm_kernel(GemmArgs a, BoundArgs b) {
-    const bool bound = KIND == KIND_BOUND;
+    constexpr bool bound = Plan<KIND>::bound;
     const int64_t TR = (bound ? b.m_pad : a.m_pad) / C::TM, TC = (bound ? b.n_pad : a.n_pad) / C::TN;
     const int nmod = bound ? 1 : a.nmod;
     int l;
@@ -578,6 +597,13 @@ hipError_t launch_residue_gemm(const GemmArgs &a, hipStream_t s) {
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     BoundArgs none{};
     const bool dump = a.prods != nullptr;
+    if (a.algo < 0 || a.algo > 2) return hipErrorInvalidValue;
+    // one product per modulus: the long-k schedule keeps no carry, so it serves every k
+    if (a.algo == 2) {
+        if (tile == 256) launch_kind<KIND_REAL, CfgLarge>(a, none, dump, blocks, s);
+        else launch_kind<KIND_REAL, CfgSmall>(a, none, dump, blocks, s);
+        return hipGetLastError();
+    }
     if (tile == 256) {
         if (a.k_pad >= kLongK) {
             if (a.algo == 0) launch_kind<KIND_KARATSUBA, CfgLarge>(a, none, dump, blocks, s);
@@ -600,7 +626,8 @@ hipError_t launch_bound_gemm(const BoundArgs &b, hipStream_t s) {
     if (b.m_pad % tile || b.n_pad % tile || b.k_pad % BK) return hipErrorInvalidValue;
     const int64_t blocks = (b.m_pad / tile) * (b.n_pad / tile);
     GemmArgs none{};
-    launch_kind<KIND_BOUND, CfgSmall>(none, b, false, blocks, s);
+    if (b.real) launch_kind<KIND_BOUND_REAL, CfgSmall>(none, b, false, blocks, s);
+    else launch_kind<KIND_BOUND, CfgSmall>(none, b, false, blocks, s);
     return hipGetLastError();
 }
 

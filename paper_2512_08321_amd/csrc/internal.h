@@ -56,21 +56,33 @@ struct OperandView {
     int contig_h;  // 1 when stride_h == 1 (rows contiguous), 0 when stride_r == 1
 };
 
+// Element kind of an operand (the `ek` of the launchers below): complex128,
+// complex64 (a bool `single` converts to these two), real float64, real float32.
+// OperandView strides count elements of that kind; a real element is handled as a
+// complex one with zero imaginary part.
+enum ElemKind { kElemZ = 0, kElemC = 1, kElemD = 2, kElemS = 3 };
+__host__ __device__ constexpr bool elem_real(int ek) { return ek >= kElemD; }
+
 // Kernel launchers (all asynchronous on `stream`).
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbits, hipStream_t s);
-hipError_t launch_row_sigma(const OperandView &v, bool single, const uint64_t *maxbits,
-                            uint64_t *sigma, hipStream_t s);
+hipError_t launch_row_maxabs(const OperandView &v, int ek, uint64_t *maxbits, hipStream_t s);
+// sigma must be zeroed.  With tau and zeros (both or neither, zeroed): also the
+// predictor's statistics tau_r = sum ceil(|x| 2^(20 - e_r)) and the zero-real count.
+hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbits,
+                            uint64_t *sigma, hipStream_t s, uint64_t *tau = nullptr,
+                            uint64_t *zeros = nullptr);
 hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
                                  int64_t rows_pad, const NTable *tab, int16_t *mu,
                                  uint32_t *status, hipStream_t s);
-hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits,
+// complex: planes Abar_R, Abar_I, Abar_R - Abar_I; real: the plane Abar
+hipError_t launch_ceil7(const OperandView &v, int ek, const uint64_t *maxbits,
                         int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s);
 hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int64_t rows,
                                  int64_t rows_pad, const NTable *tab, int16_t *mu,
                                  uint32_t *status, hipStream_t s);
-// abits bounds the bit length of |a'| (at most 11 * kMaxFChunks).
-hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
+// abits bounds the bit length of |a'| (at most 11 * kMaxFChunks).  nplanes: 3 (Karatsuba:
+// R, I, reduced R + I) or 2 (R, I) for complex operands, 1 (R) for real ones.
+hipError_t launch_split(const OperandView &v, int ek, const int16_t *mu, const NTable *tab,
                         int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
                         int64_t k_pad, hipStream_t s);
 
@@ -79,9 +91,9 @@ struct GemmArgs {
     const int8_t *B;      // [N][planes][k_pad/64][n_pad][64]
     int64_t m_pad, n_pad, k_pad;
     int nmod;
-    int algo;             // 0 Karatsuba, 1 expanded (4 products)
+    int algo;             // 0 Karatsuba, 1 expanded (4 products), 2 real (1 plane, 1 product)
     const NTable *tab;
-    int8_t *eprime;       // [N][2][n_pad][m_pad]
+    int8_t *eprime;       // [N][2][n_pad][m_pad] (real: [N][n_pad][m_pad])
     int32_t *prods;       // optional raw dump [N][nprod][n_pad][m_pad]
     int tile;             // output tile edge (128 or 256); m_pad, n_pad are multiples
 };
@@ -97,11 +109,12 @@ int gemm_tile_cols(int tile);
 
 // Accurate-mode bound product: X[i] = max_j max(Cbar_R, Cbar_I)_ij, Y[j] likewise.
 struct BoundArgs {
-    const int8_t *A;      // [3][m_pad][k_pad]: Abar_R, Abar_I, Abar_R - Abar_I
+    const int8_t *A;      // [3][m_pad][k_pad]: Abar_R, Abar_I, Abar_R - Abar_I (real: [1] Abar)
     const int8_t *B;      // [3][n_pad][k_pad]
     int64_t m_pad, n_pad, k_pad;
     int32_t *X, *Y;       // zero-initialised
     int tile;
+    int real;             // 1: real operands, X_i = max_j (Abar Bbar)_ij
 };
 hipError_t launch_bound_gemm(const BoundArgs &a, hipStream_t s);
 // Batched bound products (accurate mode): a persistent kernel over the 128 x 128 tiles of
@@ -115,19 +128,20 @@ hipError_t launch_batch_bound(const BatchBound *probs, int nprob, int64_t items,
                               uint32_t *counter, hipStream_t s);
 
 struct CrtArgs {
-    const int8_t *eprime;  // [N][2][n_pad][m_pad]
+    const int8_t *eprime;  // [N][2][n_pad][m_pad] (real outputs: [N][n_pad][m_pad])
     int64_t m, n, m_pad, n_pad;
     int nmod;
     int nlimbs;            // limbs of P for this N (host copy of tab->nlimbs)
     const NTable *tab;     // device pointer
     const int16_t *mu, *nu;
     double alpha_r, alpha_i, beta_r, beta_i;
-    void *C;               // complex128 or complex64, column-major
+    void *C;               // column-major, elements of kind `ek` (single: ek of batches)
     int64_t ldc;
-    bool single;
+    bool single;           // batched launches: complex64 (else complex128)
+    int ek;                // single launches: ElemKind of C (real: alpha_i = beta_i = 0)
 };
 hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s);
-hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool single, double ar,
+hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, int ek, double ar,
                           double ai, double br, double bi, hipStream_t s);
 
 // ---------------------------------------------------------------- batched problems
@@ -137,6 +151,7 @@ hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, bool singl
 struct BatchOperand {       // op(A) rows or op(B) columns of one problem
     OperandView v;
     uint64_t *maxbits, *sigma;  // rows_pad entries each, zeroed before the scan
+    uint64_t *tau, *zeros;      // scan pass 2 only: predictor statistics (zeroed)
     int16_t *mu;                // rows_pad
     int8_t *res;                // residue planes, slab-major, rows_pad x k_pad each
     const NTable *tab;          // constants of the problem's moduli count
@@ -152,8 +167,10 @@ struct BatchOperand {       // op(A) rows or op(B) columns of one problem
 int64_t batch_scan_blocks(const OperandView &v);
 int64_t batch_exp_blocks(int64_t rows_pad);
 int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad);
+// pass 0: row maxima; 1: sums of squares; 2: sums of squares and the predictor's
+// statistics (tau, zeros)
 hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                             bool sigma, hipStream_t s);
+                             int pass, hipStream_t s);
 hipError_t launch_batch_fast_exponents(const BatchOperand *ops, int nops, int64_t blocks,
                                        uint32_t *status, hipStream_t s);
 // Accurate mode: magnitudes of every operand, then exponents from maxbits and X.
@@ -223,22 +240,8 @@ __host__ __device__ inline MlpOffsets mlp_offsets(const MlpDims &d) {
 struct MlpActs {  // device buffers for `rows` rows
     float *a1, *h1, *a2, *h2, *z, *dz, *loss_r, *d2, *d1, *xs;
 };
-// Row sums of the statistics pass in fixed point: s = value * 2^feat_frac_bits(k),
-// accumulated with integer atomics (exact and independent of their order, so the
-// statistics are reproducible).  The sums of a row are below 2k * 4, hence the
-// fraction bits shrink for k >= 2^21 to keep them within 64 bits.
-__host__ __device__ inline int feat_frac_bits(int64_t k) {
-    int b = 0;
-    while (b < 63 && (k >> b) != 0) ++b;
-    return 61 - b < 40 ? 61 - b : 40;
-}
-struct FeatOperand {  // one operand of a batched statistics pass
-    OperandView v;
-    const uint64_t *maxbits;
-    unsigned long long *s1, *s2;
-    unsigned long long *zeros;  // the problem's zero counter
-    int64_t blk;                // first block of this operand
-};
+// Statistics of one product for the predictor: s1 = tau and s2 = sigma of the rows of
+// op(A) (a) and the columns of op(B) (b), as the scaling pass computes them.
 struct FeatProblem {
     const unsigned long long *s1a, *s2a, *s1b, *s2b;
     int64_t ra, rb;
@@ -246,13 +249,7 @@ struct FeatProblem {
     double m, n, k;
     float *out;  // OZC_MLP_FEATURES floats
 };
-int64_t batch_feat_blocks(const OperandView &v);
-hipError_t launch_batch_feat_sums(const FeatOperand *ops, int nops, int64_t blocks, bool single,
-                                  hipStream_t s);
 hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStream_t s);
-hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits,
-                            unsigned long long *s1, unsigned long long *s2,
-                            unsigned long long *zeros, hipStream_t s);
 hipError_t launch_feat_reduce(const unsigned long long *s1a, const unsigned long long *s2a,
                               int64_t ra, const unsigned long long *s1b,
                               const unsigned long long *s2b, int64_t rb,

@@ -5,15 +5,17 @@
 // operands, so the error falls by about 2^-4 per modulus).
 //
 // Statistics: per row of op(A) / column of op(B) (2k reals), with e = floor(log2
-// max|x|), l2 = 0.5 log2 sum (|x| 2^-e)^2 and l1 = log2 sum |x| 2^-e; the feature
-// vector holds log2 m, log2 n, log2 k, min/max/mean/std of l2 and l1 over the
-// nonzero rows of each operand, and the fraction of zero reals.
+// max|x|) and the scaling pass's integer sums sigma = sum ceil(|x| 2^(20-e))^2 and
+// tau = sum ceil(|x| 2^(20-e)) (taken in the same pass, prep.hip), l2 = 0.5 log2
+// sigma - 20 and l1 = log2 tau - 20; the feature vector holds log2 m, log2 n,
+// log2 k, min/max/mean/std of l2 and l1 over the nonzero rows of each operand, and
+// the fraction of zero reals.
 //
 // Network (parameter layout shared with the C-ABI): xs = (x - mu) / sd,
 // h1 = relu(W1 xs + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3; W row-major
 // (out x in).  Every floating-point reduction runs in a fixed order and the row
-// sums of the statistics are accumulated in fixed point with integer atomics, so
-// statistics, predictions and training are reproducible run to run.
+// sums of the statistics are integers, so statistics, predictions and training are
+// reproducible run to run.
 #include <math.h>
 
 #include "internal.h"
@@ -21,119 +23,9 @@
 namespace ozc {
 namespace {
 
-constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
-
-template <bool SINGLE>
-__device__ __forceinline__ void load2(const void *base, int64_t idx, double &re, double &im) {
-    if constexpr (SINGLE) {
-        const float2 v = reinterpret_cast<const float2 *>(base)[idx];
-        re = v.x;
-        im = v.y;
-    } else {
-        const double2 v = reinterpret_cast<const double2 *>(base)[idx];
-        re = v.x;
-        im = v.y;
-    }
-}
-
-// 2^-e for the row whose largest magnitude has the bit pattern mb (0 < mb < inf)
-__device__ __forceinline__ double inv_pow2_of(uint64_t mb) {
-    const int ef = (int)(mb >> 52);
-    const int e = ef == 0 ? -1074 + 63 - __clzll((long long)mb) : ef - 1023;
-    return ldexp(1.0, -e);
-}
-
-constexpr int kFeatChunk = 2048;
-
-// Sums s1 = sum |x| 2^-e, s2 = sum (|x| 2^-e)^2 and the zero count of one row,
-// one block per (row group, k chunk); rows with k contiguous take a wave per row.
-__host__ __device__ __forceinline__ int64_t feat_grid_x(const OperandView &v) {
-    return v.contig_h ? (v.rows + 3) / 4 : (v.rows + 255) / 256;
-}
-// k chunk of a block: kFeatChunk (k contiguous) or kFeatChunk / 8, halved while the
-// grid would have fewer than 1024 blocks (down to 64 and 16), so that small operands
-// still spread over the chip.  A function of the operand's shape only.
-__host__ __device__ __forceinline__ int64_t feat_chunk(const OperandView &v) {
-    const int64_t gx = feat_grid_x(v), lo = v.contig_h ? 64 : 16;
-    int64_t c = v.contig_h ? kFeatChunk : kFeatChunk / 8;
-    while (c > lo && gx * ((v.k + c - 1) / c) < 1024) c /= 2;
-    return c;
-}
-__host__ __device__ __forceinline__ int64_t feat_grid_y(const OperandView &v) {
-    const int64_t c = feat_chunk(v);
-    return (v.k + c - 1) / c;
-}
-
-template <bool SINGLE>
-__device__ __forceinline__ void feat_sums_body(const OperandView &v, const uint64_t *maxbits,
-                                               unsigned long long *s1, unsigned long long *s2,
-                                               unsigned long long *zeros, int64_t bx, int64_t by) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t c = feat_chunk(v);
-    int64_t r, h0, step;
-    if (v.contig_h) {
-        r = bx * 4 + wave;
-        h0 = by * c + lane;
-        step = 64;
-    } else {
-        r = bx * 256 + threadIdx.x;
-        h0 = by * c;
-        step = 1;
-    }
-    const int64_t h1 = min(v.k, by * c + c);
-    if (r >= v.rows) return;
-    const uint64_t mb = maxbits[r];
-    const double sc = (mb != 0 && mb < 0x7ff0000000000000ull) ? inv_pow2_of(mb) : 0.0;
-    double a1 = 0.0, a2 = 0.0;
-    unsigned long long z = 0;
-    for (int64_t h = h0; h < h1; h += step) {
-        double re, im;
-        load2<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
-        const double x = fabs(re) * sc, y = fabs(im) * sc;
-        a1 += x + y;
-        a2 = fma(x, x, fma(y, y, a2));
-        z += (re == 0.0) + (im == 0.0);
-    }
-    if (v.contig_h) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            a1 += __shfl_xor(a1, off, 64);
-            a2 += __shfl_xor(a2, off, 64);
-            z += __shfl_xor(z, off, 64);
-        }
-        if (lane != 0) return;
-    }
-    // each partial is rounded to fixed point once; the integer sums do not depend on
-    // the order in which blocks arrive
-    const double fx = ldexp(1.0, feat_frac_bits(v.k));
-    atomicAdd(&s1[r], (unsigned long long)rint(a1 * fx));
-    atomicAdd(&s2[r], (unsigned long long)rint(a2 * fx));
-    if (z) atomicAdd(&zeros[0], z);
-}
-
-template <bool SINGLE>
-__global__ __launch_bounds__(256) void feat_sums_kernel(OperandView v, const uint64_t *maxbits,
-                                                        unsigned long long *s1,
-                                                        unsigned long long *s2,
-                                                        unsigned long long *zeros) {
-    feat_sums_body<SINGLE>(v, maxbits, s1, s2, zeros, blockIdx.x, blockIdx.y);
-}
-
-template <bool SINGLE>
-__global__ __launch_bounds__(256) void batch_feat_sums_kernel(const FeatOperand *ops, int nops) {
-    const int64_t b = blockIdx.x;
-    int lo = 0, hi = nops - 1;  // last operand whose first block is <= b
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ops[mid].blk <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const FeatOperand &o = ops[lo];
-    const int64_t lb = b - o.blk, gx = feat_grid_x(o.v);
-    feat_sums_body<SINGLE>(o.v, o.maxbits, o.s1, o.s2, o.zeros, lb % gx, lb / gx);
-}
-
-// One block: statistics of l2 and l1 over the nonzero rows of both operands.
+// One block: statistics of l2 and l1 over the nonzero rows of both operands, from the
+// scaling pass's integer sums sigma (2F fraction bits) and tau (F fraction bits):
+// l2 = 0.5 (log2 sigma - 2F), l1 = log2 tau - F.
 __device__ __forceinline__ void feat_reduce_body(const unsigned long long *s1a,
                                                  const unsigned long long *s2a, int64_t ra,
                                                  const unsigned long long *s1b,
@@ -142,7 +34,7 @@ __device__ __forceinline__ void feat_reduce_body(const unsigned long long *s1a,
                                                  double n, double k, float *out) {
     __shared__ double red[256][10];  // l2 statistics in 0..4, l1 statistics in 5..9
     const int t = threadIdx.x;
-    const int fb = feat_frac_bits((int64_t)k);
+    constexpr int fb = kSigmaFracBits;
     float res[16];
     for (int op = 0; op < 2; ++op) {
         const unsigned long long *s1 = op ? s1b : s1a, *s2 = op ? s2b : s2a;
@@ -150,8 +42,8 @@ __device__ __forceinline__ void feat_reduce_body(const unsigned long long *s1a,
         double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
         double sum[2] = {0.0, 0.0}, sq[2] = {0.0, 0.0}, cnt = 0.0;
         for (int64_t r = t; r < rows; r += 256) {
-            if (s2[r] == 0) continue;  // zero row (or all entries below the resolution)
-            const double x[2] = {0.5 * (log2((double)s2[r]) - fb), log2((double)s1[r]) - fb};
+            if (s2[r] == 0) continue;  // zero row (or a row holding inf / NaN)
+            const double x[2] = {0.5 * (log2((double)s2[r]) - 2 * fb), log2((double)s1[r]) - fb};
             for (int q = 0; q < 2; ++q) {  // q = 0: l2, 1: l1
                 mn[q] = fmin(mn[q], x[q]);
                 mx[q] = fmax(mx[q], x[q]);
@@ -372,29 +264,6 @@ __global__ void argmax_kernel(const float *z, int rows, int C, int *out) {
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
-
-hipError_t launch_feat_sums(const OperandView &v, bool single, const uint64_t *maxbits,
-                            unsigned long long *s1, unsigned long long *s2,
-                            unsigned long long *zeros, hipStream_t s) {
-    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
-    const dim3 grid((unsigned)feat_grid_x(v), (unsigned)feat_grid_y(v));
-    if (single) hipLaunchKernelGGL(feat_sums_kernel<true>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
-    else hipLaunchKernelGGL(feat_sums_kernel<false>, grid, dim3(256), 0, s, v, maxbits, s1, s2, zeros);
-    return hipGetLastError();
-}
-
-int64_t batch_feat_blocks(const OperandView &v) {
-    if (v.rows <= 0 || v.k <= 0) return 0;
-    return feat_grid_x(v) * feat_grid_y(v);
-}
-
-hipError_t launch_batch_feat_sums(const FeatOperand *ops, int nops, int64_t blocks, bool single,
-                                  hipStream_t s) {
-    if (blocks <= 0 || nops <= 0) return hipSuccess;
-    if (single) hipLaunchKernelGGL(batch_feat_sums_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
-    else hipLaunchKernelGGL(batch_feat_sums_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, ops, nops);
-    return hipGetLastError();
-}
 
 hipError_t launch_batch_feat_reduce(const FeatProblem *probs, int nprob, hipStream_t s) {
     if (nprob <= 0) return hipSuccess;

@@ -15,16 +15,23 @@ namespace {
 constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
 
-template <bool SINGLE>
+// One element of kind EK (ElemKind) at index idx; real elements have im = 0.
+template <int EK>
 __device__ __forceinline__ void load_elem(const void *base, int64_t idx, double &re, double &im) {
-    if constexpr (SINGLE) {
+    if constexpr (EK == kElemC) {
         float2 v = reinterpret_cast<const float2 *>(base)[idx];
         re = (double)v.x;
         im = (double)v.y;
-    } else {
+    } else if constexpr (EK == kElemZ) {
         double2 v = reinterpret_cast<const double2 *>(base)[idx];
         re = v.x;
         im = v.y;
+    } else if constexpr (EK == kElemD) {
+        re = reinterpret_cast<const double *>(base)[idx];
+        im = 0.0;
+    } else {
+        re = (double)reinterpret_cast<const float *>(base)[idx];
+        im = 0.0;
     }
 }
 
@@ -92,7 +99,7 @@ __global__ void fill_u64_kernel(uint64_t *p, int64_t n, uint64_t v) {
 
 // Block (bx, by) of the scan grids: contig rows take 4 rows x kHChunk elements
 // (a wave per row), strided rows 256 rows x kHChunk / 8 elements.
-template <bool SINGLE>
+template <int EK>
 __device__ __forceinline__ void maxabs_contig_body(const OperandView &v, uint64_t *maxbits,
                                                    int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -103,7 +110,7 @@ __device__ __forceinline__ void maxabs_contig_body(const OperandView &v, uint64_
     uint64_t m = 0;
     for (int64_t h = h0 + lane; h < h1; h += 64) {
         double re, im;
-        load_elem<SINGLE>(v.base, r * v.stride_r + h, re, im);
+        load_elem<EK>(v.base, r * v.stride_r + h, re, im);
         uint64_t a = abs_bits(re), b = abs_bits(im);
         m = max(m, max(a, b));
     }
@@ -111,7 +118,7 @@ __device__ __forceinline__ void maxabs_contig_body(const OperandView &v, uint64_
     if (lane == 0 && m) atomicMax((unsigned long long *)&maxbits[r], (unsigned long long)m);
 }
 
-template <bool SINGLE>
+template <int EK>
 __device__ __forceinline__ void maxabs_strided_body(const OperandView &v, uint64_t *maxbits,
                                                     int64_t bx, int64_t by, int hc) {
     const int64_t r = bx * 256 + threadIdx.x;
@@ -121,7 +128,7 @@ __device__ __forceinline__ void maxabs_strided_body(const OperandView &v, uint64
     uint64_t m = 0;
     for (int64_t h = h0; h < h1; ++h) {
         double re, im;
-        load_elem<SINGLE>(v.base, r + h * v.stride_h, re, im);
+        load_elem<EK>(v.base, r + h * v.stride_h, re, im);
         m = max(m, max(abs_bits(re), abs_bits(im)));
     }
     if (m) atomicMax((unsigned long long *)&maxbits[r], (unsigned long long)m);
@@ -130,47 +137,71 @@ __device__ __forceinline__ void maxabs_strided_body(const OperandView &v, uint64
 // ---------------------------------------------------------------- fast-mode sum of squares
 // sigma_r = sum over the 2k reals of ceil(|x| 2^(F - e_r))^2, e_r = floor(log2 max|x|):
 // an integer upper bound of 2^(2F) ||row / 2^e_r||_2^2, independent of summation order.
+// With STATS (the moduli-count predictor's statistics, taken in the same pass):
+// tau_r = sum ceil(|x| 2^(F - e_r)) (an upper bound of 2^F ||row / 2^e_r||_1) and the
+// number of zero reals of the operand, added to *zeros (all rows, finite or not).
+// Real operands have k reals per row (the imaginary parts do not exist).
 
-template <bool SINGLE>
+template <int EK, bool STATS>
 __device__ __forceinline__ void sigma_contig_body(const OperandView &v, const uint64_t *maxbits,
-                                                  uint64_t *sigma, int64_t bx, int64_t by) {
+                                                  uint64_t *sigma, uint64_t *tau, uint64_t *zeros,
+                                                  int64_t bx, int64_t by) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t r = bx * 4 + wave;
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
-    if (mb == 0 || mb >= kInfBits) return;
-    const int sh = kSigmaFracBits - ilogb_bits(mb);
+    const bool live = mb != 0 && mb < kInfBits;
+    if (!STATS && !live) return;
+    const int sh = live ? kSigmaFracBits - ilogb_bits(mb) : 0;
     const int64_t h0 = by * kHChunk;
     const int64_t h1 = min(v.k, h0 + kHChunk);
-    uint64_t s = 0;
+    uint64_t s = 0, t = 0, z = 0;
     for (int64_t h = h0 + lane; h < h1; h += 64) {
         double re, im;
-        load_elem<SINGLE>(v.base, r * v.stride_r + h, re, im);
+        load_elem<EK>(v.base, r * v.stride_r + h, re, im);
+        if constexpr (STATS) z += (re == 0.0) + (!elem_real(EK) && im == 0.0);
+        if (!live) continue;
         uint64_t a = ceil_scaled(re, sh), b = ceil_scaled(im, sh);
         s += a * a + b * b;
+        if constexpr (STATS) t += a + b;
     }
     s = wave_sum_u64(s);
     if (lane == 0 && s) atomicAdd((unsigned long long *)&sigma[r], (unsigned long long)s);
+    if constexpr (STATS) {
+        t = wave_sum_u64(t);
+        z = wave_sum_u64(z);
+        if (lane == 0 && t) atomicAdd((unsigned long long *)&tau[r], (unsigned long long)t);
+        if (lane == 0 && z) atomicAdd((unsigned long long *)zeros, (unsigned long long)z);
+    }
 }
 
-template <bool SINGLE>
+template <int EK, bool STATS>
 __device__ __forceinline__ void sigma_strided_body(const OperandView &v, const uint64_t *maxbits,
-                                                   uint64_t *sigma, int64_t bx, int64_t by, int hc) {
+                                                   uint64_t *sigma, uint64_t *tau, uint64_t *zeros,
+                                                   int64_t bx, int64_t by, int hc) {
     const int64_t r = bx * 256 + threadIdx.x;
     if (r >= v.rows) return;
     const uint64_t mb = maxbits[r];
-    if (mb == 0 || mb >= kInfBits) return;
-    const int sh = kSigmaFracBits - ilogb_bits(mb);
+    const bool live = mb != 0 && mb < kInfBits;
+    if (!STATS && !live) return;
+    const int sh = live ? kSigmaFracBits - ilogb_bits(mb) : 0;
     const int64_t h0 = by * hc;
     const int64_t h1 = min(v.k, h0 + hc);
-    uint64_t s = 0;
+    uint64_t s = 0, t = 0, z = 0;
     for (int64_t h = h0; h < h1; ++h) {
         double re, im;
-        load_elem<SINGLE>(v.base, r + h * v.stride_h, re, im);
+        load_elem<EK>(v.base, r + h * v.stride_h, re, im);
+        if constexpr (STATS) z += (re == 0.0) + (!elem_real(EK) && im == 0.0);
+        if (!live) continue;
         uint64_t a = ceil_scaled(re, sh), b = ceil_scaled(im, sh);
         s += a * a + b * b;
+        if constexpr (STATS) t += a + b;
     }
     if (s) atomicAdd((unsigned long long *)&sigma[r], (unsigned long long)s);
+    if constexpr (STATS) {
+        if (t) atomicAdd((unsigned long long *)&tau[r], (unsigned long long)t);
+        if (z) atomicAdd((unsigned long long *)zeros, (unsigned long long)z);
+    }
 }
 
 // ---------------------------------------------------------------- exponents
@@ -241,11 +272,11 @@ __global__ __launch_bounds__(256) void accu_exponents_kernel(const uint64_t *max
 
 constexpr int kTileR = 32, kTileH = 64, kLdsPitch = 80;
 
-template <bool SINGLE, bool CONTIG_H>
+template <int EK, bool CONTIG_H>
 __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t *maxbits,
                                            int8_t *dst, int64_t rows_pad, int64_t k_pad,
                                            int64_t bx, int64_t by) {
-    constexpr int NPLANES = 3;
+    constexpr int NPLANES = elem_real(EK) ? 1 : 3;  // real: Abar only; complex: Abar_R, Abar_I, Abar_R - Abar_I
     __shared__ __align__(16) int8_t lds[NPLANES][kTileR][kLdsPitch];
     const int tid = threadIdx.x;
     const int64_t h0 = bx * kTileH;
@@ -264,15 +295,17 @@ __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t 
             if (mb != 0 && mb < kInfBits) {
                 const int ex = ilogb_bits(mb);
                 double re, im;
-                load_elem<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
+                load_elem<EK>(v.base, r * v.stride_r + h * v.stride_h, re, im);
                 if (v.conj) im = -im;
                 a = (int)ceil_scaled(re, (kAccuIntBits - 1) - ex);
                 b = (int)ceil_scaled(im, (kAccuIntBits - 1) - ex);
             }
         }
         lds[0][rl][hl] = (int8_t)a;
-        lds[1][rl][hl] = (int8_t)b;
-        lds[2][rl][hl] = (int8_t)(a - b);
+        if constexpr (NPLANES == 3) {
+            lds[1][rl][hl] = (int8_t)b;
+            lds[2][rl][hl] = (int8_t)(a - b);
+        }
     }
     __syncthreads();
     for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
@@ -362,7 +395,7 @@ __device__ __forceinline__ float smod_f(float x, float p, float ip) {
     return __builtin_fmaf(-__builtin_rintf(x * ip), p, x);
 }
 
-template <bool SINGLE, bool CONTIG_H, int NPLANES, int NF>
+template <int EK, bool CONTIG_H, int NPLANES, int NF>
 __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *__restrict__ mu,
                                            const NTable *__restrict__ tab, int nmod,
                                            int8_t *__restrict__ dst, int64_t rows_pad,
@@ -384,17 +417,18 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
         for (int q = 0; q < nmod * NPLANES; ++q) store_res(out + (int64_t)q * plane_pitch, z);
         return;
     }
+    static_assert(NPLANES != 1 || elem_real(EK), "one residue plane for real operands only");
     float cR[kEPT][NF], cI[kEPT][NF];
 #pragma unroll
     for (int j = 0; j < kEPT; ++j) {
         double re = 0.0, im = 0.0;
         const int64_t h = h0 + j;
         if (live && h < v.k) {
-            load_elem<SINGLE>(v.base, r * v.stride_r + h * v.stride_h, re, im);
+            load_elem<EK>(v.base, r * v.stride_r + h * v.stride_h, re, im);
             if (v.conj) im = -im;
         }
         trunc_fchunks<NF>(re, live ? ex : 0, cR[j]);
-        trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
+        if constexpr (NPLANES > 1) trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
     }
 
     for (int l = 0; l < nmod; ++l) {
@@ -407,20 +441,22 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
         int a[kEPT], b[kEPT];
 #pragma unroll
         for (int j = 0; j < kEPT; ++j) {
-            float xr = cR[j][0] * w[0], xi = cI[j][0] * w[0];
+            float xr = cR[j][0] * w[0];
 #pragma unroll
-            for (int c = 1; c < NF; ++c) {
-                xr = __builtin_fmaf(cR[j][c], w[c], xr);
-                xi = __builtin_fmaf(cI[j][c], w[c], xi);
-            }
+            for (int c = 1; c < NF; ++c) xr = __builtin_fmaf(cR[j][c], w[c], xr);
             fa[j] = smod_f(xr, p, ip);
-            fb[j] = smod_f(xi, p, ip);
             a[j] = (int)fa[j];
-            b[j] = (int)fb[j];
+            if constexpr (NPLANES > 1) {
+                float xi = cI[j][0] * w[0];
+#pragma unroll
+                for (int c = 1; c < NF; ++c) xi = __builtin_fmaf(cI[j][c], w[c], xi);
+                fb[j] = smod_f(xi, p, ip);
+                b[j] = (int)fb[j];
+            }
         }
         int8_t *o = out + (int64_t)l * NPLANES * plane_pitch;
         store_res(o, a);
-        store_res(o + plane_pitch, b);
+        if constexpr (NPLANES > 1) store_res(o + plane_pitch, b);
         if constexpr (NPLANES == 3) {
             int c[kEPT];
 #pragma unroll
@@ -432,23 +468,25 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
 
 // ---------------------------------------------------------------- kernels (one problem)
 
-template <bool SINGLE>
+template <int EK>
 __global__ __launch_bounds__(256) void row_maxabs_contig(OperandView v, uint64_t *maxbits) {
-    maxabs_contig_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y);
+    maxabs_contig_body<EK>(v, maxbits, blockIdx.x, blockIdx.y);
 }
-template <bool SINGLE>
+template <int EK>
 __global__ __launch_bounds__(256) void row_maxabs_strided(OperandView v, uint64_t *maxbits, int hc) {
-    maxabs_strided_body<SINGLE>(v, maxbits, blockIdx.x, blockIdx.y, hc);
+    maxabs_strided_body<EK>(v, maxbits, blockIdx.x, blockIdx.y, hc);
 }
-template <bool SINGLE>
+template <int EK, bool STATS>
 __global__ __launch_bounds__(256) void row_sigma_contig(OperandView v, const uint64_t *maxbits,
-                                                        uint64_t *sigma) {
-    sigma_contig_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y);
+                                                        uint64_t *sigma, uint64_t *tau,
+                                                        uint64_t *zeros) {
+    sigma_contig_body<EK, STATS>(v, maxbits, sigma, tau, zeros, blockIdx.x, blockIdx.y);
 }
-template <bool SINGLE>
+template <int EK, bool STATS>
 __global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const uint64_t *maxbits,
-                                                         uint64_t *sigma, int hc) {
-    sigma_strided_body<SINGLE>(v, maxbits, sigma, blockIdx.x, blockIdx.y, hc);
+                                                         uint64_t *sigma, uint64_t *tau,
+                                                         uint64_t *zeros, int hc) {
+    sigma_strided_body<EK, STATS>(v, maxbits, sigma, tau, zeros, blockIdx.x, blockIdx.y, hc);
 }
 __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *maxbits,
                                                              const uint64_t *sigma, int64_t rows,
@@ -456,19 +494,19 @@ __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *max
                                                              int16_t *mu, uint32_t *status) {
     fast_exponents_body(maxbits, sigma, rows, rows_pad, tab, mu, status, blockIdx.x);
 }
-template <bool SINGLE, bool CONTIG_H, int NPLANES, int NF>
+template <int EK, bool CONTIG_H, int NPLANES, int NF>
 __global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *__restrict__ mu,
                                                     const NTable *__restrict__ tab, int nmod,
                                                     int8_t *__restrict__ dst, int64_t rows_pad,
                                                     int64_t k_pad) {
-    split_body<SINGLE, CONTIG_H, NPLANES, NF>(v, mu, tab, nmod, dst, rows_pad, k_pad, blockIdx.x,
+    split_body<EK, CONTIG_H, NPLANES, NF>(v, mu, tab, nmod, dst, rows_pad, k_pad, blockIdx.x,
                                               blockIdx.y);
 }
 
-template <bool SINGLE, bool CONTIG_H>
+template <int EK, bool CONTIG_H>
 __global__ __launch_bounds__(256) void ceil7_kernel(OperandView v, const uint64_t *maxbits,
                                                     int8_t *dst, int64_t rows_pad, int64_t k_pad) {
-    ceil7_body<SINGLE, CONTIG_H>(v, maxbits, dst, rows_pad, k_pad, blockIdx.x, blockIdx.y);
+    ceil7_body<EK, CONTIG_H>(v, maxbits, dst, rows_pad, k_pad, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- kernels (batched)
@@ -493,19 +531,23 @@ __host__ __device__ __forceinline__ int64_t scan_grid_y(const OperandView &v) {
     return (v.k + hc - 1) / hc;
 }
 
-template <bool SINGLE, bool SIGMA>
+// PASS 0: row maxima; 1: sums of squares; 2: sums of squares with the predictor's
+// statistics (BatchOperand::tau, zeros)
+template <int EK, int PASS>
 __global__ __launch_bounds__(256) void batch_scan_kernel(const BatchOperand *ops, int nops) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_scan; });
     const OperandView v = ops[o].v;
     const int64_t lb = b - ops[o].blk_scan, gx = scan_grid_x(v);
     const int64_t bx = lb % gx, by = lb / gx;
+    const BatchOperand &op = ops[o];
     if (v.contig_h) {
-        if constexpr (SIGMA) sigma_contig_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by);
-        else maxabs_contig_body<SINGLE>(v, ops[o].maxbits, bx, by);
+        if constexpr (PASS > 0) sigma_contig_body<EK, PASS == 2>(v, op.maxbits, op.sigma, op.tau, op.zeros, bx, by);
+        else maxabs_contig_body<EK>(v, op.maxbits, bx, by);
     } else {
-        if constexpr (SIGMA) sigma_strided_body<SINGLE>(v, ops[o].maxbits, ops[o].sigma, bx, by, kHChunk / 8);
-        else maxabs_strided_body<SINGLE>(v, ops[o].maxbits, bx, by, kHChunk / 8);
+        if constexpr (PASS > 0)
+            sigma_strided_body<EK, PASS == 2>(v, op.maxbits, op.sigma, op.tau, op.zeros, bx, by, kHChunk / 8);
+        else maxabs_strided_body<EK>(v, op.maxbits, bx, by, kHChunk / 8);
     }
 }
 
@@ -527,19 +569,19 @@ __global__ __launch_bounds__(256) void batch_accu_exponents_kernel(const BatchOp
                         b - op.blk_exp);
 }
 
-template <bool SINGLE>
+template <int EK>
 __global__ __launch_bounds__(256) void batch_ceil7_kernel(const BatchOperand *ops, int nops) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_ceil7; });
     const BatchOperand &op = ops[o];
     const int64_t lb = b - op.blk_ceil7, gx = op.k_pad / kTileH;
     const int64_t bx = lb % gx, by = lb / gx;
-    if (op.v.contig_h) ceil7_body<SINGLE, true>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
-    else ceil7_body<SINGLE, false>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
+    if (op.v.contig_h) ceil7_body<EK, true>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
+    else ceil7_body<EK, false>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
 }
 
 // Operands of one launch may have different moduli counts; NF covers the largest |a'|.
-template <bool SINGLE, int NPLANES, int NF>
+template <int EK, int NPLANES, int NF>
 __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_split; });
@@ -547,10 +589,10 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *op
     const int64_t lb = b - op.blk_split, gx = op.k_pad / kTileH;
     const int64_t bx = lb % gx, by = lb / gx;
     if (op.v.contig_h)
-        split_body<SINGLE, true, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
+        split_body<EK, true, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
                                               op.k_pad, bx, by);
     else
-        split_body<SINGLE, false, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
+        split_body<EK, false, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
                                                op.k_pad, bx, by);
 }
 
@@ -562,12 +604,12 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 #define OZC_NF_CASES(CASE) \
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 
-template <bool SINGLE, int NPLANES>
+template <int EK, int NPLANES>
 hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, int nf, hipStream_t s) {
     dim3 grid((unsigned)blocks);
 #define OZC_BSPLIT_CASE(NF)                                                                  \
     case NF:                                                                                 \
-        hipLaunchKernelGGL((batch_split_kernel<SINGLE, NPLANES, NF>), grid, dim3(256), 0, s, \
+        hipLaunchKernelGGL((batch_split_kernel<EK, NPLANES, NF>), grid, dim3(256), 0, s, \
                            ops, nops);                                                       \
         break;
     switch (nf) {
@@ -579,13 +621,13 @@ hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, int
     return hipGetLastError();
 }
 
-template <bool SINGLE, bool CONTIG_H, int NPLANES>
+template <int EK, bool CONTIG_H, int NPLANES>
 hipError_t split_nf(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod, int nf,
                     int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kDirectRows));
 #define OZC_SPLIT_CASE(NF)                                                                   \
     case NF:                                                                                 \
-        hipLaunchKernelGGL((split_kernel<SINGLE, CONTIG_H, NPLANES, NF>), grid, dim3(256), 0, \
+        hipLaunchKernelGGL((split_kernel<EK, CONTIG_H, NPLANES, NF>), grid, dim3(256), 0, \
                            s, v, mu, tab, nmod, dst, rows_pad, k_pad);                       \
         break;
     switch (nf) {
@@ -616,35 +658,64 @@ static int strided_chunk(const OperandView &v) {
     return hc;
 }
 
-hipError_t launch_row_maxabs(const OperandView &v, bool single, uint64_t *maxbits, hipStream_t s) {
-    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+template <int EK>
+hipError_t row_maxabs_ek(const OperandView &v, uint64_t *maxbits, hipStream_t s) {
     if (v.contig_h) {
         dim3 grid((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kHChunk - 1) / kHChunk));
-        if (single) hipLaunchKernelGGL(row_maxabs_contig<true>, grid, dim3(256), 0, s, v, maxbits);
-        else hipLaunchKernelGGL(row_maxabs_contig<false>, grid, dim3(256), 0, s, v, maxbits);
+        hipLaunchKernelGGL(row_maxabs_contig<EK>, grid, dim3(256), 0, s, v, maxbits);
     } else {
         const int hc = strided_chunk(v);
         dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
-        if (single) hipLaunchKernelGGL(row_maxabs_strided<true>, grid, dim3(256), 0, s, v, maxbits, hc);
-        else hipLaunchKernelGGL(row_maxabs_strided<false>, grid, dim3(256), 0, s, v, maxbits, hc);
+        hipLaunchKernelGGL(row_maxabs_strided<EK>, grid, dim3(256), 0, s, v, maxbits, hc);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_row_sigma(const OperandView &v, bool single, const uint64_t *maxbits,
-                            uint64_t *sigma, hipStream_t s) {
+hipError_t launch_row_maxabs(const OperandView &v, int ek, uint64_t *maxbits, hipStream_t s) {
     if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+    switch (ek) {
+        case kElemZ: return row_maxabs_ek<kElemZ>(v, maxbits, s);
+        case kElemC: return row_maxabs_ek<kElemC>(v, maxbits, s);
+        case kElemD: return row_maxabs_ek<kElemD>(v, maxbits, s);
+        case kElemS: return row_maxabs_ek<kElemS>(v, maxbits, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int EK, bool STATS>
+hipError_t row_sigma_ek(const OperandView &v, const uint64_t *maxbits, uint64_t *sigma,
+                        uint64_t *tau, uint64_t *zeros, hipStream_t s) {
     if (v.contig_h) {
         dim3 grid((unsigned)((v.rows + 3) / 4), (unsigned)((v.k + kHChunk - 1) / kHChunk));
-        if (single) hipLaunchKernelGGL(row_sigma_contig<true>, grid, dim3(256), 0, s, v, maxbits, sigma);
-        else hipLaunchKernelGGL(row_sigma_contig<false>, grid, dim3(256), 0, s, v, maxbits, sigma);
+        hipLaunchKernelGGL((row_sigma_contig<EK, STATS>), grid, dim3(256), 0, s, v, maxbits, sigma,
+                           tau, zeros);
     } else {
         const int hc = strided_chunk(v);
         dim3 grid((unsigned)((v.rows + 255) / 256), (unsigned)((v.k + hc - 1) / hc));
-        if (single) hipLaunchKernelGGL(row_sigma_strided<true>, grid, dim3(256), 0, s, v, maxbits, sigma, hc);
-        else hipLaunchKernelGGL(row_sigma_strided<false>, grid, dim3(256), 0, s, v, maxbits, sigma, hc);
+        hipLaunchKernelGGL((row_sigma_strided<EK, STATS>), grid, dim3(256), 0, s, v, maxbits, sigma,
+                           tau, zeros, hc);
     }
     return hipGetLastError();
+}
+
+template <bool STATS>
+hipError_t row_sigma_stats(const OperandView &v, int ek, const uint64_t *maxbits, uint64_t *sigma,
+                           uint64_t *tau, uint64_t *zeros, hipStream_t s) {
+    switch (ek) {
+        case kElemZ: return row_sigma_ek<kElemZ, STATS>(v, maxbits, sigma, tau, zeros, s);
+        case kElemC: return row_sigma_ek<kElemC, STATS>(v, maxbits, sigma, tau, zeros, s);
+        case kElemD: return row_sigma_ek<kElemD, STATS>(v, maxbits, sigma, tau, zeros, s);
+        case kElemS: return row_sigma_ek<kElemS, STATS>(v, maxbits, sigma, tau, zeros, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbits,
+                            uint64_t *sigma, hipStream_t s, uint64_t *tau, uint64_t *zeros) {
+    if (v.rows <= 0 || v.k <= 0) return hipSuccess;
+    if ((tau == nullptr) != (zeros == nullptr)) return hipErrorInvalidValue;
+    if (tau) return row_sigma_stats<true>(v, ek, maxbits, sigma, tau, zeros, s);
+    return row_sigma_stats<false>(v, ek, maxbits, sigma, nullptr, nullptr, s);
 }
 
 hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
@@ -665,37 +736,52 @@ hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int6
     return hipGetLastError();
 }
 
-hipError_t launch_split(const OperandView &v, bool single, const int16_t *mu, const NTable *tab,
+hipError_t launch_split(const OperandView &v, int ek, const int16_t *mu, const NTable *tab,
                         int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
                         int64_t k_pad, hipStream_t s) {
     const int nf = split_fchunks(abits);
     if (rows_pad % kDirectRows || k_pad % kTileH || nf > kMaxFChunks) return hipErrorInvalidValue;
+    if ((nplanes == 1) != elem_real(ek)) return hipErrorInvalidValue;
 #define OZC_SPLIT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
-    if (single) {
-        if (v.contig_h) return nplanes == 3 ? split_nf<true, true, 3>(OZC_SPLIT_ARGS)
-                                            : split_nf<true, true, 2>(OZC_SPLIT_ARGS);
-        return nplanes == 3 ? split_nf<true, false, 3>(OZC_SPLIT_ARGS)
-                            : split_nf<true, false, 2>(OZC_SPLIT_ARGS);
+#define OZC_SPLIT_EK(EKV)                                                                  \
+    if (v.contig_h) return nplanes == 3 ? split_nf<EKV, true, 3>(OZC_SPLIT_ARGS)            \
+                                        : split_nf<EKV, true, 2>(OZC_SPLIT_ARGS);           \
+    return nplanes == 3 ? split_nf<EKV, false, 3>(OZC_SPLIT_ARGS)                           \
+                        : split_nf<EKV, false, 2>(OZC_SPLIT_ARGS);
+    switch (ek) {
+        case kElemZ: OZC_SPLIT_EK(kElemZ)
+        case kElemC: OZC_SPLIT_EK(kElemC)
+        case kElemD:
+            return v.contig_h ? split_nf<kElemD, true, 1>(OZC_SPLIT_ARGS)
+                              : split_nf<kElemD, false, 1>(OZC_SPLIT_ARGS);
+        case kElemS:
+            return v.contig_h ? split_nf<kElemS, true, 1>(OZC_SPLIT_ARGS)
+                              : split_nf<kElemS, false, 1>(OZC_SPLIT_ARGS);
+        default: return hipErrorInvalidValue;
     }
-    if (v.contig_h) return nplanes == 3 ? split_nf<false, true, 3>(OZC_SPLIT_ARGS)
-                                        : split_nf<false, true, 2>(OZC_SPLIT_ARGS);
-    return nplanes == 3 ? split_nf<false, false, 3>(OZC_SPLIT_ARGS)
-                        : split_nf<false, false, 2>(OZC_SPLIT_ARGS);
+#undef OZC_SPLIT_EK
 #undef OZC_SPLIT_ARGS
 }
 
-hipError_t launch_ceil7(const OperandView &v, bool single, const uint64_t *maxbits, int8_t *dst,
+template <int EK>
+hipError_t ceil7_ek(const OperandView &v, const uint64_t *maxbits, int8_t *dst, int64_t rows_pad,
+                    int64_t k_pad, hipStream_t s) {
+    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kTileR));
+    if (v.contig_h) hipLaunchKernelGGL((ceil7_kernel<EK, true>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+    else hipLaunchKernelGGL((ceil7_kernel<EK, false>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_ceil7(const OperandView &v, int ek, const uint64_t *maxbits, int8_t *dst,
                         int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     if (rows_pad % kTileR || k_pad % kTileH) return hipErrorInvalidValue;
-    dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kTileR));
-    if (single) {
-        if (v.contig_h) hipLaunchKernelGGL((ceil7_kernel<true, true>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
-        else hipLaunchKernelGGL((ceil7_kernel<true, false>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
-    } else {
-        if (v.contig_h) hipLaunchKernelGGL((ceil7_kernel<false, true>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
-        else hipLaunchKernelGGL((ceil7_kernel<false, false>), grid, dim3(256), 0, s, v, maxbits, dst, rows_pad, k_pad);
+    switch (ek) {
+        case kElemZ: return ceil7_ek<kElemZ>(v, maxbits, dst, rows_pad, k_pad, s);
+        case kElemC: return ceil7_ek<kElemC>(v, maxbits, dst, rows_pad, k_pad, s);
+        case kElemD: return ceil7_ek<kElemD>(v, maxbits, dst, rows_pad, k_pad, s);
+        case kElemS: return ceil7_ek<kElemS>(v, maxbits, dst, rows_pad, k_pad, s);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 int64_t batch_scan_blocks(const OperandView &v) {
@@ -708,16 +794,20 @@ int64_t batch_split_blocks(int64_t rows_pad, int64_t k_pad) {
 }
 
 hipError_t launch_batch_scan(const BatchOperand *ops, int nops, int64_t blocks, bool single,
-                             bool sigma, hipStream_t s) {
+                             int pass, hipStream_t s) {
     if (blocks <= 0 || nops <= 0) return hipSuccess;
     dim3 grid((unsigned)blocks);
-    if (single) {
-        if (sigma) hipLaunchKernelGGL((batch_scan_kernel<true, true>), grid, dim3(256), 0, s, ops, nops);
-        else hipLaunchKernelGGL((batch_scan_kernel<true, false>), grid, dim3(256), 0, s, ops, nops);
-    } else {
-        if (sigma) hipLaunchKernelGGL((batch_scan_kernel<false, true>), grid, dim3(256), 0, s, ops, nops);
-        else hipLaunchKernelGGL((batch_scan_kernel<false, false>), grid, dim3(256), 0, s, ops, nops);
+#define OZC_SCAN(EKV, PV) hipLaunchKernelGGL((batch_scan_kernel<EKV, PV>), grid, dim3(256), 0, s, ops, nops)
+    switch ((single ? 3 : 0) + pass) {
+        case 0: OZC_SCAN(kElemZ, 0); break;
+        case 1: OZC_SCAN(kElemZ, 1); break;
+        case 2: OZC_SCAN(kElemZ, 2); break;
+        case 3: OZC_SCAN(kElemC, 0); break;
+        case 4: OZC_SCAN(kElemC, 1); break;
+        case 5: OZC_SCAN(kElemC, 2); break;
+        default: return hipErrorInvalidValue;
     }
+#undef OZC_SCAN
     return hipGetLastError();
 }
 

@@ -124,3 +124,21 @@ def test_features_invariant_under_power_of_two_row_scaling():
     As = workloads.skewed(A, row_exp=rng.integers(-30, 30, 12))
     Bs = workloads.skewed(B, col_exp=rng.integers(-30, 30, 9))
     assert np.allclose(ft.features(A, B), ft.features(As, Bs), rtol=0, atol=1e-12)
+
+
+def test_features_ceil_resolution_and_subnormal_rows():
+    """The statistics are the scaling pass's integers: every nonzero magnitude adds at least
+    1 to the sums at 2^-20 of the row maximum (here 1 and 2^-40: sigma = 2^40 + 1,
+    tau = 2^20 + 1), and a row whose maximum is subnormal is normalised exactly."""
+    from oracle import features as ft
+
+    A = np.zeros((2, 1), complex)
+    A[0, 0] = complex(1.0, 2.0 ** -40)
+    A[1, 0] = complex(3 * 2.0 ** -1074, 2.0 ** -1074)  # max 3 * 2^-1074, e = -1073
+    B = np.ones((1, 1), complex)
+    f = ft.features(A, B)
+    l2 = [0.5 * math.log2(2 ** 40 + 1) - 20, 0.5 * math.log2(1.5 ** 2 + 0.5 ** 2)]
+    l1 = [math.log2(2 ** 20 + 1) - 20, math.log2(2.0)]
+    assert f[3] == pytest.approx(min(l2), abs=1e-15) and f[4] == pytest.approx(max(l2), abs=1e-15)
+    assert f[7] == pytest.approx(min(l1), abs=1e-15) and f[8] == pytest.approx(max(l1), abs=1e-15)
+    assert np.isfinite(f).all()
