@@ -48,3 +48,17 @@ def test_header_constants_match_binding():
     m = re.search(r"#define OZC_NOALLOC_WORKSPACE \(\(size_t\)(\d+) << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == ozc.NOALLOC_WORKSPACE
     assert re.search(r"#define OZC_MAX_K (\d+)", text).group(1) == str(ozc.MAX_K)
+
+
+def test_blas_shim_exports_the_redirected_calls():
+    """libozc_blas.so defines the hipBLAS GEMM entry points it serves (Section III-D list)."""
+    from paper_2512_08321_amd import build
+
+    out = subprocess.run(["nm", "-D", "--defined-only", build.SHIM], capture_output=True,
+                         text=True, check=True).stdout
+    defined = set(re.findall(r"\bT (hipblas\w+)", out))
+    want = {"hipblasSgemm", "hipblasDgemm", "hipblasCgemm", "hipblasZgemm", "hipblasGemmEx",
+            "hipblasSgemm_64", "hipblasDgemm_64", "hipblasCgemm_64", "hipblasZgemm_64",
+            "hipblasGemmEx_64"}
+    assert want <= defined
+    assert os.access(build.CLIENT, os.X_OK)
