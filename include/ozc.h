@@ -141,6 +141,23 @@ ozc_status_t ozc_cgemm(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, in
                        int64_t lda, const void *B, int64_t ldb, const float beta[2],
                        void *C, int64_t ldc);
 
+/* The emulated product op(A) op(B) of complex128 operands as a double-double pair
+ * C_hi + C_lo, for results beyond double precision.  The reconstruction is exact, so
+ * the only rounding of ozc_zgemm's result is its final conversion to double; here,
+ * per real and imaginary part, C_hi = ldexp(RNE(C'), -(mu_i + nu_j)) (the entry
+ * ozc_zgemm computes with alpha = 1, beta = 0) and C_lo = ldexp(RNE(C' - RNE(C')),
+ * -(mu_i + nu_j)), so C_hi + C_lo is the exact integer product of the truncated
+ * inputs, scaled, to within 2^-106 relative (exactly when |C'| < 2^106), a second
+ * rounding only in the subnormal range.  The accuracy is then limited by the
+ * truncation of the scaled inputs, which more moduli reduce (at 24 moduli about
+ * 2^-90 of the row maxima).  Operands, checks, configuration and errors as
+ * ozc_zgemm; C_hi and C_lo: m x n, leading dimension ldc, not read; k == 0 gives
+ * zeros; k above OZC_MAX_K: NOT_SUPPORTED.  The Freivalds check and the learned
+ * moduli count are not run (the handle's fixed N is used).  Asynchronous. */
+ozc_status_t ozc_zgemm_dd(ozc_handle_t handle, ozc_op_t transa, ozc_op_t transb, int64_t m,
+                          int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                          int64_t ldb, void *C_hi, void *C_lo, int64_t ldc);
+
 /* Real products, C := alpha op(A) op(B) + beta C for float64 (dgemm) and float32
  * (sgemm) matrices: Algorithm 1 as the paper states it for real A and B
  * (Section II), with the scaling rules of Section III-B applied to rows of k

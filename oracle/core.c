@@ -335,6 +335,25 @@ static double u256_to_double_rne(const u256 *a) {
     return neg ? -v : v;
 }
 
+/* The integer value of an integer-valued double (|d| < 2^255), as a signed 256-bit number. */
+static u256 u256_from_double(double d) {
+    u256 r = {{0, 0, 0, 0}};
+    if (d == 0.0) return r;
+    int e;
+    double f = frexp(fabs(d), &e);            /* |d| = f 2^e, f in [0.5, 1) */
+    uint64_t M = (uint64_t)ldexp(f, 53);      /* |d| = M 2^(e - 53) */
+    int sh = e - 53;
+    if (sh < 0) {
+        r.w[0] = M >> (-sh);                  /* exact: d is an integer */
+    } else {
+        int q = sh / 64, o = sh % 64;
+        if (q < 4) r.w[q] = M << o;
+        if (o && q + 1 < 4) r.w[q + 1] = M >> (64 - o);
+    }
+    if (d < 0) u256_neg(&r);
+    return r;
+}
+
 /* C' = mod(S, P) with S = sum_l s_l E'_l; s_l and P as 4 x 64-bit little-endian words. */
 static u256 crt_reduce(const int8_t *const *ep, int nmod, const u256 *s, const u256 *P,
                        long double Pld) {
@@ -368,7 +387,8 @@ static u256 crt_reduce(const int8_t *const *ep, int nmod, const u256 *s, const u
 void orc_crt_output(const int8_t *Ep, int64_t m, int64_t n, int nmod, const uint64_t *s_words,
                     const uint64_t *P_words, const int32_t *mu, const uint8_t *rowflag,
                     const int32_t *nu, const uint8_t *colflag, const double *alpha,
-                    const double *beta, const double *Cin, double *out, double *Cp_out) {
+                    const double *beta, const double *Cin, double *out, double *Cp_out,
+                    double *lo_out) {
     u256 s[32], P;
     for (int l = 0; l < nmod; ++l) memcpy(s[l].w, s_words + 4 * l, 32);
     memcpy(P.w, P_words, 32);
@@ -380,8 +400,10 @@ void orc_crt_output(const int8_t *Ep, int64_t m, int64_t n, int nmod, const uint
     for (int64_t i = 0; i < m; ++i) {
         for (int64_t j = 0; j < n; ++j) {
             double cr = 0.0, ci = 0.0;
+            if (lo_out) { lo_out[2 * (i * n + j)] = 0.0; lo_out[2 * (i * n + j) + 1] = 0.0; }
             if (rowflag[i] == 2 || colflag[j] == 2) {
                 cr = NAN; ci = NAN;
+                if (lo_out) { lo_out[2 * (i * n + j)] = NAN; lo_out[2 * (i * n + j) + 1] = NAN; }
             } else if (rowflag[i] == 1 && colflag[j] == 1) {
                 const int8_t *pr[32], *pi[32];
                 for (int l = 0; l < nmod; ++l) {
@@ -393,6 +415,14 @@ void orc_crt_output(const int8_t *Ep, int64_t m, int64_t n, int nmod, const uint
                 double dR = u256_to_double_rne(&R), dI = u256_to_double_rne(&I);
                 if (Cp_out) { Cp_out[2 * (i * n + j)] = dR; Cp_out[2 * (i * n + j) + 1] = dI; }
                 int sh = -(mu[i] + nu[j]);
+                if (lo_out) { /* the rounding residual C' - RNE(C'), rounded, scaled */
+                    u256 hR = u256_from_double(dR), hI = u256_from_double(dI);
+                    u256 rR = R, rI = I;
+                    u256_sub(&rR, &hR);
+                    u256_sub(&rI, &hI);
+                    lo_out[2 * (i * n + j)] = ldexp(u256_to_double_rne(&rR), sh);
+                    lo_out[2 * (i * n + j) + 1] = ldexp(u256_to_double_rne(&rI), sh);
+                }
                 cr = ldexp(dR, sh);
                 ci = ldexp(dI, sh);
             }

@@ -194,12 +194,17 @@ def products(resA, resB, n_moduli, algo="karatsuba", want_raw=False):
     return Ep, raw
 
 
-def crt_output(Ep, mu, fa, nu, fb, n_moduli, alpha=1.0, beta=0.0, Cin=None, want_cp=False):
+def crt_output(Ep, mu, fa, nu, fb, n_moduli, alpha=1.0, beta=0.0, Cin=None, want_cp=False,
+               want_lo=False):
+    """Steps V-v, V-vi, VI.  Returns (out, RNE(C') or None, low parts or None): the low part
+    of an entry is ldexp(RNE(C' - RNE(C')), -(mu_i + nu_j)), the second word of the
+    double-double value of the scaled C'."""
     lib = _load()
     c = constants(n_moduli)
     m, n = Ep.shape[2], Ep.shape[3]
     out = np.zeros((m, n), np.complex128)
     cp = np.zeros((m, n), np.complex128) if want_cp else None
+    lo = np.zeros((m, n), np.complex128) if want_lo else None
     al = np.array([complex(alpha).real, complex(alpha).imag], np.float64)
     be = np.array([complex(beta).real, complex(beta).imag], np.float64)
     cin = np.ascontiguousarray(np.asarray(Cin, dtype=np.complex128)) if Cin is not None else None
@@ -209,18 +214,20 @@ def crt_output(Ep, mu, fa, nu, fb, n_moduli, alpha=1.0, beta=0.0, Cin=None, want
                        _p(c["s_words"]), _p(c["P_words"]), _p(mu.astype(np.int32)),
                        _p(fa.astype(np.uint8)), _p(nu.astype(np.int32)), _p(fb.astype(np.uint8)),
                        _p(al), _p(be), _p(cin) if cin is not None else None, _p(out),
-                       _p(cp) if cp is not None else None)
-    return out, cp
+                       _p(cp) if cp is not None else None, _p(lo) if lo is not None else None)
+    return out, cp, lo
 
 
 def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, C=None,
-            single=False, want_raw=False, want_cp=False, exponents=None, fault=0):
+            single=False, want_raw=False, want_cp=False, exponents=None, fault=0, want_lo=False):
     """alpha * A @ B + beta * C by the complex Ozaki-II scheme, computed exactly.
 
     A: (m, k) op(A); B: (k, n) op(B).  ``single`` rounds the result to
     complex64 (CGEMM: inputs promoted exactly, output rounded once more).
     ``exponents`` may carry precomputed (mu, fa, nu, fb) (e.g. for sampled
     entries of a large accurate-mode problem).
+    ``want_lo`` adds the low parts of the double-double value of the scaled C'
+    (``lo``; with alpha = 1, beta = 0, out + lo is that value).
     ``fault`` = 1 plants a mistake for tests of the verification step: the
     real part of E'_1 at entry (0, 0) has its bits 0x5a flipped before the
     reconstruction.
@@ -248,10 +255,11 @@ def emulate(A, B, n_moduli, mode="fast", algo="karatsuba", alpha=1.0, beta=0.0, 
     al, be = complex(alpha), complex(beta)
     if single:
         al, be = complex(np.complex64(al)), complex(np.complex64(be))
-    out, cp = crt_output(Ep, mu, fa, nu, fb, n_moduli, al, be, Cin, want_cp)
+    out, cp, lo = crt_output(Ep, mu, fa, nu, fb, n_moduli, al, be, Cin, want_cp, want_lo)
     if single:
         out = out.astype(np.complex64)
-    return dict(mu=mu, nu=nu, fa=fa, fb=fb, resA=resA, resB=resB, Ep=Ep, raw=raw, Cp=cp, out=out)
+    return dict(mu=mu, nu=nu, fa=fa, fb=fb, resA=resA, resB=resB, Ep=Ep, raw=raw, Cp=cp, out=out,
+                lo=lo)
 
 
 def emulate_real(A, B, n_moduli, mode="fast", alpha=1.0, beta=0.0, C=None, single=False,

@@ -74,6 +74,7 @@ EXPORTS = {
     "ozc_cgemm": [_VP, _INT, _INT, _I64, _I64, _I64, _F2, _VP, _I64, _VP, _I64, _F2, _VP, _I64],
     "ozc_zgemm_noalloc": [_VP, _INT, _INT, _I64, _I64, _I64, _D2, _VP, _I64, _VP, _I64, _D2, _VP,
                           _I64],
+    "ozc_zgemm_dd": [_VP, _INT, _INT, _I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _I64],
     "ozc_dgemm": [_VP, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_double), _VP, _I64,
                   _VP, _I64, ctypes.POINTER(ctypes.c_double), _VP, _I64],
     "ozc_sgemm": [_VP, _INT, _INT, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_float), _VP, _I64,
@@ -206,6 +207,12 @@ class Handle:
         _check(lib().ozc_cgemm(self._h, OP[transa], OP[transb], m, n, k, _F2(a.real, a.imag),
                                _ptr(A), lda, _ptr(B), ldb, _F2(b.real, b.imag), _ptr(C), ldc),
                "ozc_cgemm")
+
+    def zgemm_dd(self, transa, transb, m, n, k, A, lda, B, ldb, C_hi, C_lo, ldc, stream=None):
+        """ozc_zgemm_dd: op(A) op(B) as the double-double pair C_hi + C_lo."""
+        self.set_stream(stream)
+        _check(lib().ozc_zgemm_dd(self._h, OP[transa], OP[transb], m, n, k, _ptr(A), lda, _ptr(B),
+                                  ldb, _ptr(C_hi), _ptr(C_lo), ldc), "ozc_zgemm_dd")
 
     def dgemm(self, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
         """ozc_dgemm (real float64 operands)."""

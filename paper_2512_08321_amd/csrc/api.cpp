@@ -469,6 +469,7 @@ ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, in
         ca.ldc = ldc;
         ca.single = ek == kElemC;
         ca.ek = ek;
+        ca.C_lo = ek == kElemZ ? h->dd_lo : nullptr;
         OZC_TRY(launch_crt_output(ca, s));
     }
     OZC_TRY(pe.mark(4));
@@ -746,6 +747,30 @@ ozc_status_t ozc_cgemm(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int6
     if (!alpha || !beta) return OZC_STATUS_INVALID_VALUE;
     const double al[2] = {alpha[0], alpha[1]}, be[2] = {beta[0], beta[1]};
     return run_verified(h, true, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
+}
+
+ozc_status_t ozc_zgemm_dd(ozc_handle_t h, ozc_op_t ta, ozc_op_t tb, int64_t m, int64_t n,
+                          int64_t k, const void *A, int64_t lda, const void *B, int64_t ldb,
+                          void *C_hi, void *C_lo, int64_t ldc) {
+    if (!h) return OZC_STATUS_INVALID_HANDLE;
+    ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C_hi, ldc, false);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    if (m > 0 && n > 0 && !C_lo) return OZC_STATUS_INVALID_VALUE;
+    if (k > OZC_MAX_K) return OZC_STATUS_NOT_SUPPORTED;
+    const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
+    if (m == 0 || n == 0) return OZC_STATUS_SUCCESS;
+    if (k == 0) {  // the empty product: both parts zero
+        OZC_TRY(hipSetDevice(h->device));
+        OZC_TRY(launch_scale_c(C_hi, m, n, ldc, kElemZ, 0.0, 0.0, 0.0, 0.0, h->stream));
+        OZC_TRY(launch_scale_c(C_lo, m, n, ldc, kElemZ, 0.0, 0.0, 0.0, 0.0, h->stream));
+        return OZC_STATUS_SUCCESS;
+    }
+    struct DdOut {
+        ozc_context *h;
+        ~DdOut() { h->dd_lo = nullptr; }
+    } restore{h};
+    h->dd_lo = C_lo;
+    return run(h, kElemZ, ta, tb, m, n, k, one, A, lda, B, ldb, zero, C_hi, ldc, nullptr);
 }
 
 // Real products: the handle's fixed moduli count and scaling mode; no check, no learned count.

@@ -34,6 +34,7 @@ struct ozc_context {
     uint64_t *status_dev = nullptr;     // bit 0: non-finite input met
     bool keep_status = false;           // k-chunks after the first: keep the flag of earlier chunks
     ozc::PreStats pre{};                // statistics of the predicted-N call in progress (or none)
+    void *dd_lo = nullptr;              // set only while ozc_zgemm_dd runs: the low parts
     ozc_info_t last{};
     bool profiling = false;
     // verification

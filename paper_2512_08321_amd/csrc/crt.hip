@@ -52,9 +52,66 @@ __device__ __forceinline__ void settle_range(int32_t (&a)[L], const NTable *tab)
     }
 }
 
-// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised limbs.
+// A 256-bit magnitude w (little-endian words) rounded to nearest-even as d * 2^sh.
+__device__ __forceinline__ double round_w4(const uint64_t (&w)[4], int &sh) {
+    if ((w[1] | w[2] | w[3]) == 0) {
+        sh = 0;
+        return (double)w[0];  // exact when < 2^53, otherwise one correct rounding
+    }
+    const int wi = w[3] ? 3 : (w[2] ? 2 : 1);
+    const uint64_t top = wi == 3 ? w[3] : (wi == 2 ? w[2] : w[1]);
+    const uint64_t below = wi == 3 ? w[2] : (wi == 2 ? w[1] : w[0]);
+    uint64_t rest = wi == 3 ? (w[1] | w[0]) : (wi == 2 ? w[0] : 0);
+    const int nb = 64 - __clzll((long long)top);  // 1..64
+    uint64_t W;
+    if (nb == 64) {
+        W = top;
+        rest |= below;
+    } else {
+        W = (top << (64 - nb)) | (below >> nb);
+        rest |= below << (64 - nb);
+    }
+    W |= (rest != 0) ? 1ull : 0ull;  // sticky bit below the rounding position
+    sh = 64 * (wi - 1) + nb;
+    return (double)W;
+}
+
+// w - d 2^sh for the rounded value d 2^sh of w (|difference| <= half an ulp of d):
+// the magnitude of the difference into r, its sign as the return value (true: negative).
+__device__ __forceinline__ bool rounding_residual(const uint64_t (&w)[4], double d, int sh,
+                                                  uint64_t (&r)[4]) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(d);
+    const uint64_t M = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+    const int s = (int)(bits >> 52) - 1075 + sh;  // d 2^sh = M 2^s, s >= 0 when d is inexact
+    uint64_t h[4] = {0, 0, 0, 0};
+    const int q = s >> 6, o = s & 63;
+    if (q < 4) h[q] = M << o;
+    if (o && q + 1 < 4) h[q + 1] = M >> (64 - o);
+    uint64_t borrow = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t x = w[j], y = h[j];
+        const uint64_t t = x - y;
+        const uint64_t b2 = (x < y) ? 1ull : 0ull;
+        r[j] = t - borrow;
+        borrow = b2 | ((t < borrow) ? 1ull : 0ull);
+    }
+    if (!borrow) return false;
+    uint64_t c = 1;  // negate the two's complement
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        r[j] = ~r[j] + c;
+        c = (c && r[j] == 0) ? 1ull : 0ull;
+    }
+    return true;
+}
+
+// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised limbs.  With
+// low (and shl) non-null, also the rounding residual mod(S, P) - d 2^sh rounded to
+// nearest-even as *low * 2^shl (0 when d is exact), for double-double outputs.
 template <int L>
-__device__ __forceinline__ double reconstruct(int32_t (&a)[L], const NTable *tab, int &sh) {
+__device__ __forceinline__ double reconstruct(int32_t (&a)[L], const NTable *tab, int &sh,
+                                              double *low = nullptr, int *shl = nullptr) {
     normalize<L>(a);
     constexpr int lo = L >= 3 ? L - 3 : 0;
     double sa = 0.0;
@@ -82,27 +139,17 @@ __device__ __forceinline__ double reconstruct(int32_t (&a)[L], const NTable *tab
         w[o >> 6] |= v << (o & 63);
         if ((o & 63) + kLimbBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
     }
-    double d;
-    if ((w[1] | w[2] | w[3]) == 0) {
-        sh = 0;
-        d = (double)w[0];  // exact when < 2^53, otherwise one correct rounding
-    } else {
-        const int wi = w[3] ? 3 : (w[2] ? 2 : 1);
-        const uint64_t top = wi == 3 ? w[3] : (wi == 2 ? w[2] : w[1]);
-        const uint64_t below = wi == 3 ? w[2] : (wi == 2 ? w[1] : w[0]);
-        uint64_t rest = wi == 3 ? (w[1] | w[0]) : (wi == 2 ? w[0] : 0);
-        const int nb = 64 - __clzll((long long)top);  // 1..64
-        uint64_t W;
-        if (nb == 64) {
-            W = top;
-            rest |= below;
-        } else {
-            W = (top << (64 - nb)) | (below >> nb);
-            rest |= below << (64 - nb);
+    const double d = round_w4(w, sh);
+    if (low) {
+        *low = 0.0;
+        *shl = 0;
+        const bool exact = (w[1] | w[2] | w[3]) == 0 && w[0] < (1ull << 53);
+        if (!exact) {
+            uint64_t r[4];
+            const bool rneg = rounding_residual(w, d, sh, r);
+            const double e = round_w4(r, *shl);
+            *low = e == 0.0 ? 0.0 : ((rneg != neg) ? -e : e);  // a zero residual is +0
         }
-        W |= (rest != 0) ? 1ull : 0ull;  // sticky bit below the rounding position
-        sh = 64 * (wi - 1) + nb;
-        d = (double)W;
     }
     return neg ? -d : d;
 }
@@ -154,7 +201,7 @@ __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double 
 // Real outputs (EK real) reconstruct the one E' plane of each modulus; alpha and beta
 // are real then (imaginary parts zero), so the fused multiply-add order below reduces
 // to x = alpha c, out = fma(beta, C, x).
-template <int L, int EK>
+template <int L, int EK, bool DD = false>
 __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     constexpr bool REAL = elem_real(EK);
     constexpr int EPL = REAL ? 1 : 2;  // E' planes per modulus
@@ -203,10 +250,21 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         if (i >= a.m) continue;
         const int mui = a.mu[i];
         double cr, ci;
+        double lr = 0.0, li = 0.0;  // double-double outputs: the low parts
         if (mui == kExpNonfinite || nuj == kExpNonfinite) {
             cr = ci = __builtin_nan("");
+            lr = li = cr;
         } else if (mui == kExpZero || nuj == kExpZero) {
             cr = ci = 0.0;
+        } else if constexpr (DD) {
+            int shr, shi, slr, sli;
+            double er, ei;
+            const double dr = reconstruct<L>(accR[u], a.tab, shr, &er, &slr);
+            const double di = reconstruct<L>(accI[u], a.tab, shi, &ei, &sli);
+            cr = ldexp(dr, shr - (mui + nuj));
+            ci = ldexp(di, shi - (mui + nuj));
+            lr = ldexp(er, slr - (mui + nuj));
+            li = ldexp(ei, sli - (mui + nuj));
         } else {
             int shr, shi = 0;
             const double dr = reconstruct<L>(accR[u], a.tab, shr);
@@ -214,8 +272,13 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
             cr = ldexp(dr, shr - (mui + nuj));
             ci = REAL ? 0.0 : ldexp(di, shi - (mui + nuj));
         }
-        double Cr = 0.0, Ci = 0.0;
         const int64_t idx = j * a.ldc + i;
+        if constexpr (DD) {  // alpha = 1, beta = 0: the two parts as they are
+            reinterpret_cast<double2 *>(a.C)[idx] = make_double2(cr, ci);
+            reinterpret_cast<double2 *>(a.C_lo)[idx] = make_double2(lr, li);
+            continue;
+        }
+        double Cr = 0.0, Ci = 0.0;
         if (!beta_zero) load_c<EK>(a.C, idx, Cr, Ci);
         double orr, oi;
         alpha_beta(cr, ci, a.alpha_r, a.alpha_i, a.beta_r, a.beta_i, beta_zero, Cr, Ci, orr, oi);
@@ -226,6 +289,11 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
 template <int L, int EK>
 __global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
     crt_output_body<L, EK>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void crt_dd_kernel(CrtArgs a) {
+    crt_output_body<L, kElemZ, true>(a, blockIdx.x);
 }
 
 template <int L, bool SINGLE>
@@ -267,6 +335,11 @@ template <int L>
 hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
     const int64_t threads = ((a.m + 3) / 4) * a.n;
     dim3 grid((unsigned)((threads + 255) / 256));
+    if (a.C_lo) {
+        if (a.ek != kElemZ) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((crt_dd_kernel<L>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     switch (a.ek) {
         case kElemZ: hipLaunchKernelGGL((crt_output_kernel<L, kElemZ>), grid, dim3(256), 0, s, a); break;
         case kElemC: hipLaunchKernelGGL((crt_output_kernel<L, kElemC>), grid, dim3(256), 0, s, a); break;

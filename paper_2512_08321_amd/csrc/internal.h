@@ -139,6 +139,8 @@ struct CrtArgs {
     int64_t ldc;
     bool single;           // batched launches: complex64 (else complex128)
     int ek;                // single launches: ElemKind of C (real: alpha_i = beta_i = 0)
+    void *C_lo;            // complex128 only: double-double output, C the high parts and
+                           // C_lo the low parts (alpha = 1, beta = 0); null otherwise
 };
 hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s);
 hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, int ek, double ar,

@@ -142,3 +142,32 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with monkeypatch.context() as mp:
         mp.setattr(ref, "fast_exponent", greedy)
         assert not _reconstruction_pin_holds(ref.emulate)
+
+
+@pytest.mark.parametrize("mode", ["fast", "accurate"])
+@pytest.mark.parametrize("N", [8, 16, 24])
+def test_double_double_low_parts(orc, mode, N):
+    """The low part of the double-double value of the scaled C' (the reconstruction is
+    exact): with hi = RNE(C') and lo = RNE(C' - hi), both scaled by 2^-(mu + nu), the C
+    oracle agrees with Python integers (float() of an int rounds to nearest even), and
+    hi + lo is C' exactly while |C' - hi| < 2^53."""
+    from fractions import Fraction
+
+    from oracle import reference as ref
+
+    A = workloads.complex_matrix(4, 9, 3.0, 700 + N)
+    B = workloads.complex_matrix(9, 3, 3.0, 800 + N)
+    r = ref.emulate(A.tolist(), B.tolist(), N, mode)
+    c = orc.emulate(A, B, N, mode, want_lo=True)
+    CpR, CpI = r["Cp"]
+    for i in range(4):
+        for j in range(3):
+            sh = -(r["mu"][i] + r["nu"][j])
+            for part, cp in ((0, CpR[i][j]), (1, CpI[i][j])):
+                hi = float(cp)
+                lo = float(cp - int(hi))
+                got_hi = (c["out"][i, j].real, c["out"][i, j].imag)[part]
+                got_lo = (c["lo"][i, j].real, c["lo"][i, j].imag)[part]
+                assert got_hi == math.ldexp(hi, sh) and got_lo == math.ldexp(lo, sh)
+                if abs(cp - int(hi)) < 2 ** 53:
+                    assert Fraction(got_hi) + Fraction(got_lo) == Fraction(cp) * Fraction(2) ** sh
