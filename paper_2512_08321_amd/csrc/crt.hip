@@ -30,8 +30,10 @@ __device__ __forceinline__ void normalize(int32_t (&a)[L]) {
 }
 
 // After normalize(): value >= 0  <=>  top limb >= 0.
+using ConstTab = const OZC_AS_CONST NTable *;
+
 template <int L>
-__device__ __forceinline__ void settle_range(int32_t (&a)[L], const NTable *tab) {
+__device__ __forceinline__ void settle_range(int32_t (&a)[L], ConstTab tab) {
     int32_t t[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) t[j] = 2 * a[j] - tab->Plimb[j];
@@ -110,7 +112,7 @@ __device__ __forceinline__ bool rounding_residual(const uint64_t (&w)[4], double
 // low (and shl) non-null, also the rounding residual mod(S, P) - d 2^sh rounded to
 // nearest-even as *low * 2^shl (0 when d is exact), for double-double outputs.
 template <int L>
-__device__ __forceinline__ double reconstruct(int32_t (&a)[L], const NTable *tab, int &sh,
+__device__ __forceinline__ double reconstruct(int32_t (&a)[L], ConstTab tab, int &sh,
                                               double *low = nullptr, int *shl = nullptr) {
     normalize<L>(a);
     constexpr int lo = L >= 3 ? L - 3 : 0;
@@ -169,31 +171,34 @@ __device__ __forceinline__ void alpha_beta(double cr, double ci, double ar, doub
 }
 
 // C elements of kind EK (ElemKind); real elements carry no imaginary part.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
 template <int EK>
 __device__ __forceinline__ void load_c(const void *C, int64_t idx, double &re, double &im) {
     if constexpr (EK == kElemC) {
-        const float2 v = reinterpret_cast<const float2 *>(C)[idx];
+        const fvec2 v = global_ptr(reinterpret_cast<const fvec2 *>(C))[idx];
         re = v.x;
         im = v.y;
     } else if constexpr (EK == kElemZ) {
-        const double2 v = reinterpret_cast<const double2 *>(C)[idx];
+        const dvec2 v = global_ptr(reinterpret_cast<const dvec2 *>(C))[idx];
         re = v.x;
         im = v.y;
     } else if constexpr (EK == kElemD) {
-        re = reinterpret_cast<const double *>(C)[idx];
+        re = global_ptr(reinterpret_cast<const double *>(C))[idx];
         im = 0.0;
     } else {
-        re = reinterpret_cast<const float *>(C)[idx];
+        re = global_ptr(reinterpret_cast<const float *>(C))[idx];
         im = 0.0;
     }
 }
 
 template <int EK>
 __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double im) {
-    if constexpr (EK == kElemC) reinterpret_cast<float2 *>(C)[idx] = make_float2((float)re, (float)im);
-    else if constexpr (EK == kElemZ) reinterpret_cast<double2 *>(C)[idx] = make_double2(re, im);
-    else if constexpr (EK == kElemD) reinterpret_cast<double *>(C)[idx] = re;
-    else reinterpret_cast<float *>(C)[idx] = (float)re;
+    if constexpr (EK == kElemC) global_ptr(reinterpret_cast<fvec2 *>(C))[idx] = fvec2{(float)re, (float)im};
+    else if constexpr (EK == kElemZ) global_ptr(reinterpret_cast<dvec2 *>(C))[idx] = dvec2{re, im};
+    else if constexpr (EK == kElemD) global_ptr(reinterpret_cast<double *>(C))[idx] = re;
+    else global_ptr(reinterpret_cast<float *>(C))[idx] = (float)re;
 }
 
 // One thread: 4 consecutive rows i of one column j; block bx covers threads
@@ -218,19 +223,20 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
 #pragma unroll
         for (int q = 0; q < L; ++q) accR[u][q] = accI[u][q] = 0;
 
-    const int8_t *E = a.eprime + j * a.m_pad + ib;
+    ConstTab tab = const_ptr(a.tab);
+    const OZC_AS_GLOBAL int8_t *E = global_ptr(a.eprime) + j * a.m_pad + ib;
 #pragma unroll 4
     for (int l = 0; l < a.nmod; ++l) {
-        const uint32_t wr = *reinterpret_cast<const uint32_t *>(E + (int64_t)(EPL * l) * planeC);
+        const uint32_t wr = *reinterpret_cast<const OZC_AS_GLOBAL uint32_t *>(E + (int64_t)(EPL * l) * planeC);
         const uint32_t wi =
-            REAL ? 0u : *reinterpret_cast<const uint32_t *>(E + (int64_t)(EPL * l + 1) * planeC);
+            REAL ? 0u : *reinterpret_cast<const OZC_AS_GLOBAL uint32_t *>(E + (int64_t)(EPL * l + 1) * planeC);
         int er[4], ei[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             er[u] = (int)(int8_t)(wr >> (8 * u));
             ei[u] = (int)(int8_t)(wi >> (8 * u));
         }
-        const int32_t *sl = a.tab->mod[l].slimb;
+        const OZC_AS_CONST int32_t *sl = tab->mod[l].slimb;
 #pragma unroll
         for (int q = 0; q < L; ++q) {
             const int32_t s = sl[q];
@@ -242,13 +248,13 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         }
     }
 
-    const int nuj = a.nu[j];
+    const int nuj = global_ptr(a.nu)[j];
     const bool beta_zero = a.beta_r == 0.0 && a.beta_i == 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int64_t i = ib + u;
         if (i >= a.m) continue;
-        const int mui = a.mu[i];
+        const int mui = global_ptr(a.mu)[i];
         double cr, ci;
         double lr = 0.0, li = 0.0;  // double-double outputs: the low parts
         if (mui == kExpNonfinite || nuj == kExpNonfinite) {
@@ -259,23 +265,23 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         } else if constexpr (DD) {
             int shr, shi, slr, sli;
             double er, ei;
-            const double dr = reconstruct<L>(accR[u], a.tab, shr, &er, &slr);
-            const double di = reconstruct<L>(accI[u], a.tab, shi, &ei, &sli);
+            const double dr = reconstruct<L>(accR[u], tab, shr, &er, &slr);
+            const double di = reconstruct<L>(accI[u], tab, shi, &ei, &sli);
             cr = ldexp(dr, shr - (mui + nuj));
             ci = ldexp(di, shi - (mui + nuj));
             lr = ldexp(er, slr - (mui + nuj));
             li = ldexp(ei, sli - (mui + nuj));
         } else {
             int shr, shi = 0;
-            const double dr = reconstruct<L>(accR[u], a.tab, shr);
-            const double di = REAL ? 0.0 : reconstruct<L>(accI[u], a.tab, shi);
+            const double dr = reconstruct<L>(accR[u], tab, shr);
+            const double di = REAL ? 0.0 : reconstruct<L>(accI[u], tab, shi);
             cr = ldexp(dr, shr - (mui + nuj));
             ci = REAL ? 0.0 : ldexp(di, shi - (mui + nuj));
         }
         const int64_t idx = j * a.ldc + i;
         if constexpr (DD) {  // alpha = 1, beta = 0: the two parts as they are
-            reinterpret_cast<double2 *>(a.C)[idx] = make_double2(cr, ci);
-            reinterpret_cast<double2 *>(a.C_lo)[idx] = make_double2(lr, li);
+            global_ptr(reinterpret_cast<dvec2 *>(a.C))[idx] = dvec2{cr, ci};
+            global_ptr(reinterpret_cast<dvec2 *>(a.C_lo))[idx] = dvec2{lr, li};
             continue;
         }
         double Cr = 0.0, Ci = 0.0;

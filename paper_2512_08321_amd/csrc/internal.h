@@ -17,6 +17,22 @@ constexpr int kAccuIntBits = 6;     // accurate mode: magnitudes scaled below 2^
 constexpr int16_t kExpZero = -32768;
 constexpr int16_t kExpNonfinite = 32767;
 
+// Explicit address spaces for device accesses.  A pointer that a kernel loads from
+// memory (the per-problem arguments of the batched kernels) is generic to the
+// compiler, which then emits flat accesses, vector loads even for wave-uniform table
+// reads; naming the global (1) and constant (4) spaces gives global and scalar loads.
+// The constant space is for data that no kernel writes (the moduli tables).
+#define OZC_AS_GLOBAL __attribute__((address_space(1)))
+#define OZC_AS_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ OZC_AS_GLOBAL T *global_ptr(T *p) {
+    return (OZC_AS_GLOBAL T *)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ const OZC_AS_CONST T *const_ptr(const T *p) {
+    return (const OZC_AS_CONST T *)(uintptr_t)p;
+}
+
 // Per-modulus constants.
 struct ModConst {
     uint32_t p;                  // modulus

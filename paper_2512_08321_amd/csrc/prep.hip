@@ -16,21 +16,25 @@ constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
 
 // One element of kind EK (ElemKind) at index idx; real elements have im = 0.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
+// One element of kind EK (ElemKind) at index idx; real elements have im = 0.
 template <int EK>
 __device__ __forceinline__ void load_elem(const void *base, int64_t idx, double &re, double &im) {
     if constexpr (EK == kElemC) {
-        float2 v = reinterpret_cast<const float2 *>(base)[idx];
+        const fvec2 v = global_ptr(reinterpret_cast<const fvec2 *>(base))[idx];
         re = (double)v.x;
         im = (double)v.y;
     } else if constexpr (EK == kElemZ) {
-        double2 v = reinterpret_cast<const double2 *>(base)[idx];
+        const dvec2 v = global_ptr(reinterpret_cast<const dvec2 *>(base))[idx];
         re = v.x;
         im = v.y;
     } else if constexpr (EK == kElemD) {
-        re = reinterpret_cast<const double *>(base)[idx];
+        re = global_ptr(reinterpret_cast<const double *>(base))[idx];
         im = 0.0;
     } else {
-        re = (double)reinterpret_cast<const float *>(base)[idx];
+        re = (double)global_ptr(reinterpret_cast<const float *>(base))[idx];
         im = 0.0;
     }
 }
@@ -225,8 +229,9 @@ __device__ __forceinline__ void fast_exponents_body(const uint64_t *maxbits, con
         } else if (mb != 0) {
             const uint64_t s = sigma[r];
             int d = 0;
-            while (d < kThr - 1 && tab->fast_thr[d] < s) ++d;
-            out = (int16_t)(tab->fast_tmax - d - ilogb_bits(mb));
+            const OZC_AS_CONST NTable *ct = const_ptr(tab);
+            while (d < kThr - 1 && ct->fast_thr[d] < s) ++d;
+            out = (int16_t)(ct->fast_tmax - d - ilogb_bits(mb));
         }
     }
     mu[r] = out;
@@ -247,8 +252,9 @@ __device__ __forceinline__ void accu_exponents_body(const uint64_t *maxbits, con
         } else if (mb != 0 && X[r] > 0) {
             const uint64_t x = (uint64_t)X[r];
             int d = 0;
-            while (d < kThr - 1 && tab->accu_thr[d] < x) ++d;
-            out = (int16_t)((kAccuIntBits - 1) - ilogb_bits(mb) + tab->accu_thi - d);
+            const OZC_AS_CONST NTable *ct = const_ptr(tab);
+            while (d < kThr - 1 && ct->accu_thr[d] < x) ++d;
+            out = (int16_t)((kAccuIntBits - 1) - ilogb_bits(mb) + ct->accu_thi - d);
         }
     }
     mu[r] = out;
@@ -310,9 +316,10 @@ __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t 
     __syncthreads();
     for (int t = tid; t < NPLANES * kTileR * 4; t += 256) {
         const int pl = t >> 7, row = (t >> 2) & 31, seg = t & 3;
-        const uint4 val = *reinterpret_cast<const uint4 *>(&lds[pl][row][seg * 16]);
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 val = *reinterpret_cast<const u32x4 *>(&lds[pl][row][seg * 16]);
         int8_t *out = dst + (int64_t)pl * plane_pitch + (bx * rows_pad + r0 + row) * kTileH + seg * 16;
-        *reinterpret_cast<uint4 *>(out) = val;
+        *global_ptr(reinterpret_cast<u32x4 *>(out)) = val;
     }
 }
 
@@ -351,11 +358,11 @@ template <int E>
 __device__ __forceinline__ void store_res(int8_t *p, const int (&r)[E]) {
     if constexpr (E == 8) {
         const u32x2 w{pack_bytes(r[0], r[1], r[2], r[3]), pack_bytes(r[4], r[5], r[6], r[7])};
-        *reinterpret_cast<u32x2 *>(p) = w;
+        *global_ptr(reinterpret_cast<u32x2 *>(p)) = w;
     } else if constexpr (E == 4) {
-        *reinterpret_cast<uint32_t *>(p) = pack_bytes(r[0], r[1], r[2], r[3]);
+        *global_ptr(reinterpret_cast<uint32_t *>(p)) = pack_bytes(r[0], r[1], r[2], r[3]);
     } else {
-        *reinterpret_cast<uint16_t *>(p) = (uint16_t)((r[0] & 0xff) | ((r[1] & 0xff) << 8));
+        *global_ptr(reinterpret_cast<uint16_t *>(p)) = (uint16_t)((r[0] & 0xff) | ((r[1] & 0xff) << 8));
     }
 }
 
@@ -409,7 +416,7 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
     const int64_t plane_pitch = rows_pad * k_pad;
 
     int ex = kExpZero;
-    if (r < v.rows) ex = mu[r];
+    if (r < v.rows) ex = global_ptr(mu)[r];
     const bool live = ex != kExpZero && ex != kExpNonfinite;
     int8_t *out = dst + (bx * rows_pad + r) * kTileH + kEPT * oc;
     if (!live || h0 >= v.k) {  // padding, or a row without scaling: every residue is 0
@@ -432,7 +439,7 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
     }
 
     for (int l = 0; l < nmod; ++l) {
-        const ModConst &mc = tab->mod[l];
+        const OZC_AS_CONST ModConst &mc = const_ptr(tab)->mod[l];
         const float p = mc.pf, ip = mc.ipf;
         float w[NF];
 #pragma unroll
