@@ -224,16 +224,13 @@ void check_tolerances(const ozc_context *h, bool single, int64_t n, int64_t k, d
     *gam = 4.0 * (double)(n + k + 4) * 0x1p-104;  // rounding of the double-double evaluation
 }
 
-ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
-                           int64_t n, int64_t k, const double alpha[2], const void *A,
-                           int64_t lda, const void *B, int64_t ldb, const double beta[2],
-                           const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
-                           const CheckBufs &b, unsigned long long *word, hipStream_t s) {
+ozc_status_t enqueue_check_inputs(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
+                                  int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                                  const void *B, int64_t ldb, const double beta[2],
+                                  const void *cin, int64_t ld_cin, const CheckBufs &b, hipStream_t s) {
     const uint64_t seed = h->verify_seed;
-    double rel, gam;
-    check_tolerances(h, single, n, k, &rel, &gam);
     const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
-    // v = C_in x (m), y = op(B) x (k), z = op(A) y (m), w = C x (m)
+    // v = C_in x (m), y = op(B) x (k), z = op(A) y (m)
     if (!beta_zero)
         OZC_TRY(launch_gemv(cin, single, 0, m, n, ld_cin, nullptr, nullptr, nullptr, seed, b.v, b.vl,
                             b.va, b.scratch, s));
@@ -248,13 +245,34 @@ ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb
     else
         OZC_TRY(launch_gemv(A, single, (int)ta, k, m, lda, b.y, b.yl, b.ya, 0, b.z, b.zl, b.za,
                             b.scratch, s));
-    OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, seed, b.w, b.wl, b.wa,
-                        b.scratch, s));
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t enqueue_check_result(ozc_context *h, bool single, int64_t m, int64_t n, int64_t k,
+                                  const double alpha[2], const double beta[2], const void *C,
+                                  int64_t ldc, const CheckBufs &b, unsigned long long *word,
+                                  hipStream_t s) {
+    double rel, gam;
+    check_tolerances(h, single, n, k, &rel, &gam);
+    const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
+    // w = C x (m), then the row test against alpha z + beta v
+    OZC_TRY(launch_gemv(C, single, 0, m, n, ldc, nullptr, nullptr, nullptr, h->verify_seed, b.w, b.wl,
+                        b.wa, b.scratch, s));
     OZC_TRY(launch_freivalds_rows(b.w, b.wl, b.wa, b.z, b.zl, b.za, beta_zero ? nullptr : b.v, b.vl,
                                   b.va, m, alpha, beta, rel, gam, word, s));
     return OZC_STATUS_SUCCESS;
 }
 
+ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                           int64_t n, int64_t k, const double alpha[2], const void *A,
+                           int64_t lda, const void *B, int64_t ldb, const double beta[2],
+                           const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
+                           const CheckBufs &b, unsigned long long *word, hipStream_t s) {
+    ozc_status_t st = enqueue_check_inputs(h, single, ta, tb, m, n, k, A, lda, B, ldb, beta, cin,
+                                           ld_cin, b, s);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    return enqueue_check_result(h, single, m, n, k, alpha, beta, C, ldc, b, word, s);
+}
 
 ozc_status_t ensure_vws(ozc_context *h, size_t bytes) {
     if (bytes <= h->vws_bytes) return OZC_STATUS_SUCCESS;
@@ -532,24 +550,43 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
             h->pre = PreStats{};
         }
     } restore0{h, h->nmod};
+    // The learned count is enqueued first and awaited as late as possible: with the check
+    // on, its products with the inputs run while the host waits for the count.
+    bool pending = false;
+    int N_pred = h->nmod;
     if (h->auto_n) {
         ozc_status_t sa = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
         if (sa != OZC_STATUS_SUCCESS) return sa;
-        int N = 9;  // complex64: the fixed count (single-precision level)
+        N_pred = 9;  // complex64: the fixed count (single-precision level)
         if (!single) {
             OZC_TRY(hipSetDevice(h->device));
             // the prediction's scaling statistics serve every attempt of this call
-            sa = predict_moduli(h, single, ta, tb, m, n, k, A, lda, B, ldb, &N, &h->pre);
+            sa = predict_moduli_begin(h, single, ta, tb, m, n, k, A, lda, B, ldb, &N_pred, &h->pre,
+                                      &pending);
             if (sa != OZC_STATUS_SUCCESS) return sa;
         }
-        h->nmod = N;
     }
-    if (!h->verify) return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
-    ozc_status_t st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
+    auto take_count = [&]() -> ozc_status_t {
+        if (pending) {
+            pending = false;
+            ozc_status_t sw = predict_moduli_wait(h, &N_pred);
+            if (sw != OZC_STATUS_SUCCESS) return sw;
+        }
+        h->nmod = N_pred;
+        return OZC_STATUS_SUCCESS;
+    };
+    ozc_status_t st;
+    if (!h->verify) {
+        if ((st = take_count()) != OZC_STATUS_SUCCESS) return st;
+        return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+    }
+    st = check_args(ta, tb, m, n, k, A, lda, B, ldb, C, ldc, false);
     if (st != OZC_STATUS_SUCCESS) return st;
     const bool alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0;
-    if (m == 0 || n == 0 || k == 0 || alpha_zero)
+    if (m == 0 || n == 0 || k == 0 || alpha_zero) {
+        if ((st = take_count()) != OZC_STATUS_SUCCESS) return st;
         return run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
+    }
     hipStream_t s = h->stream;
     OZC_TRY(hipSetDevice(h->device));
     const bool beta_zero = beta[0] == 0.0 && beta[1] == 0.0;
@@ -567,6 +604,10 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
     void *cin = vw + o_cin;
     if (!beta_zero)
         OZC_TRY(hipMemcpy2DAsync(cin, es * m, C, es * ldc, es * m, n, hipMemcpyDeviceToDevice, s));
+    // the check's products with the inputs: once per call (reruns do not change them)
+    st = enqueue_check_inputs(h, single, ta, tb, m, n, k, A, lda, B, ldb, beta, cin, m, bufs, s);
+    if (st != OZC_STATUS_SUCCESS) return st;
+    if ((st = take_count()) != OZC_STATUS_SUCCESS) return st;
     struct RestoreN {
         ozc_context *h;
         int n0;
@@ -579,8 +620,7 @@ ozc_status_t run_verified(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
         h->nmod = N;
         st = run(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr);
         if (st != OZC_STATUS_SUCCESS) break;
-        st = enqueue_check(h, single, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, cin, m,
-                           bufs, word, s);
+        st = enqueue_check_result(h, single, m, n, k, alpha, beta, C, ldc, bufs, word, s);
         if (st != OZC_STATUS_SUCCESS) break;
         unsigned long long host[2] = {0, 0};
         OZC_TRY(hipMemcpyAsync(host, word, sizeof(host), hipMemcpyDeviceToHost, s));

@@ -35,12 +35,18 @@ struct MlpState {
     int margin = 0;         // added to the predicted count
     char *many = nullptr;   // scratch of the many-product prediction
     size_t many_bytes = 0;
+    // one product's predicted class, copied to pinned host memory and awaited through an
+    // event, so that the stream keeps the work queued behind the copy
+    int *cls_host = nullptr;
+    hipEvent_t cls_ready = nullptr;
 
     void release() {
         for (void *p : {(void *)params, (void *)m, (void *)v, (void *)grad, (void *)loss_acc,
                         (void *)pred, (void *)acts, (void *)idx, (void *)stat, (void *)feat,
                         (void *)many})
             if (p) (void)hipFree(p);
+        if (cls_host) (void)hipHostFree(cls_host);
+        if (cls_ready) (void)hipEventDestroy(cls_ready);
     }
 };
 
@@ -178,12 +184,15 @@ ozc_status_t compute_features(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t
     return OZC_STATUS_SUCCESS;
 }
 
-// Predicted N for one product (synchronises the stream).  Without parameters:
-// the fixed fallback count.  pre (may be null) receives the scaling statistics the
-// prediction computed, for the call that follows.
-ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
-                            int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
-                            int64_t ldb, int *N, PreStats *pre) {
+// Enqueues the prediction of N for one product.  *pending tells whether the count is
+// still on its way (then predict_moduli_wait delivers it); otherwise *N is final (the
+// fixed fallback count without parameters or for an empty product).  pre (may be
+// null) receives the scaling statistics the prediction computes, for the call that
+// follows.  Work the caller enqueues before the wait runs while the host waits.
+ozc_status_t predict_moduli_begin(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
+                                  int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                                  const void *B, int64_t ldb, int *N, PreStats *pre, bool *pending) {
+    *pending = false;
     if (pre) *pre = PreStats{};
     MlpState *st = mlp_state(h);
     if (!st) return OZC_STATUS_ALLOC_FAILED;
@@ -191,14 +200,40 @@ ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t t
         *N = st->n_fix;
         return OZC_STATUS_SUCCESS;
     }
+    if (!st->cls_host) {
+        if (hipHostMalloc((void **)&st->cls_host, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+            st->cls_host = nullptr;
+            (void)hipGetLastError();
+            return OZC_STATUS_ALLOC_FAILED;
+        }
+    }
+    if (!st->cls_ready) OZC_TRY(hipEventCreateWithFlags(&st->cls_ready, hipEventDisableTiming));
     ozc_status_t s = compute_features(h, single, ta, tb, m, n, k, A, lda, B, ldb, st->feat, pre);
     if (s != OZC_STATUS_SUCCESS) return s;
     OZC_TRY(launch_mlp_infer(kDims, st->params, st->feat, 1, st->pred, h->stream));
-    int cls = 0;
-    OZC_TRY(hipMemcpyAsync(&cls, st->pred, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    OZC_TRY(hipStreamSynchronize(h->stream));
+    OZC_TRY(hipMemcpyAsync(st->cls_host, st->pred, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    OZC_TRY(hipEventRecord(st->cls_ready, h->stream));
+    *pending = true;
+    return OZC_STATUS_SUCCESS;
+}
+
+ozc_status_t predict_moduli_wait(ozc_context *h, int *N) {
+    MlpState *st = h->mlp;
+    if (!st || !st->cls_ready || !st->cls_host) return OZC_STATUS_INVALID_VALUE;
+    OZC_TRY(hipEventSynchronize(st->cls_ready));
+    const int cls = *(volatile int *)st->cls_host;
     *N = std::min(OZC_MAX_MODULI, std::max(OZC_MIN_MODULI, OZC_MLP_MIN_N + cls + st->margin));
     return OZC_STATUS_SUCCESS;
+}
+
+// Predicted N for one product (waits for it).
+ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
+                            int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
+                            int64_t ldb, int *N, PreStats *pre) {
+    bool pending = false;
+    ozc_status_t s = predict_moduli_begin(h, single, ta, tb, m, n, k, A, lda, B, ldb, N, pre, &pending);
+    if (s != OZC_STATUS_SUCCESS || !pending) return s;
+    return predict_moduli_wait(h, N);
 }
 
 // Predicted N for many products at once: one statistics pass over all

@@ -74,6 +74,12 @@ void mlp_release(ozc_context *h);
 ozc_status_t predict_moduli(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb, int64_t m,
                             int64_t n, int64_t k, const void *A, int64_t lda, const void *B,
                             int64_t ldb, int *N, PreStats *pre);
+// The same in two steps: begin enqueues the prediction (pending: the count is on its way),
+// wait delivers the count; the stream may take more work in between.
+ozc_status_t predict_moduli_begin(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
+                                  int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                                  const void *B, int64_t ldb, int *N, PreStats *pre, bool *pending);
+ozc_status_t predict_moduli_wait(ozc_context *h, int *N);
 ozc_status_t predict_moduli_many(ozc_context *h, bool single, const std::vector<OperandView> &va,
                                  const std::vector<OperandView> &vb, std::vector<int> &N);
 
@@ -99,4 +105,14 @@ ozc_status_t enqueue_check(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb
                            int64_t lda, const void *B, int64_t ldb, const double beta[2],
                            const void *C, int64_t ldc, const void *cin, int64_t ld_cin,
                            const CheckBufs &b, unsigned long long *word, hipStream_t s);
+// Its two parts: the products with the inputs (C_in x, op(B) x, op(A) op(B) x), which
+// no rerun changes, and the part that reads the result (C x and the row test).
+ozc_status_t enqueue_check_inputs(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t tb,
+                                  int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                                  const void *B, int64_t ldb, const double beta[2],
+                                  const void *cin, int64_t ld_cin, const CheckBufs &b, hipStream_t s);
+ozc_status_t enqueue_check_result(ozc_context *h, bool single, int64_t m, int64_t n, int64_t k,
+                                  const double alpha[2], const double beta[2], const void *C,
+                                  int64_t ldc, const CheckBufs &b, unsigned long long *word,
+                                  hipStream_t s);
 }  // namespace ozc
