@@ -326,8 +326,8 @@ __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t 
 // ---------------------------------------------------------------- residue split
 // Truncation a' = trunc(x 2^mu) and symmetric residues modulo every p_l (and,
 // for Karatsuba, the reduced sum of the real and imaginary residues), written
-// zero-padded to rows_pad x k_pad in the slab-major order of the product
-// kernels.  No LDS staging: a block of 256 threads covers 16 rows and one
+// with zero k-padding to k_pad in the slab-major order of the product kernels
+// (rows up to rows_pad; the padding rows are left as they are).  No LDS staging: a block of 256 threads covers 16 rows and one
 // 64-wide k-slab; each thread holds 4 consecutive k of one row and writes
 // their residues as one 4-byte word per plane and modulus.  Sixteen
 // consecutive lanes share a row, so each wave writes 4 whole 64-byte rows
@@ -415,11 +415,13 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
     const int64_t h0 = bx * kTileH + kEPT * oc;
     const int64_t plane_pitch = rows_pad * k_pad;
 
-    int ex = kExpZero;
-    if (r < v.rows) ex = global_ptr(mu)[r];
+    // Rows past the operand (row padding) are not written: they meet only output rows or
+    // columns past the product, which nothing reads.  Padding along k must be zero.
+    if (r >= v.rows) return;
+    const int ex = global_ptr(mu)[r];
     const bool live = ex != kExpZero && ex != kExpNonfinite;
     int8_t *out = dst + (bx * rows_pad + r) * kTileH + kEPT * oc;
-    if (!live || h0 >= v.k) {  // padding, or a row without scaling: every residue is 0
+    if (!live || h0 >= v.k) {  // k padding, or a row without scaling: every residue is 0
         const int z[kEPT] = {};
         for (int q = 0; q < nmod * NPLANES; ++q) store_res(out + (int64_t)q * plane_pitch, z);
         return;

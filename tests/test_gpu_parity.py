@@ -186,6 +186,21 @@ def test_edge_cases(handle, orc):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("algo", ["karatsuba", "4m"])
+def test_row_padding_left_from_an_earlier_call(handle, orc, algo):
+    """The split leaves the padding rows of the residue planes as an earlier call left
+    them (they meet only output rows and columns past the product): a ragged product
+    right after a larger one with other data and moduli count in the same workspace keeps
+    every intermediate and the output bit-exact."""
+    A = workloads.complex_matrix(600, 300, 4.0, 901)
+    B = workloads.complex_matrix(300, 500, 4.0, 902)
+    _gemm_call(handle, A, B, np.zeros((600, 500)), 1.0, 0.0, 20, "fast", algo)
+    A = workloads.complex_matrix(131, 190, 0.5, 903)
+    B = workloads.complex_matrix(190, 77, 0.5, 904)
+    g, ref = _run_inspect(handle, orc, A, B, 14, "fast", algo)
+    _check_inspect(g, ref, algo)
+
+
 def test_nonfinite_inputs(handle, orc):
     A = workloads.complex_matrix(40, 20, 1.0, 71)
     B = workloads.complex_matrix(20, 30, 1.0, 72)
