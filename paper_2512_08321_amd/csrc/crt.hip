@@ -9,48 +9,53 @@
 // equation (5); Section IV-A); here S is accumulated exactly in signed
 // 19-bit limbs with 32-bit integer multiply-adds (N * 128 * 2^19 < 2^31 for
 // N <= 24), which removes the reconstruction error altogether and makes the
-// output bit-reproducible against an exact reference.
+// output bit-reproducible against an exact reference.  The reduction mod P works
+// on pairs of limbs as 38-bit chunks in FP64 (exact integers below 2^53), the
+// rounding on the 256-bit integer |C'|.
 #include "internal.h"
 
 namespace ozc {
 namespace {
 
-constexpr int32_t kLimbMask = (1 << kLimbBits) - 1;
-
-template <int L>
-__device__ __forceinline__ void normalize(int32_t (&a)[L]) {
-    int32_t c = 0;
-#pragma unroll
-    for (int j = 0; j < L - 1; ++j) {
-        const int32_t v = a[j] + c;
-        a[j] = v & kLimbMask;
-        c = v >> kLimbBits;  // arithmetic shift: floor division
-    }
-    a[L - 1] += c;
-}
-
-// After normalize(): value >= 0  <=>  top limb >= 0.
 using ConstTab = const OZC_AS_CONST NTable *;
 
-template <int L>
-__device__ __forceinline__ void settle_range(int32_t (&a)[L], ConstTab tab) {
-    int32_t t[L];
+// The reduction works on 38-bit chunks (two limbs each) held in FP64: every value it
+// forms is an integer below 2^53, so every operation below is exact.
+constexpr double kChunk = 274877906944.0;            // 2^38
+constexpr double kInvChunk = 1.0 / 274877906944.0;   // 2^-38
+
+// Chunks 0 .. C-2 into [0, 2^38), the carries into the top chunk (which keeps the sign).
+template <int C>
+__device__ __forceinline__ void normalize(double (&r)[C]) {
 #pragma unroll
-    for (int j = 0; j < L; ++j) t[j] = 2 * a[j] - tab->Plimb[j];
-    normalize<L>(t);
-    if (t[L - 1] >= 0) {  // 2R >= P
+    for (int c = 0; c < C - 1; ++c) {
+        const double f = floor(r[c] * kInvChunk);
+        r[c] = fma(-f, kChunk, r[c]);
+        r[c + 1] += f;
+    }
+}
+
+// After normalize(): value >= 0  <=>  top chunk >= 0.  Brings R into [-P/2, P/2)
+// when the quotient estimate was one off.
+template <int C>
+__device__ __forceinline__ void settle_range(double (&r)[C], ConstTab tab) {
+    double t[C];
 #pragma unroll
-        for (int j = 0; j < L; ++j) a[j] -= tab->Plimb[j];
-        normalize<L>(a);
+    for (int c = 0; c < C; ++c) t[c] = 2.0 * r[c] - tab->Pchunk[c];
+    normalize<C>(t);
+    if (t[C - 1] >= 0.0) {  // 2R >= P
+#pragma unroll
+        for (int c = 0; c < C; ++c) r[c] -= tab->Pchunk[c];
+        normalize<C>(r);
         return;
     }
 #pragma unroll
-    for (int j = 0; j < L; ++j) t[j] = 2 * a[j] + tab->Plimb[j];
-    normalize<L>(t);
-    if (t[L - 1] < 0) {  // 2R < -P
+    for (int c = 0; c < C; ++c) t[c] = 2.0 * r[c] + tab->Pchunk[c];
+    normalize<C>(t);
+    if (t[C - 1] < 0.0) {  // 2R < -P
 #pragma unroll
-        for (int j = 0; j < L; ++j) a[j] += tab->Plimb[j];
-        normalize<L>(a);
+        for (int c = 0; c < C; ++c) r[c] += tab->Pchunk[c];
+        normalize<C>(r);
     }
 }
 
@@ -108,38 +113,50 @@ __device__ __forceinline__ bool rounding_residual(const uint64_t (&w)[4], double
     return true;
 }
 
-// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised limbs.  With
-// low (and shl) non-null, also the rounding residual mod(S, P) - d 2^sh rounded to
-// nearest-even as *low * 2^shl (0 when d is exact), for double-double outputs.
+// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised 19-bit limbs
+// (|a_j| < 2^31).  With low (and shl) non-null, also the rounding residual
+// mod(S, P) - d 2^sh rounded to nearest-even as *low * 2^shl (0 when d is exact), for
+// double-double outputs.
+// Pairs of limbs become 38-bit chunks in FP64 (|r_c| < 2^50, exact); the quotient q =
+// rint(S / P) comes from their Horner sum times fl(1/P) (error far below 2^-20, since
+// |S| < 2^7 N P); R = S - q P chunk by chunk (|q P_c| < 2^50, exact); a quotient within
+// 2^-20 of a tie is checked exactly (settle_range).  |R| then goes to a 256-bit integer
+// for the rounding.
 template <int L>
 __device__ __forceinline__ double reconstruct(int32_t (&a)[L], ConstTab tab, int &sh,
                                               double *low = nullptr, int *shl = nullptr) {
-    normalize<L>(a);
-    constexpr int lo = L >= 3 ? L - 3 : 0;
-    double sa = 0.0;
+    constexpr int C = (L + 1) / 2;
+    double r[C];
 #pragma unroll
-    for (int j = L - 1; j >= lo; --j) sa = sa * (double)(1 << kLimbBits) + (double)a[j];
-    const double x = ldexp(sa, kLimbBits * lo) * tab->inv_P;  // ~ S / P, error < 2^-36
-    const double qd = rint(x);
-    const int32_t q = (int32_t)qd;  // |q| <= 128 N + 1 < 2^12
+    for (int c = 0; c < C; ++c)
+        r[c] = 2 * c + 1 < L ? fma((double)a[2 * c + 1], (double)(1 << kLimbBits), (double)a[2 * c])
+                             : (double)a[2 * c];
+    double sa = r[C - 1];
 #pragma unroll
-    for (int j = 0; j < L; ++j) a[j] -= q * tab->Plimb[j];
-    normalize<L>(a);
-    if (fabs(x - qd) > 0.5 - 1.0 / 1048576.0) settle_range<L>(a, tab);
+    for (int c = C - 2; c >= 0; --c) sa = fma(sa, kChunk, r[c]);
+    const double x = sa * tab->inv_P;  // ~ S / P
+    const double qd = rint(x);         // |q| <= 128 N + 1 < 2^12
+#pragma unroll
+    for (int c = 0; c < C; ++c) r[c] = fma(-qd, tab->Pchunk[c], r[c]);
+    normalize<C>(r);
+    if (fabs(x - qd) > 0.5 - 1.0 / 1048576.0) settle_range<C>(r, tab);
 
-    const bool neg = a[L - 1] < 0;
+    const bool neg = r[C - 1] < 0.0;
     if (neg) {
 #pragma unroll
-        for (int j = 0; j < L; ++j) a[j] = -a[j];
-        normalize<L>(a);
+        for (int c = 0; c < C; ++c) r[c] = -r[c];
+        normalize<C>(r);
     }
+    // chunk c (in [0, 2^38), the top one too since |R| < P / 2) at bit 38 c
     uint64_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-        const int o = kLimbBits * j;
-        const uint64_t v = (uint64_t)(uint32_t)a[j];
+    for (int c = 0; c < C; ++c) {
+        const double hi = floor(r[c] * 0x1p-32);
+        const uint32_t lo32 = (uint32_t)fma(-hi, 0x1p32, r[c]);
+        const uint64_t v = ((uint64_t)(uint32_t)hi << 32) | lo32;
+        const int o = 2 * kLimbBits * c;
         w[o >> 6] |= v << (o & 63);
-        if ((o & 63) + kLimbBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
+        if ((o & 63) + 2 * kLimbBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
     }
     const double d = round_w4(w, sh);
     if (low) {
@@ -147,9 +164,9 @@ __device__ __forceinline__ double reconstruct(int32_t (&a)[L], ConstTab tab, int
         *shl = 0;
         const bool exact = (w[1] | w[2] | w[3]) == 0 && w[0] < (1ull << 53);
         if (!exact) {
-            uint64_t r[4];
-            const bool rneg = rounding_residual(w, d, sh, r);
-            const double e = round_w4(r, *shl);
+            uint64_t rr[4];
+            const bool rneg = rounding_residual(w, d, sh, rr);
+            const double e = round_w4(rr, *shl);
             *low = e == 0.0 ? 0.0 : ((rneg != neg) ? -e : e);  // a zero residual is +0
         }
     }

@@ -48,6 +48,7 @@ struct NTable {
     int32_t n;
     int32_t nlimbs;               // limbs of P (and of every s_l)
     int32_t Plimb[kMaxLimbs];     // 19-bit limbs of P
+    double Pchunk[(kMaxLimbs + 1) / 2];  // 38-bit chunks of P (limb 2c + limb (2c+1) 2^19)
     double P_approx;              // P rounded to double
     double inv_P;                 // 1 / P rounded to double
     int32_t fast_tmax;            // largest t with 2^(2t+5) <= P - 1

@@ -136,6 +136,9 @@ void build_tables(NTable *tables) {
         const int pbits = P.bitlen();
         t.nlimbs = (pbits + kLimbBits - 1) / kLimbBits;
         for (int j = 0; j < t.nlimbs; ++j) t.Plimb[j] = (int32_t)P.bits(kLimbBits * j, kLimbBits);
+        for (int c = 0; 2 * c < t.nlimbs; ++c)  // exact: below 2^38
+            t.Pchunk[c] = (double)t.Plimb[2 * c] +
+                          (2 * c + 1 < t.nlimbs ? (double)t.Plimb[2 * c + 1] * (double)(1 << kLimbBits) : 0.0);
         t.P_approx = P.approx();
         t.inv_P = 1.0 / t.P_approx;
 
