@@ -6,12 +6,11 @@
 // into [-P/2, P/2) and rounds C' to the nearest double (ties to even), then
 // scales by 2^-(mu_i + nu_j).  The paper evaluates S as an unevaluated sum
 // of two doubles and reduces it in double-double arithmetic (Section II,
-// equation (5); Section IV-A); here S is accumulated exactly in signed
-// 19-bit limbs with 32-bit integer multiply-adds (N * 128 * 2^19 < 2^31 for
-// N <= 24), which removes the reconstruction error altogether and makes the
-// output bit-reproducible against an exact reference.  The reduction mod P works
-// on pairs of limbs as 38-bit chunks in FP64 (exact integers below 2^53), the
-// rounding on the 256-bit integer |C'|.
+// equation (5); Section IV-A); here S is accumulated exactly as 38-bit chunks
+// in FP64 (s_l split into 38-bit chunks, every partial sum an integer below
+// 24 * 2^38 * 2^7 < 2^53), and reduced mod P on the same chunks, which removes
+// the reconstruction error altogether and makes the output bit-reproducible
+// against an exact reference; the rounding works on the 256-bit integer |C'|.
 #include "internal.h"
 
 namespace ozc {
@@ -113,24 +112,17 @@ __device__ __forceinline__ bool rounding_residual(const uint64_t (&w)[4], double
     return true;
 }
 
-// mod(S, P) rounded to nearest-even as d * 2^sh; S given as unnormalised 19-bit limbs
-// (|a_j| < 2^31).  With low (and shl) non-null, also the rounding residual
-// mod(S, P) - d 2^sh rounded to nearest-even as *low * 2^shl (0 when d is exact), for
-// double-double outputs.
-// Pairs of limbs become 38-bit chunks in FP64 (|r_c| < 2^50, exact); the quotient q =
-// rint(S / P) comes from their Horner sum times fl(1/P) (error far below 2^-20, since
-// |S| < 2^7 N P); R = S - q P chunk by chunk (|q P_c| < 2^50, exact); a quotient within
-// 2^-20 of a tie is checked exactly (settle_range).  |R| then goes to a 256-bit integer
-// for the rounding.
-template <int L>
-__device__ __forceinline__ double reconstruct(int32_t (&a)[L], ConstTab tab, int &sh,
+// mod(S, P) rounded to nearest-even as d * 2^sh; S given as C unnormalised 38-bit
+// chunks in FP64 (|r_c| < 2^50).  With low (and shl) non-null, also the rounding
+// residual mod(S, P) - d 2^sh rounded to nearest-even as *low * 2^shl (0 when d is
+// exact), for double-double outputs.
+// The quotient q = rint(S / P) comes from the chunks' Horner sum times fl(1/P) (error
+// far below 2^-20, since |S| < 2^7 N P); R = S - q P chunk by chunk (|q P_c| < 2^50,
+// exact); a quotient within 2^-20 of a tie is checked exactly (settle_range).  |R| then
+// goes to a 256-bit integer for the rounding.
+template <int C>
+__device__ __forceinline__ double reconstruct(double (&r)[C], ConstTab tab, int &sh,
                                               double *low = nullptr, int *shl = nullptr) {
-    constexpr int C = (L + 1) / 2;
-    double r[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        r[c] = 2 * c + 1 < L ? fma((double)a[2 * c + 1], (double)(1 << kLimbBits), (double)a[2 * c])
-                             : (double)a[2 * c];
     double sa = r[C - 1];
 #pragma unroll
     for (int c = C - 2; c >= 0; --c) sa = fma(sa, kChunk, r[c]);
@@ -234,11 +226,14 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     if (j >= a.n || ib >= a.m) return;
 
     const int64_t planeC = a.n_pad * a.m_pad;
-    int32_t accR[4][L], accI[4][L];
+    // S = sum_l s_l E'_l in 38-bit chunks: |partial sums| < 24 2^38 2^7 < 2^50, every
+    // fused multiply-add exact
+    constexpr int C = (L + 1) / 2;
+    double accR[4][C], accI[4][C];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int q = 0; q < L; ++q) accR[u][q] = accI[u][q] = 0;
+        for (int c = 0; c < C; ++c) accR[u][c] = accI[u][c] = 0.0;
 
     ConstTab tab = const_ptr(a.tab);
     const OZC_AS_GLOBAL int8_t *E = global_ptr(a.eprime) + j * a.m_pad + ib;
@@ -247,20 +242,20 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         const uint32_t wr = *reinterpret_cast<const OZC_AS_GLOBAL uint32_t *>(E + (int64_t)(EPL * l) * planeC);
         const uint32_t wi =
             REAL ? 0u : *reinterpret_cast<const OZC_AS_GLOBAL uint32_t *>(E + (int64_t)(EPL * l + 1) * planeC);
-        int er[4], ei[4];
+        double er[4], ei[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            er[u] = (int)(int8_t)(wr >> (8 * u));
-            ei[u] = (int)(int8_t)(wi >> (8 * u));
+            er[u] = (double)(int)(int8_t)(wr >> (8 * u));
+            ei[u] = (double)(int)(int8_t)(wi >> (8 * u));
         }
-        const OZC_AS_CONST int32_t *sl = tab->mod[l].slimb;
+        const OZC_AS_CONST double *sc = tab->mod[l].schunk;
 #pragma unroll
-        for (int q = 0; q < L; ++q) {
-            const int32_t s = sl[q];
+        for (int c = 0; c < C; ++c) {
+            const double s = sc[c];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                accR[u][q] += __mul24(s, er[u]);
-                if constexpr (!REAL) accI[u][q] += __mul24(s, ei[u]);
+                accR[u][c] = fma(s, er[u], accR[u][c]);
+                if constexpr (!REAL) accI[u][c] = fma(s, ei[u], accI[u][c]);
             }
         }
     }
@@ -282,16 +277,16 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
         } else if constexpr (DD) {
             int shr, shi, slr, sli;
             double er, ei;
-            const double dr = reconstruct<L>(accR[u], tab, shr, &er, &slr);
-            const double di = reconstruct<L>(accI[u], tab, shi, &ei, &sli);
+            const double dr = reconstruct<C>(accR[u], tab, shr, &er, &slr);
+            const double di = reconstruct<C>(accI[u], tab, shi, &ei, &sli);
             cr = ldexp(dr, shr - (mui + nuj));
             ci = ldexp(di, shi - (mui + nuj));
             lr = ldexp(er, slr - (mui + nuj));
             li = ldexp(ei, sli - (mui + nuj));
         } else {
             int shr, shi = 0;
-            const double dr = reconstruct<L>(accR[u], tab, shr);
-            const double di = REAL ? 0.0 : reconstruct<L>(accI[u], tab, shi);
+            const double dr = reconstruct<C>(accR[u], tab, shr);
+            const double di = REAL ? 0.0 : reconstruct<C>(accI[u], tab, shi);
             cr = ldexp(dr, shr - (mui + nuj));
             ci = REAL ? 0.0 : ldexp(di, shi - (mui + nuj));
         }

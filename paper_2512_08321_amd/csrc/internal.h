@@ -37,7 +37,7 @@ __device__ __forceinline__ const OZC_AS_CONST T *const_ptr(const T *p) {
 struct ModConst {
     uint32_t p;                  // modulus
     uint32_t half;               // ceil(p / 2): residues >= half map to r - p
-    int32_t slimb[kMaxLimbs];    // 19-bit limbs of s_l = (P / p_l) q_l
+    double schunk[(kMaxLimbs + 1) / 2];  // 38-bit chunks of s_l = (P / p_l) q_l (exact doubles)
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float
     float wf[kMaxFChunks];       // symmetric residue of 2^(11 j) mod p (|wf| <= p / 2)

@@ -174,7 +174,10 @@ void build_tables(NTable *tables) {
             const Big Ml = P.div(p);
             const uint32_t q = inverse_mod(Ml.mod(p), p);
             const Big s = Ml.mul(q);
-            for (int j = 0; j < t.nlimbs; ++j) mc.slimb[j] = (int32_t)s.bits(kLimbBits * j, kLimbBits);
+            for (int c = 0; 2 * c < t.nlimbs; ++c)  // exact: below 2^38
+                mc.schunk[c] = (double)s.bits(2 * kLimbBits * c, kLimbBits) +
+                               (double)s.bits(2 * kLimbBits * c + kLimbBits, kLimbBits) *
+                                   (double)(1 << kLimbBits);
         }
     }
 }
