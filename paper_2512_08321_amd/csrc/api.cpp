@@ -475,7 +475,7 @@ ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, in
         ca.m_pad = L.m_pad;
         ca.n_pad = L.n_pad;
         ca.nmod = h->nmod;
-        ca.nlimbs = th.nlimbs;
+        ca.nchunks = th.nchunks;
         ca.tab = tab;
         ca.mu = muA;
         ca.nu = nuB;

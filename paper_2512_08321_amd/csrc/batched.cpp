@@ -28,7 +28,7 @@ struct Problem {
 }  // namespace
 
 struct BatchPlan {
-    // A launch over a contiguous range of descriptors; param = chunk bits (split) or limbs (CRT).
+    // A launch over a contiguous range of descriptors; param = chunk bits (split) or chunks of P (CRT).
     struct Range {
         int first, count;
         int64_t blocks;
@@ -42,7 +42,7 @@ struct BatchPlan {
     std::vector<Range> splits;      // one split launch per chunk count
     std::vector<BatchGemm> gm[2];   // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
     std::vector<BatchCrt> crt;      // ordered by CRT launch
-    std::vector<Range> crts;        // one CRT launch per limb count
+    std::vector<Range> crts;        // one CRT launch per chunk count of P
     std::vector<BatchBound> bound;  // accurate mode: bound products
     int64_t blk_scan = 0, blk_exp = 0, blk_ceil7 = 0, items[2] = {0, 0}, bound_items = 0;
     size_t stats_off = 0, stats_words = 0, counter_off = 0;
@@ -180,7 +180,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     const int nprod = P.algo == 0 ? 3 : 4;
 
     struct Pad {
-        int tile, nmod, nf, nlimbs;
+        int tile, nmod, nf, nchunks;
         int64_t m_pad, n_pad, k_pad;
         size_t sA, sB, xA, xB, muA, muB, barA, barB, resA, resB, ep;
         size_t p;  // index into probs
@@ -203,7 +203,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         d.p = p;
         d.nmod = N;
         d.nf = split_fchunks(abits);
-        d.nlimbs = th.nlimbs;
+        d.nchunks = th.nchunks;
         d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
         d.m_pad = round_up(q.m, gemm_tile_rows(d.tile));
         d.n_pad = round_up(q.n, gemm_tile_cols(d.tile));
@@ -327,16 +327,16 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         g.nmod = d.nmod;
         P.gm[d.tile == 256 ? 0 : 1].push_back(g);
     }
-    // reconstruction ordered by limb count: one CRT launch per count
-    std::vector<const Pad *> by_limbs;
-    for (const Pad &d : pads) by_limbs.push_back(&d);
-    std::stable_sort(by_limbs.begin(), by_limbs.end(),
-                     [](const Pad *x, const Pad *y) { return x->nlimbs < y->nlimbs; });
-    for (const Pad *dp : by_limbs) {
+    // reconstruction ordered by the chunk count of P: one CRT launch per count
+    std::vector<const Pad *> by_chunks;
+    for (const Pad &d : pads) by_chunks.push_back(&d);
+    std::stable_sort(by_chunks.begin(), by_chunks.end(),
+                     [](const Pad *x, const Pad *y) { return x->nchunks < y->nchunks; });
+    for (const Pad *dp : by_chunks) {
         const Pad &d = *dp;
         const Problem &q = probs[d.p];
-        if (P.crts.empty() || P.crts.back().param != d.nlimbs)
-            P.crts.push_back({(int)P.crt.size(), 0, 0, d.nlimbs});
+        if (P.crts.empty() || P.crts.back().param != d.nchunks)
+            P.crts.push_back({(int)P.crt.size(), 0, 0, d.nchunks});
         BatchPlan::Range &cr = P.crts.back();
         BatchCrt c{};
         c.a.eprime = (const int8_t *)(uintptr_t)(ep_off + d.ep);
@@ -345,7 +345,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         c.a.m_pad = d.m_pad;
         c.a.n_pad = d.n_pad;
         c.a.nmod = d.nmod;
-        c.a.nlimbs = d.nlimbs;
+        c.a.nchunks = d.nchunks;
         c.a.tab = nullptr;  // bound later
         c.a.mu = (const int16_t *)(uintptr_t)(mu_off + d.muA);
         c.a.nu = (const int16_t *)(uintptr_t)(mu_off + d.muB);

@@ -20,8 +20,8 @@ using ConstTab = const OZC_AS_CONST NTable *;
 
 // The reduction works on 38-bit chunks (two limbs each) held in FP64: every value it
 // forms is an integer below 2^53, so every operation below is exact.
-constexpr double kChunk = 274877906944.0;            // 2^38
-constexpr double kInvChunk = 1.0 / 274877906944.0;   // 2^-38
+constexpr double kChunk = (double)(1ull << kChunkBits);   // 2^38
+constexpr double kInvChunk = 1.0 / kChunk;                 // 2^-38, exact
 
 // Chunks 0 .. C-2 into [0, 2^38), the carries into the top chunk (which keeps the sign).
 template <int C>
@@ -146,9 +146,9 @@ __device__ __forceinline__ double reconstruct(double (&r)[C], ConstTab tab, int 
         const double hi = floor(r[c] * 0x1p-32);
         const uint32_t lo32 = (uint32_t)fma(-hi, 0x1p32, r[c]);
         const uint64_t v = ((uint64_t)(uint32_t)hi << 32) | lo32;
-        const int o = 2 * kLimbBits * c;
+        const int o = kChunkBits * c;
         w[o >> 6] |= v << (o & 63);
-        if ((o & 63) + 2 * kLimbBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
+        if ((o & 63) + kChunkBits > 64) w[(o >> 6) + 1] |= v >> (64 - (o & 63));
     }
     const double d = round_w4(w, sh);
     if (low) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void store_c(void *C, int64_t idx, double re, double 
 // Real outputs (EK real) reconstruct the one E' plane of each modulus; alpha and beta
 // are real then (imaginary parts zero), so the fused multiply-add order below reduces
 // to x = alpha c, out = fma(beta, C, x).
-template <int L, int EK, bool DD = false>
+template <int C, int EK, bool DD = false>
 __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     constexpr bool REAL = elem_real(EK);
     constexpr int EPL = REAL ? 1 : 2;  // E' planes per modulus
@@ -228,7 +228,6 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     const int64_t planeC = a.n_pad * a.m_pad;
     // S = sum_l s_l E'_l in 38-bit chunks: |partial sums| < 24 2^38 2^7 < 2^50, every
     // fused multiply-add exact
-    constexpr int C = (L + 1) / 2;
     double accR[4][C], accI[4][C];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -304,17 +303,17 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
     }
 }
 
-template <int L, int EK>
+template <int C, int EK>
 __global__ __launch_bounds__(256) void crt_output_kernel(CrtArgs a) {
-    crt_output_body<L, EK>(a, blockIdx.x);
+    crt_output_body<C, EK>(a, blockIdx.x);
 }
 
-template <int L>
+template <int C>
 __global__ __launch_bounds__(256) void crt_dd_kernel(CrtArgs a) {
-    crt_output_body<L, kElemZ, true>(a, blockIdx.x);
+    crt_output_body<C, kElemZ, true>(a, blockIdx.x);
 }
 
-template <int L, bool SINGLE>
+template <int C, bool SINGLE>
 __global__ __launch_bounds__(256) void batch_crt_kernel(const BatchCrt *probs, int nprob) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nprob - 1;  // last problem whose first block is <= b
@@ -323,14 +322,14 @@ __global__ __launch_bounds__(256) void batch_crt_kernel(const BatchCrt *probs, i
         if (probs[mid].blk0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    crt_output_body<L, SINGLE>(probs[lo].a, b - probs[lo].blk0);
+    crt_output_body<C, SINGLE>(probs[lo].a, b - probs[lo].blk0);
 }
 
-template <int L>
-hipError_t launch_batch_L(const BatchCrt *probs, int nprob, int64_t blocks, bool single, hipStream_t s) {
+template <int C>
+hipError_t launch_batch_C(const BatchCrt *probs, int nprob, int64_t blocks, bool single, hipStream_t s) {
     dim3 grid((unsigned)blocks);
-    if (single) hipLaunchKernelGGL((batch_crt_kernel<L, true>), grid, dim3(256), 0, s, probs, nprob);
-    else hipLaunchKernelGGL((batch_crt_kernel<L, false>), grid, dim3(256), 0, s, probs, nprob);
+    if (single) hipLaunchKernelGGL((batch_crt_kernel<C, true>), grid, dim3(256), 0, s, probs, nprob);
+    else hipLaunchKernelGGL((batch_crt_kernel<C, false>), grid, dim3(256), 0, s, probs, nprob);
     return hipGetLastError();
 }
 
@@ -349,20 +348,20 @@ __global__ void scale_c_kernel(void *C, int64_t m, int64_t n, int64_t ldc, doubl
     store_c<EK>(C, j * ldc + i, orr, oi);
 }
 
-template <int L>
-hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
+template <int C>
+hipError_t launch_C(const CrtArgs &a, hipStream_t s) {
     const int64_t threads = ((a.m + 3) / 4) * a.n;
     dim3 grid((unsigned)((threads + 255) / 256));
     if (a.C_lo) {
         if (a.ek != kElemZ) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((crt_dd_kernel<L>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((crt_dd_kernel<C>), grid, dim3(256), 0, s, a);
         return hipGetLastError();
     }
     switch (a.ek) {
-        case kElemZ: hipLaunchKernelGGL((crt_output_kernel<L, kElemZ>), grid, dim3(256), 0, s, a); break;
-        case kElemC: hipLaunchKernelGGL((crt_output_kernel<L, kElemC>), grid, dim3(256), 0, s, a); break;
-        case kElemD: hipLaunchKernelGGL((crt_output_kernel<L, kElemD>), grid, dim3(256), 0, s, a); break;
-        case kElemS: hipLaunchKernelGGL((crt_output_kernel<L, kElemS>), grid, dim3(256), 0, s, a); break;
+        case kElemZ: hipLaunchKernelGGL((crt_output_kernel<C, kElemZ>), grid, dim3(256), 0, s, a); break;
+        case kElemC: hipLaunchKernelGGL((crt_output_kernel<C, kElemC>), grid, dim3(256), 0, s, a); break;
+        case kElemD: hipLaunchKernelGGL((crt_output_kernel<C, kElemD>), grid, dim3(256), 0, s, a); break;
+        case kElemS: hipLaunchKernelGGL((crt_output_kernel<C, kElemS>), grid, dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -373,18 +372,12 @@ hipError_t launch_L(const CrtArgs &a, hipStream_t s) {
 hipError_t launch_crt_output(const CrtArgs &a, hipStream_t s) {
     if (a.m <= 0 || a.n <= 0) return hipSuccess;
     if (a.m_pad % 4) return hipErrorInvalidValue;
-    switch (a.nlimbs) {
-        case 1: return launch_L<1>(a, s);
-        case 2: return launch_L<2>(a, s);
-        case 3: return launch_L<3>(a, s);
-        case 4: return launch_L<4>(a, s);
-        case 5: return launch_L<5>(a, s);
-        case 6: return launch_L<6>(a, s);
-        case 7: return launch_L<7>(a, s);
-        case 8: return launch_L<8>(a, s);
-        case 9: return launch_L<9>(a, s);
-        case 10: return launch_L<10>(a, s);
-        case 11: return launch_L<11>(a, s);
+    switch (a.nchunks) {
+        case 1: return launch_C<1>(a, s);
+        case 2: return launch_C<2>(a, s);
+        case 3: return launch_C<3>(a, s);
+        case 4: return launch_C<4>(a, s);
+        case 5: return launch_C<5>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -405,21 +398,15 @@ hipError_t launch_scale_c(void *C, int64_t m, int64_t n, int64_t ldc, int ek, do
 
 int64_t batch_crt_blocks(int64_t m, int64_t n) { return (((m + 3) / 4) * n + 255) / 256; }
 
-hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
+hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nchunks,
                             bool single, hipStream_t s) {
     if (blocks <= 0 || nprob <= 0) return hipSuccess;
-    switch (nlimbs) {
-        case 1: return launch_batch_L<1>(probs, nprob, blocks, single, s);
-        case 2: return launch_batch_L<2>(probs, nprob, blocks, single, s);
-        case 3: return launch_batch_L<3>(probs, nprob, blocks, single, s);
-        case 4: return launch_batch_L<4>(probs, nprob, blocks, single, s);
-        case 5: return launch_batch_L<5>(probs, nprob, blocks, single, s);
-        case 6: return launch_batch_L<6>(probs, nprob, blocks, single, s);
-        case 7: return launch_batch_L<7>(probs, nprob, blocks, single, s);
-        case 8: return launch_batch_L<8>(probs, nprob, blocks, single, s);
-        case 9: return launch_batch_L<9>(probs, nprob, blocks, single, s);
-        case 10: return launch_batch_L<10>(probs, nprob, blocks, single, s);
-        case 11: return launch_batch_L<11>(probs, nprob, blocks, single, s);
+    switch (nchunks) {
+        case 1: return launch_batch_C<1>(probs, nprob, blocks, single, s);
+        case 2: return launch_batch_C<2>(probs, nprob, blocks, single, s);
+        case 3: return launch_batch_C<3>(probs, nprob, blocks, single, s);
+        case 4: return launch_batch_C<4>(probs, nprob, blocks, single, s);
+        case 5: return launch_batch_C<5>(probs, nprob, blocks, single, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -7,8 +7,8 @@
 namespace ozc {
 
 constexpr int kMaxModuli = 24;
-constexpr int kLimbBits = 19;       // CRT limbs: N * 128 * (2^19 - 1) < 2^31 for N <= 24
-constexpr int kMaxLimbs = 11;       // ceil((log2 P + 1) / 19) for N <= 24
+constexpr int kChunkBits = 38;      // CRT in FP64 chunks: N * 128 * 2^38 < 2^53 for N <= 24
+constexpr int kMaxChunks = 5;       // ceil(bits(P) / 38) for N <= 24 (P below 2^185)
 constexpr int kFChunkBits = 11;     // residue split: |a'| as 11-bit chunks (FP32 arithmetic)
 constexpr int kMaxFChunks = 9;      // |a'| < 2^99 (N <= 24 needs at most 97 bits)
 constexpr int kThr = 64;            // threshold table length for the exponent rules
@@ -37,7 +37,7 @@ __device__ __forceinline__ const OZC_AS_CONST T *const_ptr(const T *p) {
 struct ModConst {
     uint32_t p;                  // modulus
     uint32_t half;               // ceil(p / 2): residues >= half map to r - p
-    double schunk[(kMaxLimbs + 1) / 2];  // 38-bit chunks of s_l = (P / p_l) q_l (exact doubles)
+    double schunk[kMaxChunks];   // 38-bit chunks of s_l = (P / p_l) q_l (exact doubles)
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float
     float wf[kMaxFChunks];       // symmetric residue of 2^(11 j) mod p (|wf| <= p / 2)
@@ -46,9 +46,8 @@ struct ModConst {
 // Constants of one moduli count N.
 struct NTable {
     int32_t n;
-    int32_t nlimbs;               // limbs of P (and of every s_l)
-    int32_t Plimb[kMaxLimbs];     // 19-bit limbs of P
-    double Pchunk[(kMaxLimbs + 1) / 2];  // 38-bit chunks of P (limb 2c + limb (2c+1) 2^19)
+    int32_t nchunks;              // 38-bit chunks of P (and of every s_l)
+    double Pchunk[kMaxChunks];    // 38-bit chunks of P (exact doubles)
     double P_approx;              // P rounded to double
     double inv_P;                 // 1 / P rounded to double
     int32_t fast_tmax;            // largest t with 2^(2t+5) <= P - 1
@@ -148,7 +147,7 @@ struct CrtArgs {
     const int8_t *eprime;  // [N][2][n_pad][m_pad] (real outputs: [N][n_pad][m_pad])
     int64_t m, n, m_pad, n_pad;
     int nmod;
-    int nlimbs;            // limbs of P for this N (host copy of tab->nlimbs)
+    int nchunks;           // chunks of P for this N (host copy of tab->nchunks)
     const NTable *tab;     // device pointer
     const int16_t *mu, *nu;
     double alpha_r, alpha_i, beta_r, beta_i;
@@ -231,7 +230,7 @@ struct BatchCrt {
     int64_t blk0;
 };
 int64_t batch_crt_blocks(int64_t m, int64_t n);  // blocks of one problem's reconstruction
-hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nlimbs,
+hipError_t launch_batch_crt(const BatchCrt *probs, int nprob, int64_t blocks, int nchunks,
                             bool single, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 

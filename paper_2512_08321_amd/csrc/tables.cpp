@@ -119,6 +119,12 @@ uint32_t inverse_mod(uint32_t a, uint32_t p) {  // a * x = 1 (mod p), p <= 256
 
 }  // namespace
 
+// Bits [38 c, 38 c + 38) of v as an exact double.
+static double chunk(const Big &v, int c) {
+    constexpr int h = kChunkBits / 2;
+    return (double)v.bits(kChunkBits * c, h) + (double)v.bits(kChunkBits * c + h, h) * (double)(1u << h);
+}
+
 void build_tables(NTable *tables) {
     // Step I: greedy descending pairwise-coprime integers <= 256.
     std::vector<int> all;
@@ -134,11 +140,10 @@ void build_tables(NTable *tables) {
         Big P(1);
         for (int l = 0; l < n; ++l) P = P.mul((uint32_t)all[l]);
         const int pbits = P.bitlen();
-        t.nlimbs = (pbits + kLimbBits - 1) / kLimbBits;
-        for (int j = 0; j < t.nlimbs; ++j) t.Plimb[j] = (int32_t)P.bits(kLimbBits * j, kLimbBits);
-        for (int c = 0; 2 * c < t.nlimbs; ++c)  // exact: below 2^38
-            t.Pchunk[c] = (double)t.Plimb[2 * c] +
-                          (2 * c + 1 < t.nlimbs ? (double)t.Plimb[2 * c + 1] * (double)(1 << kLimbBits) : 0.0);
+        // at most kMaxChunks for N <= 24; a larger count would make every CRT launch
+        // fail with an invalid-value error rather than overrun the tables
+        t.nchunks = (pbits + kChunkBits - 1) / kChunkBits;
+        for (int c = 0; c < std::min(t.nchunks, kMaxChunks); ++c) t.Pchunk[c] = chunk(P, c);
         t.P_approx = P.approx();
         t.inv_P = 1.0 / t.P_approx;
 
@@ -174,10 +179,7 @@ void build_tables(NTable *tables) {
             const Big Ml = P.div(p);
             const uint32_t q = inverse_mod(Ml.mod(p), p);
             const Big s = Ml.mul(q);
-            for (int c = 0; 2 * c < t.nlimbs; ++c)  // exact: below 2^38
-                mc.schunk[c] = (double)s.bits(2 * kLimbBits * c, kLimbBits) +
-                               (double)s.bits(2 * kLimbBits * c + kLimbBits, kLimbBits) *
-                                   (double)(1 << kLimbBits);
+            for (int c = 0; c < std::min(t.nchunks, kMaxChunks); ++c) mc.schunk[c] = chunk(s, c);
         }
     }
 }
