@@ -18,7 +18,7 @@ namespace {
 
 using ConstTab = const OZC_AS_CONST NTable *;
 
-// The reduction works on 38-bit chunks (two limbs each) held in FP64: every value it
+// The reduction works on the 38-bit chunks of S held in FP64: every value it
 // forms is an integer below 2^53, so every operation below is exact.
 constexpr double kChunk = (double)(1ull << kChunkBits);   // 2^38
 constexpr double kInvChunk = 1.0 / kChunk;                 // 2^-38, exact
