@@ -47,6 +47,40 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def paper_model_seconds(m, n, k, N, mode="fast", single=False, b=8e12, p=INT8_PEAK_TOPS * 1e12,
+                        c=None):
+    """Execution time of the emulation predicted by the paper's model (Section III-C):
+    the memory terms of the scaling, split, products and reconstruction steps over the
+    bandwidth b (bytes/s) plus the INT8 products over the matrix-engine rate p (ops/s).
+    c is the model's overhead term (the moduli count unless given).  The model assumes
+    3N separate INT8 GEMMs whose INT32 outputs make a round trip through memory, the
+    (14N + c) mn bytes of its product step."""
+    c = N if c is None else c
+    if mode == "fast":
+        per_k, per_mn = (3 * N + (16 if single else 32) + c, 16 * N + (8 if single else 16) + 2 * c)
+        mem = (per_k * k + 4) * (m + n) + per_mn * m * n
+        ops = 6.0 * N * m * n * k
+    else:
+        per_k, per_mn = ((19 if single else 35) + 3 * N + c, 16 * N + (32 if single else 40) + 2 * c)
+        mem = (per_k * k + 8) * (m + n) + per_mn * m * n
+        ops = 6.0 * (N + 1) * m * n * k
+    return mem / b + ops / p
+
+
+def model_line(m, n, k, N, args, copy_bw, achieved_tops, measured_ms):
+    """The paper's model (Section III-C) with this run's copy bandwidth and product-kernel
+    rate, beside the measured time; c = N as in the paper's heatmaps."""
+    if args.algo != "karatsuba":
+        return None  # the model is stated for the three-product (Karatsuba) form
+    t = paper_model_seconds(m, n, k, N, args.mode, args.single, b=copy_bw, p=achieved_tops * 1e12)
+    return {"section": "III-C", "c": N, "b_TBps": round(copy_bw / 1e12, 3),
+            "p_TOPS": round(achieved_tops, 1), "predicted_ms": round(t * 1e3, 2),
+            "predicted_tflops": round(8.0 * m * n * k / t / 1e12, 1),
+            "measured_ms": round(measured_ms, 2),
+            "note": "the model counts 3N separate INT8 GEMMs with an INT32 round trip "
+                    "((14N + c) mn bytes); the product kernel here reduces in registers"}
+
+
 def gemm_source_hash() -> str:
     with open(GEMM_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -167,6 +201,21 @@ def main():
         log(f"[bench] calibration copy of {nb} bytes done")
         del src, dst
 
+    # device-to-device copy bandwidth (read + written bytes per second), the b of the
+    # paper's performance model
+    cp_n = 2 ** 31
+    cp_src = torch.empty(cp_n, dtype=torch.uint8, device="cuda")
+    cp_dst = torch.empty(cp_n, dtype=torch.uint8, device="cuda")
+    cp_dst.copy_(cp_src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        cp_dst.copy_(cp_src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_bw = 3 * 2.0 * cp_n / (ev0.elapsed_time(ev1) * 1e-3)
+    del cp_src, cp_dst
+
     h = ozc.Handle(0, num_moduli=N, mode=args.mode, algo=args.algo)
     call = h.cgemm if args.single else h.zgemm
     if args.verify:
@@ -286,6 +335,7 @@ def main():
                      "traffic": traffic_from_profiles(workload_key)},
         "cpu_baseline": cpu,
         "workspace_gib": round(info["workspace"] / 2 ** 30, 2),
+        "paper_model": model_line(m, n, k, N, args, copy_bw, achieved, ms),
     }
     print(json.dumps(out), flush=True)
     h.close()

@@ -45,3 +45,44 @@ def test_traffic_follows_the_kernel_source_hash(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "gemm_source_hash", lambda: "0" * 16)
     assert bench.traffic_from_profiles(key) is None
     assert bench.traffic_from_profiles("no such workload") is None
+
+
+def test_performance_model_reproduces_the_worked_example():
+    """Section III-C: with 2-4 TB/s of bandwidth and 1500 TOPS of INT8 throughput the
+    model puts accurate-mode ZGEMM at m = n = k = 16384 (13 moduli, c = 13) near
+    120 TFLOPS."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    s = 16384
+    tflops = {b: 8.0 * s ** 3 / bench.paper_model_seconds(s, s, s, 13, "accurate", b=b * 1e12,
+                                                          p=1.5e15) / 1e12
+              for b in (2, 3, 4)}
+    assert 110 < tflops[2] < tflops[3] < tflops[4] < 130
+    assert abs(tflops[3] - 120) < 5
+    # the compute-bound limit: 8 mnk flops against 6 (N + 1) mnk INT8 operations
+    limit = 8.0 * 1.5e15 / (6 * 14) / 1e12
+    assert tflops[4] < limit
+    assert abs(8.0 * s ** 3 / bench.paper_model_seconds(s, s, s, 13, "accurate", b=1e30,
+                                                        p=1.5e15) / 1e12 - limit) < 1e-9
+
+
+def test_performance_model_orders_the_variants():
+    """Accurate mode costs one more product and more traffic than fast mode; single
+    precision moves fewer bytes than double; the memory terms shrink relative to the
+    products as k grows."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    s, N = 8192, 13
+    t = {(mode, single): bench.paper_model_seconds(s, s, s, N, mode, single, b=3e12, p=1.5e15)
+         for mode in ("fast", "accurate") for single in (False, True)}
+    assert t[("accurate", False)] > t[("fast", False)]
+    assert t[("accurate", True)] > t[("fast", True)]
+    assert t[("fast", True)] < t[("fast", False)]
+    assert t[("accurate", True)] < t[("accurate", False)]
+    # fast mode, double: steps 1-3 of the model summed by hand for m = n = k = 1, N = 1, c = 0
+    assert bench.paper_model_seconds(1, 1, 1, 1, "fast", b=1.0, p=1e300, c=0) == (35 + 4) * 2 + 32
+    share = [bench.paper_model_seconds(s, s, kk, N, b=3e12, p=1.5e15) / (6.0 * N * s * s * kk / 1.5e15)
+             for kk in (1024, 16384, 262144)]
+    assert share[0] > share[1] > share[2] > 1.0
