@@ -451,7 +451,7 @@ ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, in
         abits = th.max_abits_accu;
     }
     if (fault == 2) OZC_TRY(launch_debug_add_exp(muA, 12, s));
-    if (abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
+    if (abits > kMaxSplitBits) return OZC_STATUS_NOT_SUPPORTED;
 
     // Steps IV, V-i/ii: truncation and residues
     OZC_TRY(pe.mark(1));

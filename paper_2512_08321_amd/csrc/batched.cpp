@@ -39,7 +39,7 @@ struct BatchPlan {
     int algo = 0, planes = 0, group = 1, nmax = 0;
     size_t ws_bytes = 0;
     std::vector<BatchOperand> ops;  // ordered by split launch
-    std::vector<Range> splits;      // one split launch per chunk count
+    std::vector<Range> splits;      // one split launch per word count
     std::vector<BatchGemm> gm[2];   // [0]: 256 x 256 tiles, [1]: 128 x 128 tiles
     std::vector<BatchCrt> crt;      // ordered by CRT launch
     std::vector<Range> crts;        // one CRT launch per chunk count of P
@@ -180,7 +180,7 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     const int nprod = P.algo == 0 ? 3 : 4;
 
     struct Pad {
-        int tile, nmod, nf, nchunks;
+        int tile, nmod, nw, nchunks;
         int64_t m_pad, n_pad, k_pad;
         size_t sA, sB, xA, xB, muA, muB, barA, barB, resA, resB, ep;
         size_t p;  // index into probs
@@ -198,11 +198,11 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
         if (N < OZC_MIN_MODULI || N > OZC_MAX_MODULI) return OZC_STATUS_INVALID_VALUE;
         const NTable &th = h->tab_host[(size_t)N - 1];
         const int abits = P.accurate ? th.max_abits_accu : th.max_abits_fast;
-        if (abits > kFChunkBits * kMaxFChunks) return OZC_STATUS_NOT_SUPPORTED;
+        if (abits > kMaxSplitBits) return OZC_STATUS_NOT_SUPPORTED;
         Pad d{};
         d.p = p;
         d.nmod = N;
-        d.nf = split_fchunks(abits);
+        d.nw = split_words(abits);
         d.nchunks = th.nchunks;
         d.tile = std::min(q.m, q.n) >= pol.tile_threshold ? 256 : 128;
         d.m_pad = round_up(q.m, gemm_tile_rows(d.tile));
@@ -263,15 +263,15 @@ ozc_status_t plan_batch(const ozc_context *h, bool single, const ozc_batch_polic
     P.bound.clear();
     P.gm[0].clear();
     P.gm[1].clear();
-    // operands ordered by chunk count: one split launch per count
-    std::vector<const Pad *> by_nf;
-    for (const Pad &d : pads) by_nf.push_back(&d);
-    std::stable_sort(by_nf.begin(), by_nf.end(), [](const Pad *x, const Pad *y) { return x->nf < y->nf; });
-    for (const Pad *dp : by_nf) {
+    // operands ordered by word count of the split: one split launch per count
+    std::vector<const Pad *> by_nw;
+    for (const Pad &d : pads) by_nw.push_back(&d);
+    std::stable_sort(by_nw.begin(), by_nw.end(), [](const Pad *x, const Pad *y) { return x->nw < y->nw; });
+    for (const Pad *dp : by_nw) {
         const Pad &d = *dp;
         const Problem &q = probs[d.p];
-        if (P.splits.empty() || P.splits.back().param != d.nf * kFChunkBits)
-            P.splits.push_back({(int)P.ops.size(), 0, 0, d.nf * kFChunkBits});
+        if (P.splits.empty() || P.splits.back().param != 32 * d.nw - 1)
+            P.splits.push_back({(int)P.ops.size(), 0, 0, 32 * d.nw - 1});
         BatchPlan::Range &sr = P.splits.back();
         BatchOperand a{}, b{};
         a.v = view_A(q.A, q.ta, q.m, q.k, q.lda);

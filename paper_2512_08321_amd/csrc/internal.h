@@ -9,8 +9,8 @@ namespace ozc {
 constexpr int kMaxModuli = 24;
 constexpr int kChunkBits = 38;      // CRT in FP64 chunks: N * 128 * 2^38 < 2^53 for N <= 24
 constexpr int kMaxChunks = 5;       // ceil(bits(P) / 38) for N <= 24 (P below 2^185)
-constexpr int kFChunkBits = 11;     // residue split: |a'| as 11-bit chunks (FP32 arithmetic)
-constexpr int kMaxFChunks = 9;      // |a'| < 2^99 (N <= 24 needs at most 97 bits)
+constexpr int kMaxSplitWords = 4;  // residue split: a' as a biased integer of up to 4 32-bit
+                                    // words, so |a'| < 2^127 (N <= 24 needs at most 97 bits)
 constexpr int kThr = 64;            // threshold table length for the exponent rules
 constexpr int kSigmaFracBits = 20;  // fast mode: fixed-point fraction bits of sum of squares
 constexpr int kAccuIntBits = 6;     // accurate mode: magnitudes scaled below 2^6
@@ -40,7 +40,8 @@ struct ModConst {
     double schunk[kMaxChunks];   // 38-bit chunks of s_l = (P / p_l) q_l (exact doubles)
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float
-    float wf[kMaxFChunks];       // symmetric residue of 2^(11 j) mod p (|wf| <= p / 2)
+    uint32_t wbyte[kMaxSplitWords];  // byte 4 i + b of the words: 2^(8 (4 i + b)) mod p
+    uint32_t wbias[kMaxSplitWords];  // entry W - 1: -(2^(32 W - 1) mod p) (two's complement)
 };
 
 // Constants of one moduli count N.
@@ -96,7 +97,7 @@ hipError_t launch_ceil7(const OperandView &v, int ek, const uint64_t *maxbits,
 hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int64_t rows,
                                  int64_t rows_pad, const NTable *tab, int16_t *mu,
                                  uint32_t *status, hipStream_t s);
-// abits bounds the bit length of |a'| (at most 11 * kMaxFChunks).  nplanes: 3 (Karatsuba:
+// abits bounds the bit length of |a'| (at most 32 * kMaxSplitWords - 1).  nplanes: 3 (Karatsuba:
 // R, I, reduced R + I) or 2 (R, I) for complex operands, 1 (R) for real ones.
 hipError_t launch_split(const OperandView &v, int ek, const int16_t *mu, const NTable *tab,
                         int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
@@ -197,10 +198,9 @@ hipError_t launch_batch_ceil7(const BatchOperand *ops, int nops, int64_t blocks,
                               hipStream_t s);
 hipError_t launch_batch_accu_exponents(const BatchOperand *ops, int nops, int64_t blocks,
                                        uint32_t *status, hipStream_t s);
-// 11-bit chunks that hold |a'| < 2^abits.
-inline int split_fchunks(int abits) {
-    return abits <= kFChunkBits ? 1 : (abits + kFChunkBits - 1) / kFChunkBits;
-}
+// 32-bit words of the biased form a' + 2^(32 W - 1) of a signed a' with |a'| < 2^abits.
+inline int split_words(int abits) { return abits < 32 ? 1 : (abits + 32) / 32; }
+constexpr int kMaxSplitBits = 32 * kMaxSplitWords - 1;
 // abits: the largest bit length of |a'| among the operands (the chunk count of the launch).
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
                               int nplanes, int abits, hipStream_t s);

@@ -335,14 +335,18 @@ __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t 
 // with each other one load instruction reads 4 rows at 16 k (64-byte runs);
 // for rows with contiguous k each lane reads its own 64-byte run.
 //
-// Residues in FP32: |a'| is held as NF signed 11-bit chunks c_j (a' =
-// sum_j c_j 2^(11 j)), so x = sum_j c_j w_j with w_j the symmetric residue of
-// 2^(11 j) is an integer with |x| <= 9 * 2047 * 128 < 2^22, exact in FP32.
-// q = rint(x * fl(1/p)) is round(x / p): the computed quotient is within
-// |x / p| 2^-23 (1 + 2^-23) < 1 / (2p) of x / p, and for odd p no x / p lies
-// closer than 1 / (2p) to a half-integer; so s = x - q p (one exact fma) is the
-// symmetric residue.  For p = 256 an exact tie gives s = +128 instead of -128,
-// the same byte.
+// Residues through byte dot products: the signed a' is written as the W-word integer
+// u = a' + 2^(32 W - 1) (0 <= u < 2^(32 W), W the smallest word count with
+// |a'| < 2^(32 W - 1)), and per modulus x = sum_j u_j w_j - (2^(32 W - 1) mod p),
+// with u_j the bytes of u and w_j = 2^(8 j) mod p in [0, p - 1]: one unsigned
+// 4-byte dot product per word (the bias enters as the accumulator's start), an
+// integer congruent to a' modulo p with |x| <= 16 * 255 * 255 + 255 < 2^20.
+// Its symmetric residue comes in FP32: x is exact, q = rint(x * fl(1/p)) is
+// round(x / p) (the computed quotient is within |x / p| 2^-23 (1 + 2^-23) < 1 / (2p)
+// of x / p, and for odd p no x / p lies closer than 1 / (2p) to a half-integer), so
+// s = x - q p (one exact fma) is the symmetric residue.  For p = 256 an exact tie
+// gives s = +128 instead of -128, the same byte.  The reduced sum of the real and
+// imaginary residues (|x| <= 256) takes the same rule.
 constexpr int kEPT = 4;                   // k-consecutive elements per thread
 constexpr int kDirectRows = 4 * kEPT;     // 256 threads, 64 / kEPT threads per row
 
@@ -366,43 +370,39 @@ __device__ __forceinline__ void store_res(int8_t *p, const int (&r)[E]) {
     }
 }
 
-// a' = trunc(|x| 2^mu) as NF 11-bit chunks, signed like x, in FP32.
-template <int NF>
-__device__ __forceinline__ void trunc_fchunks(double x, int mu, float (&c)[NF]) {
-    uint64_t M;
-    int E;
-    decompose(x, M, E);
-    const int s = E + mu;
-    uint64_t lo = 0, hi = 0;
-    if (M != 0) {
-        if (s >= 64) {
-            hi = M << (s - 64);
-        } else if (s > 0) {
-            lo = M << s;
-            hi = M >> (64 - s);
-        } else if (s > -64) {
-            lo = M >> (-s);
-        }
-    }
-    constexpr uint64_t mask = (1ull << kFChunkBits) - 1;
-    const bool neg = x < 0.0;
+// u = a' + 2^(32 W - 1) for a' = trunc(|x| 2^mu) signed like x (|a'| < 2^(32 W - 1)),
+// as W little-endian 32-bit words, in FP64: a' is exact as a double (|x| 2^mu is a
+// power-of-two scaling of x, and anything below 1 truncates to 0), and the words come
+// off from the bottom, q_{i+1} = floor(q_i 2^-32), word_i = q_i - 2^32 q_{i+1} in
+// [0, 2^32) (exact: an integer below 2^32); the top q is signed, and adding the bias
+// 2^31 to it flips its sign bit.
+template <int W>
+__device__ __forceinline__ void biased_words(double x, int mu, uint32_t (&u)[W]) {
+    double q = __builtin_trunc(__builtin_ldexp(x, mu));
 #pragma unroll
-    for (int j = 0; j < NF; ++j) {
-        const int o = kFChunkBits * j;
-        uint64_t v;
-        if (o + kFChunkBits <= 64) v = lo >> o;
-        else if (o >= 64) v = hi >> (o - 64);
-        else v = (lo >> o) | (hi << (64 - o));
-        const float f = (float)(uint32_t)(v & mask);
-        c[j] = neg ? -f : f;
+    for (int i = 0; i < W - 1; ++i) {
+        const double hi = __builtin_floor(q * 0x1p-32);
+        u[i] = (uint32_t)__builtin_fma(hi, -0x1p32, q);
+        q = hi;
     }
+    u[W - 1] = (uint32_t)(int32_t)q ^ 0x80000000u;
+}
+
+// x = sum_j u_j w_j - (2^(32 W - 1) mod p) as a float (an exact integer, |x| < 2^20).
+template <int W>
+__device__ __forceinline__ float byte_dot(const uint32_t (&u)[W], const uint32_t (&wb)[W],
+                                          uint32_t bias) {
+    uint32_t acc = bias;
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc = __builtin_amdgcn_udot4(u[i], wb[i], acc, false);
+    return (float)(int32_t)acc;
 }
 
 __device__ __forceinline__ float smod_f(float x, float p, float ip) {
     return __builtin_fmaf(-__builtin_rintf(x * ip), p, x);
 }
 
-template <int EK, bool CONTIG_H, int NPLANES, int NF>
+template <int EK, bool CONTIG_H, int NPLANES, int W>
 __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *__restrict__ mu,
                                            const NTable *__restrict__ tab, int nmod,
                                            int8_t *__restrict__ dst, int64_t rows_pad,
@@ -427,39 +427,35 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
         return;
     }
     static_assert(NPLANES != 1 || elem_real(EK), "one residue plane for real operands only");
-    float cR[kEPT][NF], cI[kEPT][NF];
+    // elements past k (the ragged last slab) enter as zeros, whose residues are 0
+    uint32_t uR[kEPT][W], uI[kEPT][W];
 #pragma unroll
     for (int j = 0; j < kEPT; ++j) {
         double re = 0.0, im = 0.0;
         const int64_t h = h0 + j;
-        if (live && h < v.k) {
+        if (h < v.k) {
             load_elem<EK>(v.base, r * v.stride_r + h * v.stride_h, re, im);
             if (v.conj) im = -im;
         }
-        trunc_fchunks<NF>(re, live ? ex : 0, cR[j]);
-        if constexpr (NPLANES > 1) trunc_fchunks<NF>(im, live ? ex : 0, cI[j]);
+        biased_words<W>(re, ex, uR[j]);
+        if constexpr (NPLANES > 1) biased_words<W>(im, ex, uI[j]);
     }
 
     for (int l = 0; l < nmod; ++l) {
         const OZC_AS_CONST ModConst &mc = const_ptr(tab)->mod[l];
         const float p = mc.pf, ip = mc.ipf;
-        float w[NF];
+        uint32_t wb[W];
 #pragma unroll
-        for (int c = 0; c < NF; ++c) w[c] = mc.wf[c];
+        for (int i = 0; i < W; ++i) wb[i] = mc.wbyte[i];
+        const uint32_t bias = mc.wbias[W - 1];
         float fa[kEPT], fb[kEPT];
         int a[kEPT], b[kEPT];
 #pragma unroll
         for (int j = 0; j < kEPT; ++j) {
-            float xr = cR[j][0] * w[0];
-#pragma unroll
-            for (int c = 1; c < NF; ++c) xr = __builtin_fmaf(cR[j][c], w[c], xr);
-            fa[j] = smod_f(xr, p, ip);
+            fa[j] = smod_f(byte_dot<W>(uR[j], wb, bias), p, ip);
             a[j] = (int)fa[j];
             if constexpr (NPLANES > 1) {
-                float xi = cI[j][0] * w[0];
-#pragma unroll
-                for (int c = 1; c < NF; ++c) xi = __builtin_fmaf(cI[j][c], w[c], xi);
-                fb[j] = smod_f(xi, p, ip);
+                fb[j] = smod_f(byte_dot<W>(uI[j], wb, bias), p, ip);
                 b[j] = (int)fb[j];
             }
         }
@@ -503,13 +499,13 @@ __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *max
                                                              int16_t *mu, uint32_t *status) {
     fast_exponents_body(maxbits, sigma, rows, rows_pad, tab, mu, status, blockIdx.x);
 }
-template <int EK, bool CONTIG_H, int NPLANES, int NF>
+template <int EK, bool CONTIG_H, int NPLANES, int W>
 __global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *__restrict__ mu,
                                                     const NTable *__restrict__ tab, int nmod,
                                                     int8_t *__restrict__ dst, int64_t rows_pad,
                                                     int64_t k_pad) {
-    split_body<EK, CONTIG_H, NPLANES, NF>(v, mu, tab, nmod, dst, rows_pad, k_pad, blockIdx.x,
-                                              blockIdx.y);
+    split_body<EK, CONTIG_H, NPLANES, W>(v, mu, tab, nmod, dst, rows_pad, k_pad, blockIdx.x,
+                                             blockIdx.y);
 }
 
 template <int EK, bool CONTIG_H>
@@ -589,8 +585,8 @@ __global__ __launch_bounds__(256) void batch_ceil7_kernel(const BatchOperand *op
     else ceil7_body<EK, false>(op.v, op.maxbits, op.bar, op.rows_pad, op.k_pad, bx, by);
 }
 
-// Operands of one launch may have different moduli counts; NF covers the largest |a'|.
-template <int EK, int NPLANES, int NF>
+// Operands of one launch may have different moduli counts; W covers the largest |a'|.
+template <int EK, int NPLANES, int W>
 __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *ops, int nops) {
     const int64_t b = blockIdx.x;
     const int o = find_seg(nops, b, [&](int i) { return ops[i].blk_split; });
@@ -598,11 +594,11 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const BatchOperand *op
     const int64_t lb = b - op.blk_split, gx = op.k_pad / kTileH;
     const int64_t bx = lb % gx, by = lb / gx;
     if (op.v.contig_h)
-        split_body<EK, true, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
-                                              op.k_pad, bx, by);
+        split_body<EK, true, NPLANES, W>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
+                                             op.k_pad, bx, by);
     else
-        split_body<EK, false, NPLANES, NF>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
-                                               op.k_pad, bx, by);
+        split_body<EK, false, NPLANES, W>(op.v, op.mu, op.tab, op.nmod, op.res, op.rows_pad,
+                                              op.k_pad, bx, by);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -610,19 +606,18 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-#define OZC_NF_CASES(CASE) \
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
+#define OZC_W_CASES(CASE) CASE(1) CASE(2) CASE(3) CASE(4)
 
 template <int EK, int NPLANES>
-hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, int nf, hipStream_t s) {
+hipError_t batch_split_w(const BatchOperand *ops, int nops, int64_t blocks, int nw, hipStream_t s) {
     dim3 grid((unsigned)blocks);
-#define OZC_BSPLIT_CASE(NF)                                                                  \
-    case NF:                                                                                 \
-        hipLaunchKernelGGL((batch_split_kernel<EK, NPLANES, NF>), grid, dim3(256), 0, s, \
+#define OZC_BSPLIT_CASE(W)                                                                   \
+    case W:                                                                                  \
+        hipLaunchKernelGGL((batch_split_kernel<EK, NPLANES, W>), grid, dim3(256), 0, s,  \
                            ops, nops);                                                       \
         break;
-    switch (nf) {
-        OZC_NF_CASES(OZC_BSPLIT_CASE)
+    switch (nw) {
+        OZC_W_CASES(OZC_BSPLIT_CASE)
         default:
             return hipErrorInvalidValue;
     }
@@ -631,23 +626,23 @@ hipError_t batch_split_nf(const BatchOperand *ops, int nops, int64_t blocks, int
 }
 
 template <int EK, bool CONTIG_H, int NPLANES>
-hipError_t split_nf(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod, int nf,
+hipError_t split_w(const OperandView &v, const int16_t *mu, const NTable *tab, int nmod, int nw,
                     int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s) {
     dim3 grid((unsigned)(k_pad / kTileH), (unsigned)(rows_pad / kDirectRows));
-#define OZC_SPLIT_CASE(NF)                                                                   \
-    case NF:                                                                                 \
-        hipLaunchKernelGGL((split_kernel<EK, CONTIG_H, NPLANES, NF>), grid, dim3(256), 0, \
+#define OZC_SPLIT_CASE(W)                                                                    \
+    case W:                                                                                  \
+        hipLaunchKernelGGL((split_kernel<EK, CONTIG_H, NPLANES, W>), grid, dim3(256), 0,  \
                            s, v, mu, tab, nmod, dst, rows_pad, k_pad);                       \
         break;
-    switch (nf) {
-        OZC_NF_CASES(OZC_SPLIT_CASE)
+    switch (nw) {
+        OZC_W_CASES(OZC_SPLIT_CASE)
         default:
             return hipErrorInvalidValue;
     }
 #undef OZC_SPLIT_CASE
     return hipGetLastError();
 }
-#undef OZC_NF_CASES
+#undef OZC_W_CASES
 
 
 }  // namespace
@@ -748,24 +743,25 @@ hipError_t launch_accu_exponents(const uint64_t *maxbits, const int32_t *X, int6
 hipError_t launch_split(const OperandView &v, int ek, const int16_t *mu, const NTable *tab,
                         int nmod, int nplanes, int abits, int8_t *dst, int64_t rows_pad,
                         int64_t k_pad, hipStream_t s) {
-    const int nf = split_fchunks(abits);
-    if (rows_pad % kDirectRows || k_pad % kTileH || nf > kMaxFChunks) return hipErrorInvalidValue;
+    if (abits > kMaxSplitBits) return hipErrorInvalidValue;
+    const int nw = split_words(abits);
+    if (rows_pad % kDirectRows || k_pad % kTileH) return hipErrorInvalidValue;
     if ((nplanes == 1) != elem_real(ek)) return hipErrorInvalidValue;
-#define OZC_SPLIT_ARGS v, mu, tab, nmod, nf, dst, rows_pad, k_pad, s
+#define OZC_SPLIT_ARGS v, mu, tab, nmod, nw, dst, rows_pad, k_pad, s
 #define OZC_SPLIT_EK(EKV)                                                                  \
-    if (v.contig_h) return nplanes == 3 ? split_nf<EKV, true, 3>(OZC_SPLIT_ARGS)            \
-                                        : split_nf<EKV, true, 2>(OZC_SPLIT_ARGS);           \
-    return nplanes == 3 ? split_nf<EKV, false, 3>(OZC_SPLIT_ARGS)                           \
-                        : split_nf<EKV, false, 2>(OZC_SPLIT_ARGS);
+    if (v.contig_h) return nplanes == 3 ? split_w<EKV, true, 3>(OZC_SPLIT_ARGS)            \
+                                        : split_w<EKV, true, 2>(OZC_SPLIT_ARGS);           \
+    return nplanes == 3 ? split_w<EKV, false, 3>(OZC_SPLIT_ARGS)                           \
+                        : split_w<EKV, false, 2>(OZC_SPLIT_ARGS);
     switch (ek) {
         case kElemZ: OZC_SPLIT_EK(kElemZ)
         case kElemC: OZC_SPLIT_EK(kElemC)
         case kElemD:
-            return v.contig_h ? split_nf<kElemD, true, 1>(OZC_SPLIT_ARGS)
-                              : split_nf<kElemD, false, 1>(OZC_SPLIT_ARGS);
+            return v.contig_h ? split_w<kElemD, true, 1>(OZC_SPLIT_ARGS)
+                              : split_w<kElemD, false, 1>(OZC_SPLIT_ARGS);
         case kElemS:
-            return v.contig_h ? split_nf<kElemS, true, 1>(OZC_SPLIT_ARGS)
-                              : split_nf<kElemS, false, 1>(OZC_SPLIT_ARGS);
+            return v.contig_h ? split_w<kElemS, true, 1>(OZC_SPLIT_ARGS)
+                              : split_w<kElemS, false, 1>(OZC_SPLIT_ARGS);
         default: return hipErrorInvalidValue;
     }
 #undef OZC_SPLIT_EK
@@ -851,13 +847,13 @@ hipError_t launch_batch_ceil7(const BatchOperand *ops, int nops, int64_t blocks,
 hipError_t launch_batch_split(const BatchOperand *ops, int nops, int64_t blocks, bool single,
                               int nplanes, int abits, hipStream_t s) {
     if (blocks <= 0 || nops <= 0) return hipSuccess;
-    const int nf = split_fchunks(abits);
-    if (nf > kMaxFChunks) return hipErrorInvalidValue;
+    if (abits > kMaxSplitBits) return hipErrorInvalidValue;
+    const int nw = split_words(abits);
     if (single)
-        return nplanes == 3 ? batch_split_nf<true, 3>(ops, nops, blocks, nf, s)
-                            : batch_split_nf<true, 2>(ops, nops, blocks, nf, s);
-    return nplanes == 3 ? batch_split_nf<false, 3>(ops, nops, blocks, nf, s)
-                        : batch_split_nf<false, 2>(ops, nops, blocks, nf, s);
+        return nplanes == 3 ? batch_split_w<true, 3>(ops, nops, blocks, nw, s)
+                            : batch_split_w<true, 2>(ops, nops, blocks, nw, s);
+    return nplanes == 3 ? batch_split_w<false, 3>(ops, nops, blocks, nw, s)
+                        : batch_split_w<false, 2>(ops, nops, blocks, nw, s);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {

@@ -169,11 +169,17 @@ void build_tables(NTable *tables) {
             mc.half = (p + 1) / 2;
             mc.pf = (float)p;
             mc.ipf = 1.0f / (float)p;  // correctly rounded single division
-            uint64_t pw = 1;
-            for (int j = 0; j < kMaxFChunks; ++j) {
-                const uint32_t r = (uint32_t)(pw % p);
-                mc.wf[j] = (float)(r >= mc.half ? (int)r - (int)p : (int)r);
-                pw = (pw % p) * ((1ull << kFChunkBits) % p);
+            // residue split: weights of the bytes of a word vector (2^(8 j) mod p, in
+            // [0, p - 1]) and the offsets that remove the bias 2^(32 W - 1)
+            uint32_t pw = 1;  // 2^(8 j) mod p
+            for (int j = 0; j < 4 * kMaxSplitWords; ++j) {
+                mc.wbyte[j / 4] |= pw << (8 * (j % 4));
+                pw = (pw * 256u) % p;
+            }
+            for (int w = 1; w <= kMaxSplitWords; ++w) {
+                uint32_t b = 1;  // 2^(32 w - 1) mod p
+                for (int e = 0; e < 32 * w - 1; ++e) b = (b * 2u) % p;
+                mc.wbias[w - 1] = 0u - b;
             }
             // Step II: q_l = (P/p_l)^-1 mod p_l, s_l = (P/p_l) q_l
             const Big Ml = P.div(p);
