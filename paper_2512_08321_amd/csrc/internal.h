@@ -41,7 +41,8 @@ struct ModConst {
     float pf;                    // p
     float ipf;                   // 1 / p rounded to float
     uint32_t wbyte[kMaxSplitWords];  // byte 4 i + b of the words: 2^(8 (4 i + b)) mod p
-    uint32_t wbias[kMaxSplitWords];  // entry W - 1: -(2^(32 W - 1) mod p) (two's complement)
+    uint32_t wbias[kMaxSplitWords];  // entry W - 1: 128 - (2^(32 W - 1) mod p) (two's complement)
+    float rbias;                     // 0.5 - 128 ipf (exact)
 };
 
 // Constants of one moduli count N.

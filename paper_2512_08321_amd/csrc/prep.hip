@@ -337,22 +337,29 @@ __device__ __forceinline__ void ceil7_body(const OperandView &v, const uint64_t 
 //
 // Residues through byte dot products: the signed a' is written as the W-word integer
 // u = a' + 2^(32 W - 1) (0 <= u < 2^(32 W), W the smallest word count with
-// |a'| < 2^(32 W - 1)), and per modulus x = sum_j u_j w_j - (2^(32 W - 1) mod p),
-// with u_j the bytes of u and w_j = 2^(8 j) mod p in [0, p - 1]: one unsigned
-// 4-byte dot product per word (the bias enters as the accumulator's start), an
-// integer congruent to a' modulo p with |x| <= 16 * 255 * 255 + 255 < 2^20.
-// Its symmetric residue comes in FP32: x is exact, q = rint(x * fl(1/p)) is
-// round(x / p) (the computed quotient is within |x / p| 2^-23 (1 + 2^-23) < 1 / (2p)
-// of x / p, and for odd p no x / p lies closer than 1 / (2p) to a half-integer), so
-// s = x - q p (one exact fma) is the symmetric residue.  For p = 256 an exact tie
-// gives s = +128 instead of -128, the same byte.  The reduced sum of the real and
-// imaginary residues (|x| <= 256) takes the same rule.
+// |a'| < 2^(32 W - 1)), and per modulus x' = sum_j u_j w_j + 128 - (2^(32 W - 1) mod p),
+// with u_j the bytes of u and w_j = 2^(8 j) mod p in [0, p - 1]: one unsigned 4-byte
+// dot product per word (the offsets enter as the accumulator's start), so that
+// x = x' - 128 is congruent to a' modulo p and |x| <= 16 * 255 * 255 + 255 < 2^20.
+// Its symmetric residue s comes in FP32 as the byte s + 128 = x' - p q with
+// q = floor(fl(x' fl(1/p) + (0.5 - 128 fl(1/p)))) = floor(fl(x fl(1/p) + 0.5)), one fma
+// (the offset is exact): the computed value is within |x / p| 2^-24 + ulp / 2 < 1 / (2p)
+// of x / p + 1/2, which for odd p lies at least 1 / (2p) from every integer, so q is
+// x / p rounded to the nearest integer; for p = 256 everything is exact and a tie
+// rounds up, giving s = -128.  So s + 128 is an exact integer in [0, 255]: one
+// conversion-and-insert per byte, and flipping bit 7 of each byte gives the signed
+// residue.  The reduced sum of the real and imaginary residues takes the same rule.
 constexpr int kEPT = 4;                   // k-consecutive elements per thread
 constexpr int kDirectRows = 4 * kEPT;     // 256 threads, 64 / kEPT threads per row
 
 __device__ __forceinline__ uint32_t pack_bytes(int a, int b, int c, int d) {
     return (uint32_t)(a & 0xff) | ((uint32_t)(b & 0xff) << 8) | ((uint32_t)(c & 0xff) << 16) |
            ((uint32_t)(d & 0xff) << 24);
+}
+
+// Four residues (one byte each, k ascending) as one store.
+__device__ __forceinline__ void store_word(int8_t *p, uint32_t w) {
+    *global_ptr(reinterpret_cast<uint32_t *>(p)) = w;
 }
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -388,7 +395,7 @@ __device__ __forceinline__ void biased_words(double x, int mu, uint32_t (&u)[W])
     u[W - 1] = (uint32_t)(int32_t)q ^ 0x80000000u;
 }
 
-// x = sum_j u_j w_j - (2^(32 W - 1) mod p) as a float (an exact integer, |x| < 2^20).
+// x' = sum_j u_j w_j + 128 - (2^(32 W - 1) mod p) as a float (an exact integer).
 template <int W>
 __device__ __forceinline__ float byte_dot(const uint32_t (&u)[W], const uint32_t (&wb)[W],
                                           uint32_t bias) {
@@ -396,6 +403,11 @@ __device__ __forceinline__ float byte_dot(const uint32_t (&u)[W], const uint32_t
 #pragma unroll
     for (int i = 0; i < W; ++i) acc = __builtin_amdgcn_udot4(u[i], wb[i], acc, false);
     return (float)(int32_t)acc;
+}
+
+// s + 128 for the symmetric residue s of x = x' - 128 (x' an exact integer, |x| < 2^20).
+__device__ __forceinline__ float smod_u8(float xs, float p, float ip, float rbias) {
+    return __builtin_fmaf(-__builtin_floorf(__builtin_fmaf(xs, ip, rbias)), p, xs);
 }
 
 __device__ __forceinline__ float smod_f(float x, float p, float ip) {
@@ -427,6 +439,7 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
         return;
     }
     static_assert(NPLANES != 1 || elem_real(EK), "one residue plane for real operands only");
+    static_assert(kEPT == 4, "one 4-byte word of residues per plane and modulus");
     // elements past k (the ragged last slab) enter as zeros, whose residues are 0
     uint32_t uR[kEPT][W], uI[kEPT][W];
 #pragma unroll
@@ -443,31 +456,29 @@ __device__ __forceinline__ void split_body(const OperandView &v, const int16_t *
 
     for (int l = 0; l < nmod; ++l) {
         const OZC_AS_CONST ModConst &mc = const_ptr(tab)->mod[l];
-        const float p = mc.pf, ip = mc.ipf;
+        const float p = mc.pf, ip = mc.ipf, rb = mc.rbias;
         uint32_t wb[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) wb[i] = mc.wbyte[i];
         const uint32_t bias = mc.wbias[W - 1];
-        float fa[kEPT], fb[kEPT];
-        int a[kEPT], b[kEPT];
+        uint32_t wa = 0, wbi = 0, wc = 0;  // residues + 128 as bytes, k ascending
 #pragma unroll
         for (int j = 0; j < kEPT; ++j) {
-            fa[j] = smod_f(byte_dot<W>(uR[j], wb, bias), p, ip);
-            a[j] = (int)fa[j];
+            const float sa = smod_u8(byte_dot<W>(uR[j], wb, bias), p, ip, rb);
+            wa = __builtin_amdgcn_cvt_pk_u8_f32(sa, j, wa);
             if constexpr (NPLANES > 1) {
-                fb[j] = smod_f(byte_dot<W>(uI[j], wb, bias), p, ip);
-                b[j] = (int)fb[j];
+                const float sb = smod_u8(byte_dot<W>(uI[j], wb, bias), p, ip, rb);
+                wbi = __builtin_amdgcn_cvt_pk_u8_f32(sb, j, wbi);
+                if constexpr (NPLANES == 3) {  // (s_a + s_b) + 128 = (sa - 128) + sb
+                    const float sc = smod_u8((sa - 128.0f) + sb, p, ip, rb);
+                    wc = __builtin_amdgcn_cvt_pk_u8_f32(sc, j, wc);
+                }
             }
         }
         int8_t *o = out + (int64_t)l * NPLANES * plane_pitch;
-        store_res(o, a);
-        if constexpr (NPLANES > 1) store_res(o + plane_pitch, b);
-        if constexpr (NPLANES == 3) {
-            int c[kEPT];
-#pragma unroll
-            for (int j = 0; j < kEPT; ++j) c[j] = (int)smod_f(fa[j] + fb[j], p, ip);
-            store_res(o + 2 * plane_pitch, c);
-        }
+        store_word(o, wa ^ 0x80808080u);
+        if constexpr (NPLANES > 1) store_word(o + plane_pitch, wbi ^ 0x80808080u);
+        if constexpr (NPLANES == 3) store_word(o + 2 * plane_pitch, wc ^ 0x80808080u);
     }
 }
 

@@ -170,7 +170,8 @@ void build_tables(NTable *tables) {
             mc.pf = (float)p;
             mc.ipf = 1.0f / (float)p;  // correctly rounded single division
             // residue split: weights of the bytes of a word vector (2^(8 j) mod p, in
-            // [0, p - 1]) and the offsets that remove the bias 2^(32 W - 1)
+            // [0, p - 1]) and the offsets that remove the bias 2^(32 W - 1) and add the
+            // 128 that makes every residue a byte in [0, 255]
             uint32_t pw = 1;  // 2^(8 j) mod p
             for (int j = 0; j < 4 * kMaxSplitWords; ++j) {
                 mc.wbyte[j / 4] |= pw << (8 * (j % 4));
@@ -179,8 +180,9 @@ void build_tables(NTable *tables) {
             for (int w = 1; w <= kMaxSplitWords; ++w) {
                 uint32_t b = 1;  // 2^(32 w - 1) mod p
                 for (int e = 0; e < 32 * w - 1; ++e) b = (b * 2u) % p;
-                mc.wbias[w - 1] = 0u - b;
+                mc.wbias[w - 1] = 128u - b;
             }
+            mc.rbias = 0.5f - 128.0f * mc.ipf;  // exact: both terms are multiples of 2^-32 below 2
             // Step II: q_l = (P/p_l)^-1 mod p_l, s_l = (P/p_l) q_l
             const Big Ml = P.div(p);
             const uint32_t q = inverse_mod(Ml.mod(p), p);

@@ -1,15 +1,17 @@
 """The residue split's arithmetic, checked on the host.
 
 The split writes the truncated integer a' (signed like its input, |a'| < 2^(32 W - 1))
-as the W-word integer u = a' + 2^(32 W - 1), takes x = sum_j u_j w_j - (2^(32 W - 1)
+as the W-word integer u = a' + 2^(32 W - 1), takes x' = sum_j u_j w_j + 128 - (2^(32 W - 1)
 mod p) over the bytes u_j of u with w_j = 2^(8 j) mod p (unsigned 4-byte dot products,
-the bias as the accumulator's start), and reduces x to its symmetric residue in FP32 as
-s = x - p rint(x fl(1/p)).
+the offsets as the accumulator's start), so that x = x' - 128 is congruent to a', and
+forms the byte s + 128 of the symmetric residue s of x in FP32 as
+x' - p floor(fl(x' fl(1/p) + (0.5 - 128 fl(1/p)))) (one fma inside the floor).
 
-1. The FP32 rule is evaluated in IEEE single precision for every integer with
-   |x| <= 16 * 255 * 255 + 255 (the largest byte sum) and every modulus of the largest
-   moduli set, against the exact symmetric residue in [-(p-1)/2, p/2) (byte-wise for
-   p = 256, where a tie gives +128 for -128, the same byte).
+1. That rule is evaluated for every integer with |x| <= 16 * 255 * 255 + 255 (the largest
+   byte sum) and every modulus of the largest moduli set: the fma is replayed exactly
+   (the product and sum are exact in double, then rounded once to single), and the
+   result must be an integer in [0, 255] equal to s + 128 for the exact symmetric
+   residue s in [-(p-1)/2, (p-1)/2] (for p = 256: in [-128, 127]).
 2. The words come from FP64 steps (a' = trunc(x 2^mu), then q_{i+1} = floor(q_i 2^-32)
    and word_i = q_i - 2^32 q_{i+1} from the bottom, the top word's sign bit flipped);
    they are replayed here in IEEE double for values at the edges of every word count
@@ -28,20 +30,29 @@ MODULI = [int(p) for p in core.constants(24)["p"]]
 
 
 @pytest.mark.parametrize("p", MODULI)
-def test_fp32_rule_matches_exact_residue(p):
+def test_fp32_byte_rule_matches_exact_residue(p):
     x = np.arange(-X_MAX, X_MAX + 1, dtype=np.int64)
-    xf = x.astype(np.float32)
-    assert np.array_equal(xf.astype(np.int64), x)  # exact in FP32
+    xs = (x + 128).astype(np.float32)
+    assert np.array_equal(xs.astype(np.int64), x + 128)  # exact in FP32
     ip = np.float32(1) / np.float32(p)
-    q = np.rint(xf * ip)  # float32 product, round half to even
-    s = (xf - q * np.float32(p)).astype(np.int64)  # q p and the difference are exact
+    rb = np.float32(0.5) - np.float32(128) * ip
+    assert float(rb) == 0.5 - 128 * float(ip)  # the offset is exact
+    y = np.float32(xs.astype(np.float64) * float(ip) + float(rb))  # fma: one rounding
+    q = np.floor(y).astype(np.float64)
+    s = xs.astype(np.float64) - q * p  # q p and the difference are exact
+    assert np.all(s == np.round(s)) and s.min() >= 0 and s.max() <= 255
     r = np.mod(x, p)
-    half = (p + 1) // 2
+    half = (p + 1) // 2 if p % 2 else p // 2
     want = np.where(r >= half, r - p, r)
-    if p == 256:
-        assert np.array_equal(s & 0xFF, want & 0xFF)
-    else:
-        assert np.array_equal(s, want)
+    assert np.array_equal(s.astype(np.int64) - 128, want)
+
+
+def test_fp32_byte_rule_catches_plain_rounding():
+    """Rounding half to even instead of the floor rule gives +128 at p = 256 ties,
+    which is no byte of [0, 255] once shifted."""
+    x = np.array([128, 384, -128], dtype=np.float64)
+    q = np.rint(x / 256.0)
+    assert (x - 256 * q + 128).max() == 256
 
 
 def _words_fp64(x, mu, W):
@@ -91,9 +102,9 @@ def test_biased_words_and_byte_sums(W):
             assert words == [(u >> (32 * i)) & 0xFFFFFFFF for i in range(W)], (v, mu, W)
             by = [(words[j // 4] >> (8 * (j % 4))) & 0xFF for j in range(4 * W)]
             for p in MODULI:
-                s = sum(b * w for b, w in zip(by, weights[p])) - offset[p]
-                assert abs(s) <= X_MAX
-                assert (s - a) % p == 0
+                s = sum(b * w for b, w in zip(by, weights[p])) + 128 - offset[p]
+                assert abs(s - 128) <= X_MAX
+                assert (s - 128 - a) % p == 0
 
 
 def test_planted_mistakes_fail():
