@@ -186,6 +186,40 @@ def test_edge_cases(handle, orc):
     torch.cuda.synchronize()
 
 
+def _extreme_operands():
+    """Rows and columns scaled across the whole double range (subnormal rows, rows near
+    2^900), a spread of 2^-80..1 inside every row, signed zeros and lone subnormals in
+    normal rows; every product stays finite."""
+    m, k, n = 70, 80, 66
+    A = workloads.complex_matrix(m, k, 2.0, 901)
+    B = workloads.complex_matrix(k, n, 2.0, 902)
+    rng = np.random.default_rng(903)
+    inner_a = rng.integers(-80, 1, size=(m, k))
+    inner_b = rng.integers(-80, 1, size=(k, n))
+    A = np.ldexp(A.real, inner_a) + 1j * np.ldexp(A.imag, inner_a)
+    B = np.ldexp(B.real, inner_b) + 1j * np.ldexp(B.imag, inner_b)
+    row_exp = np.array([-1060, -1030, -520, 0, 480, 900] * 12)[:m]
+    col_exp = np.array([-900, -400, 0, 60, -1000, 30] * 11)[:n]
+    A = workloads.skewed(np.asfortranarray(A), row_exp=row_exp)
+    B = workloads.skewed(np.asfortranarray(B), col_exp=col_exp)
+    A[3, :5] = -0.0
+    A[4, 7] = complex(-0.0, 0.0)
+    A[5, 9] = complex(5e-324, -5e-324)
+    B[11, 3] = complex(0.0, -0.0)
+    B[12, 4] = complex(-2.5e-320, 1e-310)
+    return np.asfortranarray(A), np.asfortranarray(B)
+
+
+@pytest.mark.parametrize("N,mode", [(6, "fast"), (14, "fast"), (14, "accurate"), (20, "fast"),
+                                    (24, "accurate")])
+def test_extreme_magnitudes_bit_exact(handle, orc, N, mode):
+    """Every word count of the residue split (1 to 4) on inputs across the double range."""
+    A, B = _extreme_operands()
+    assert np.isfinite(A).all() and np.isfinite(B).all()
+    g, ref = _run_inspect(handle, orc, A, B, N, mode, "karatsuba")
+    _check_inspect(g, ref, "karatsuba")
+
+
 @pytest.mark.parametrize("algo", ["karatsuba", "4m"])
 def test_row_padding_left_from_an_earlier_call(handle, orc, algo):
     """The split leaves the padding rows of the residue planes as an earlier call left
