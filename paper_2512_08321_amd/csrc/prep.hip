@@ -15,7 +15,6 @@ namespace {
 constexpr uint64_t kAbsMask = 0x7fffffffffffffffull;
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
 
-// One element of kind EK (ElemKind) at index idx; real elements have im = 0.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 
@@ -408,10 +407,6 @@ __device__ __forceinline__ float byte_dot(const uint32_t (&u)[W], const uint32_t
 // s + 128 for the symmetric residue s of x = x' - 128 (x' an exact integer, |x| < 2^20).
 __device__ __forceinline__ float smod_u8(float xs, float p, float ip, float rbias) {
     return __builtin_fmaf(-__builtin_floorf(__builtin_fmaf(xs, ip, rbias)), p, xs);
-}
-
-__device__ __forceinline__ float smod_f(float x, float p, float ip) {
-    return __builtin_fmaf(-__builtin_rintf(x * ip), p, x);
 }
 
 template <int EK, bool CONTIG_H, int NPLANES, int W>
