@@ -220,6 +220,39 @@ def test_extreme_magnitudes_bit_exact(handle, orc, N, mode):
     _check_inspect(g, ref, "karatsuba")
 
 
+def _random_case(i):
+    rng = np.random.default_rng(7000 + i)
+    dims = []
+    for _ in range(3):
+        if rng.random() < 0.25:  # near a tile or slab edge
+            d = int(rng.choice([64, 128, 256])) + int(rng.integers(-1, 2))
+        else:
+            d = int(round(np.exp(rng.uniform(0.0, np.log(400)))))
+        dims.append(max(1, d))
+    m, n, k = dims
+    single = bool(rng.random() < 0.3)
+    N = int(rng.integers(2, 17 if single else 25))
+    mode = str(rng.choice(["fast", "accurate"]))
+    algo = str(rng.choice(["karatsuba", "4m"]))
+    ta, tb = (str(rng.choice(["N", "T", "C"])) for _ in range(2))
+    phi = float(rng.uniform(0.0, 6.0))
+    pads = tuple(int(x) for x in rng.integers(0, 4, size=2))
+    return m, n, k, single, N, mode, algo, ta, tb, phi, pads
+
+
+@pytest.mark.parametrize("i", range(40))
+def test_randomized_configurations(handle, orc, i):
+    """Seeded random shapes (1..400, tile edges +-1), moduli counts, modes, product forms,
+    op() forms, value spreads, precisions and leading-dimension padding."""
+    m, n, k, single, N, mode, algo, ta, tb, phi, (pa, pb) = _random_case(i)
+    dt = np.complex64 if single else np.complex128
+    A = workloads.complex_matrix(m, k, phi, 8000 + 2 * i, dtype=dt)
+    B = workloads.complex_matrix(k, n, phi, 8001 + 2 * i, dtype=dt)
+    g, ref = _run_inspect(handle, orc, A, B, N, mode, algo, ta, tb, single=single, lda_pad=pa,
+                          ldb_pad=pb)
+    _check_inspect(g, ref, algo)
+
+
 @pytest.mark.parametrize("algo", ["karatsuba", "4m"])
 def test_row_padding_left_from_an_earlier_call(handle, orc, algo):
     """The split leaves the padding rows of the residue planes as an earlier call left
