@@ -81,6 +81,24 @@ def model_line(m, n, k, N, args, copy_bw, achieved_tops, measured_ms):
                     "((14N + c) mn bytes); the product kernel here reduces in registers"}
 
 
+def phase_rates(m, n, k, N, single, algo, mode, prof):
+    """Algorithmic HBM bytes of the memory-side phases over their measured times (TB/s):
+    the scans read both operands twice (fast mode; in accurate mode the scaling phase also
+    holds the bound product and is left out), the split reads each operand once and writes
+    its residue planes, the reconstruction reads the E' planes and writes C (beta = 0)."""
+    eb = 8 if single else 16
+    planes = 3 if algo == "karatsuba" else 2
+    calls = max(1, prof["calls"])
+    out = {}
+    byts = {"split": (m + n) * k * (eb + planes * N), "crt": m * n * (2 * N + eb)}
+    if mode == "fast":
+        byts["scale"] = 2 * (m + n) * k * eb
+    for key, b in byts.items():
+        t = prof[f"{key}_ms"] / calls
+        out[key] = round(b / (t * 1e-3) / 1e12, 3) if t > 0 else None
+    return out
+
+
 def gemm_source_hash() -> str:
     with open(GEMM_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -329,6 +347,7 @@ def main():
         "parity_sample": parity,
         "phase_ms": {key: round(prof[key] / max(1, prof["calls"]), 4)
                      for key in ("scale_ms", "split_ms", "gemm_ms", "crt_ms", "total_ms")},
+        "phase_hbm_TBps": phase_rates(m, n, k, N, args.single, args.algo, args.mode, prof),
         "roofline": {"bound": "mfma", "kernel": "residue_gemm_kernel",
                      "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / INT8_PEAK_TOPS, 4),

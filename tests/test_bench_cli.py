@@ -86,3 +86,19 @@ def test_performance_model_orders_the_variants():
     share = [bench.paper_model_seconds(s, s, kk, N, b=3e12, p=1.5e15) / (6.0 * N * s * s * kk / 1.5e15)
              for kk in (1024, 16384, 262144)]
     assert share[0] > share[1] > share[2] > 1.0
+
+
+def test_phase_rates_count_the_algorithmic_bytes():
+    """Split: 16 B read and 3N B written per complex element of both operands; reconstruction:
+    2N B of E' read and 16 B written per output; scans: both operands read twice."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    prof = {"calls": 2, "scale_ms": 2.0, "split_ms": 4.0, "crt_ms": 6.0}
+    r = bench.phase_rates(1000, 2000, 3000, 14, False, "karatsuba", "fast", prof)
+    assert r["split"] == round((3000 * 3000 * (16 + 42)) / 2e-3 / 1e12, 3)
+    assert r["crt"] == round(1000 * 2000 * (28 + 16) / 3e-3 / 1e12, 3)
+    assert r["scale"] == round(2 * 3000 * 3000 * 16 / 1e-3 / 1e12, 3)
+    single = bench.phase_rates(1000, 2000, 3000, 6, True, "4m", "accurate", prof)
+    assert "scale" not in single
+    assert single["split"] == round((3000 * 3000 * (8 + 12)) / 2e-3 / 1e12, 3)
