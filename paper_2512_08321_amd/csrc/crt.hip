@@ -261,11 +261,15 @@ __device__ __forceinline__ void crt_output_body(const CrtArgs &a, int64_t bx) {
 
     const int nuj = global_ptr(a.nu)[j];
     const bool beta_zero = a.beta_r == 0.0 && a.beta_i == 0.0;
+    // the row exponents before any store of C, so that no load waits behind one
+    int mus[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mus[u] = ib + u < a.m ? global_ptr(a.mu)[ib + u] : 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int64_t i = ib + u;
         if (i >= a.m) continue;
-        const int mui = global_ptr(a.mu)[i];
+        const int mui = mus[u];
         double cr, ci;
         double lr = 0.0, li = 0.0;  // double-double outputs: the low parts
         if (mui == kExpNonfinite || nuj == kExpNonfinite) {
@@ -322,7 +326,11 @@ __global__ __launch_bounds__(256) void batch_crt_kernel(const BatchCrt *probs, i
         if (probs[mid].blk0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    crt_output_body<C, SINGLE>(probs[lo].a, b - probs[lo].blk0);
+    // The problem's arguments are copied out of the list first: read through a reference
+    // into global memory, every field would be loaded again after each store of C (the
+    // compiler cannot rule out that the stores overwrite the list).
+    const CrtArgs a = probs[lo].a;
+    crt_output_body<C, SINGLE>(a, b - probs[lo].blk0);
 }
 
 template <int C>
