@@ -182,7 +182,9 @@ void build_tables(NTable *tables) {
                 for (int e = 0; e < 32 * w - 1; ++e) b = (b * 2u) % p;
                 mc.wbias[w - 1] = 128u - b;
             }
-            mc.rbias = 0.5f - 128.0f * mc.ipf;  // exact: both terms are multiples of 2^-32 below 2
+            // exact: 128 ipf and 0.5 are multiples of 2^-24 (ipf has 24 bits at exponent -8)
+            // and their difference is below 1 in magnitude, so it fits in 24 bits
+            mc.rbias = 0.5f - 128.0f * mc.ipf;
             // Step II: q_l = (P/p_l)^-1 mod p_l, s_l = (P/p_l) q_l
             const Big Ml = P.div(p);
             const uint32_t q = inverse_mod(Ml.mod(p), p);
