@@ -376,10 +376,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
         if constexpr (!bound) {
             ER = a.eprime + (int64_t)l * P::eplanes * planeC;
             EI = ER + planeC;  // not used by real products
-            // A parked carry is read back before any store of this epilogue: all its words
-            // in one burst of loads, instead of one load after each store (an HBM round trip
-            // per word, since the compiler cannot move a load above a possibly aliasing store).
-            if (!C::REG_CARRY && sgi >= 1 && (karatsuba || sgi != 2)) {
+            if (C::PREFETCH && !C::REG_CARRY && sgi >= 1 && (karatsuba || sgi != 2)) {
                 static_for<BM>([&](auto bi) {
                     static_for<BN>([&](auto bj) {
                         static_for<4>([&](auto g) { cw[bi][bj][g] = *eword(EI, bi, bj, g); });
@@ -455,7 +452,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             else *ei = pack4(o);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
-                            const uint32_t w = cw[bi][bj][g];
+                            const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
                             static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) - acc_u(u), pd, ipd); });
                             *er = pack4(o);
                             if constexpr (karatsuba) {
@@ -465,7 +462,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             }
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
-                            const uint32_t w = cw[bi][bj][g];
+                            const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
                             static_for<4>([&](auto u) {
                                 o[u] = reduce_fp(karatsuba ? acc_u(u) - byte_of(w, u) : byte_of(w, u) + acc_u(u), pd, ipd);
                             });
