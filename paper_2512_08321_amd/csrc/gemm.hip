@@ -436,6 +436,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
             });
         } else {
             static_for<BM>([&](auto bi) {
+                // A parked carry is read back one row of blocks at a time (BN * 4 words in one
+                // burst of loads) before that row's stores: a load after a store is not moved
+                // above it (they might alias), so word-by-word read-back waited for a memory
+                // round trip per word.  Reading all BM rows before any store was no faster
+                // overall (fewer E' write-backs, but more operand misses in L2).
+                if (!C::PREFETCH && !C::REG_CARRY && sgi >= 1 && (karatsuba || sgi != 2)) {
+                    static_for<BN>([&](auto bj) {
+                        static_for<4>([&](auto g) { cw[bi][bj][g] = *eword(EI, bi, bj, g); });
+                    });
+                }
                 static_for<BN>([&](auto bj) {
                     static_for<4>([&](auto g) {
                         uint32_t *er = eword(ER, bi, bj, g);
@@ -452,7 +462,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             else *ei = pack4(o);
                         } else if (sgi == 1) {
                             // Karatsuba: E'_R = mod(D - E), carry mod(D + E); expanded: E'_R = mod(RR - II)
-                            const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
+                            const uint32_t w = cw[bi][bj][g];
                             static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) - acc_u(u), pd, ipd); });
                             *er = pack4(o);
                             if constexpr (karatsuba) {
@@ -462,7 +472,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             }
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
-                            const uint32_t w = C::PREFETCH || C::REG_CARRY ? cw[bi][bj][g] : *ei;
+                            const uint32_t w = cw[bi][bj][g];
                             static_for<4>([&](auto u) {
                                 o[u] = reduce_fp(karatsuba ? acc_u(u) - byte_of(w, u) : byte_of(w, u) + acc_u(u), pd, ipd);
                             });
