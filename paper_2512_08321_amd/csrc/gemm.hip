@@ -69,8 +69,9 @@ struct Plan {
 // the rounded product is off by less than 2^-22, and x / p lies at least 1/(2p) from a
 // half-integer unless p = 256, where 1/p is exact), and x - q p is exact.  For p = 256
 // a tie gives +128 instead of -128: the same byte.  The argument stays in INT32: an
-// accumulator is bounded by k 127^2 (odd p; k <= 2^17) and a residue adds at most 127,
-// below 2^31 - p; for p = 256 the wrap-around modulo 2^32 leaves the residue unchanged.
+// accumulator is bounded by k 127^2 (odd p; k <= 2^17) and the residues added to it
+// (at most three times 127) keep it below 2^31 - p; for p = 256 the wrap-around modulo
+// 2^32 leaves the residue unchanged.
 // Five FP64 instructions, against two quarter-rate integer multiplies and fix-ups for
 // a Barrett reduction (2.5% faster batches, 1.5% at 4096^3).
 __device__ __forceinline__ int reduce_fp(int x, double pd, double ipd) {
@@ -256,6 +257,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
 
     v16i acc[BM][BN];
     uint32_t cw[BM][BN][4];  // packed carry residues (kept here, or reloaded from E'_I)
+    uint32_t cr[BM][BN][4];  // Karatsuba, carry in registers, small tiles: E'_R, kept for E'_I
     if constexpr (C::PREFETCH) issue_first(0);
 
 #pragma unroll 1
@@ -364,9 +366,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
         // Karatsuba, mod(RR) and mod(RI) for the expanded form) stays in registers, or
         // is parked in this thread's own E'_I words, which receive the final E'_I last
         // (each lane re-reads only what it wrote, so no synchronisation is needed).
+        // With the carry in registers and small tiles, Karatsuba keeps mod(D) and E'_R
+        // instead of mod(D + E): three reductions per output rather than four.
         // Parked carries are loaded and awaited first; then the next product's first
         // stages are queued, so that their copies overlap the rest of this epilogue.
         constexpr bool karatsuba = KIND == KIND_KARATSUBA;
+        // the E'_R registers fit beside small tiles' accumulators only
+        constexpr bool keep_er = karatsuba && C::REG_CARRY && C::BM * C::BN <= 4;
         auto eword = [&](int8_t *E, int bi, int bj, int g) {
             const int64_t i = i0 + wm * WTM + bi * 32 + 8 * g + 4 * (lane >> 5);
             const int64_t j = j0 + wn * WTN + bj * 32 + (lane & 31);
@@ -453,7 +459,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                         // The first product of a pair is reduced and carried; the second
                         // enters the reduction unreduced (accumulator +- carried residue
                         // stays in range, see reduce_fp): 4 reductions per output and
-                        // modulus in both forms.
+                        // modulus in both forms, 3 for Karatsuba with keep_er.
                         int o[4];
                         auto acc_u = [&](int u) { return acc[bi][bj][4 * (int)g + u]; };
                         if (sgi == 0 || (!karatsuba && sgi == 2)) {
@@ -465,11 +471,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &a, const BoundArgs &b,
                             const uint32_t w = cw[bi][bj][g];
                             static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) - acc_u(u), pd, ipd); });
                             *er = pack4(o);
-                            if constexpr (karatsuba) {
+                            if constexpr (keep_er) {
+                                cr[bi][bj][g] = pack4(o);
+                            } else if constexpr (karatsuba) {
                                 static_for<4>([&](auto u) { o[u] = reduce_fp(byte_of(w, u) + acc_u(u), pd, ipd); });
                                 if constexpr (C::REG_CARRY) cw[bi][bj][g] = pack4(o);
                                 else *ei = pack4(o);
                             }
+                        } else if constexpr (keep_er) {
+                            // E'_I = mod(F - D - E) = mod(F - 2 mod(D) + E'_R), since
+                            // D + E = 2 D - (D - E): one reduction fewer than carrying mod(D + E)
+                            const uint32_t w = cw[bi][bj][g], r = cr[bi][bj][g];
+                            static_for<4>([&](auto u) {
+                                o[u] = reduce_fp(acc_u(u) - 2 * byte_of(w, u) + byte_of(r, u), pd, ipd);
+                            });
+                            *ei = pack4(o);
                         } else {
                             // Karatsuba: E'_I = mod(F - mod(D + E)); expanded: E'_I = mod(RI + IR)
                             const uint32_t w = cw[bi][bj][g];
@@ -511,30 +527,52 @@ __global__ __launch_bounds__(C::THREADS) void batch_gemm_kernel(const BatchGemm 
     // run together on an XCD are neighbours of one product and share their operand
     // panels in that XCD's L2.  A block whose queue is empty takes items from the
     // other queues.  Any dispatch order gives the same results.
+    // Per item the block needs the queue's counter and its problem's record, each a
+    // round trip to L2: the next item is claimed as soon as the current one is known
+    // (the atomic returns while this item computes), and the problem is looked up
+    // first where the previous item was (a block's items rise within a queue, and a
+    // problem has many items), with a binary search only when that misses.  Item
+    // numbers are below 2^32 (the counters are 32-bit), so the index arithmetic is
+    // 32-bit.  The counter address is offset by a zero the compiler cannot see through:
+    // for a uniform address it combines the lanes' atomics into one and reads the
+    // result back at once, which would wait for the round trip right there.
     const int64_t nchunks = items / chunk, rem = items - nchunks * chunk;
+    const uint32_t ch = (uint32_t)chunk;
     const int home = (int)(blockIdx.x % kBatchQueues);
+    int lo = 0;          // problem of the previous item
+    uint32_t ahead = 0;  // thread 0: the item claimed for the next round
+    uint32_t zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
     for (int qs = 0; qs < kBatchQueues; ++qs) {
         const int q = (home + qs) % kBatchQueues;
         const int64_t nq = (nchunks / kBatchQueues + (q < nchunks % kBatchQueues ? 1 : 0)) * chunk +
                            (nchunks % kBatchQueues == q ? rem : 0);
+        if (threadIdx.x == 0) ahead = atomicAdd(&counters[q], 1u);
         for (;;) {
-            if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(&counters[q], 1u);
+            if (threadIdx.x == 0) item_s = (int64_t)ahead;
             __syncthreads();
             const int64_t j = item_s;
             __syncthreads();
             if (j >= nq) break;
-            const int64_t w = ((j / chunk) * kBatchQueues + q) * chunk + j % chunk;
-            int lo = 0, hi = nprob - 1;  // last problem whose first item is <= w
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (probs[mid].item0 <= w) lo = mid;
-                else hi = mid - 1;
+            if (threadIdx.x == 0) ahead = atomicAdd(&counters[q] + zero, 1u);
+            const uint32_t j32 = (uint32_t)j, jc = j32 / ch;
+            const int64_t w = ((int64_t)jc * kBatchQueues + q) * ch + (j32 - jc * ch);
+            const int64_t f0 = probs[lo].item0;
+            const int64_t f1 = lo + 1 < nprob ? probs[lo + 1].item0 : items;
+            if (w < f0 || w >= f1) {  // last problem whose first item is <= w
+                int hi = w < f0 ? lo - 1 : nprob - 1;
+                lo = w < f0 ? 0 : lo + 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (probs[mid].item0 <= w) lo = mid;
+                    else hi = mid - 1;
+                }
             }
             const BatchGemm &pb = probs[lo];
-            const int64_t T = (int64_t)pb.TR * pb.TC, local = w - pb.item0;
+            const uint32_t T = (uint32_t)pb.TR * (uint32_t)pb.TC, local = (uint32_t)(w - pb.item0);
             const int lg = (int)(local / T);
-            const int64_t t = local - (int64_t)lg * T;
-            const int64_t ti = t / pb.TC, tj = t - ti * pb.TC;
+            const uint32_t t = local - (uint32_t)lg * T;
+            const int64_t ti = t / (uint32_t)pb.TC, tj = t - (uint32_t)ti * (uint32_t)pb.TC;
             GemmArgs a{pb.A, pb.B, pb.m_pad, pb.n_pad, pb.k_pad, pb.nmod, KIND == KIND_4M ? 1 : 0,
                        pb.tab, pb.eprime, nullptr, C::TM};
             const int l1 = min(pb.nmod, (lg + 1) * group);
