@@ -105,6 +105,9 @@ def test_batch_matches_oracle_and_single_calls(handle, orc, single, mode):
     handle.set_config(N, mode, "karatsuba")
     handle.set_batch_policy(tile_threshold=160, moduli_group=1, use_graph=True)
     probs = _make_batch(11 + single, 14, 1, 300, single=single)
+    probs += _make_batch(15 + single, 2, 170, 260, single=single)
+    sizes = [min(q["A"].shape[0], q["B"].shape[1]) for q in probs]
+    assert min(sizes) < 160 <= max(sizes)  # both tile sizes (128 and 256) in the batch
     dev = _upload(probs)
     handle.gemm_vbatched(dev, single=single)
     got = _download(dev)
