@@ -428,14 +428,12 @@ ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, in
         OZC_TRY(launch_fill_u64((uint64_t *)XA, (int64_t)(L.muA - L.XA) / 8, 0, s));
     } else {
         OZC_TRY(launch_fill_u64(maxA, (int64_t)(L.muA - L.maxA) / 8, 0, s));
-        OZC_TRY(launch_row_maxabs(vA, ek, maxA, s));
-        OZC_TRY(launch_row_maxabs(vB, ek, maxB, s));
+        OZC_TRY(launch_pair_scans(vA, vB, ek, maxA, maxB, sigA, sigB, false, s));
     }
     int abits;
     if (h->mode == OZC_MODE_FAST) {
         if (!pre) {
-            OZC_TRY(launch_row_sigma(vA, ek, maxA, sigA, s));
-            OZC_TRY(launch_row_sigma(vB, ek, maxB, sigB, s));
+            OZC_TRY(launch_pair_scans(vA, vB, ek, maxA, maxB, sigA, sigB, true, s));
         }
         OZC_TRY(launch_fast_exponents(cmaxA, csigA, m, L.m_pad, tab, muA, status, s));
         OZC_TRY(launch_fast_exponents(cmaxB, csigB, n, L.n_pad, tab, nuB, status, s));

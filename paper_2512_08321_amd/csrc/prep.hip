@@ -499,6 +499,35 @@ __global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const ui
                                                          uint64_t *zeros, int hc) {
     sigma_strided_body<EK, STATS>(v, maxbits, sigma, tau, zeros, blockIdx.x, blockIdx.y, hc);
 }
+// The scans of both operands of one call in one launch, blocks of A first, then those
+// of B, each on the grid its own launch would have: one ramp-up and tail per pass
+// instead of two, which shows where an operand takes tens of microseconds.  The
+// maxima and the integer sums of squares are combined by atomics, so the result does
+// not depend on the order of the blocks.
+struct ScanSide {
+    OperandView v;
+    uint64_t *maxbits, *sigma;
+    int64_t gx, blocks;  // grid columns and blocks of this operand
+    int hc;              // strided layout: k-elements per thread
+};
+template <int EK, bool SIGMA>
+__device__ __forceinline__ void scan_side(const ScanSide &sd, int64_t lb) {
+    const int64_t bx = lb % sd.gx, by = lb / sd.gx;
+    if (sd.v.contig_h) {
+        if constexpr (SIGMA) sigma_contig_body<EK, false>(sd.v, sd.maxbits, sd.sigma, nullptr, nullptr, bx, by);
+        else maxabs_contig_body<EK>(sd.v, sd.maxbits, bx, by);
+    } else {
+        if constexpr (SIGMA)
+            sigma_strided_body<EK, false>(sd.v, sd.maxbits, sd.sigma, nullptr, nullptr, bx, by, sd.hc);
+        else maxabs_strided_body<EK>(sd.v, sd.maxbits, bx, by, sd.hc);
+    }
+}
+template <int EK, bool SIGMA>
+__global__ __launch_bounds__(256) void pair_scan_kernel(ScanSide a, ScanSide b) {
+    const int64_t blk = blockIdx.x;
+    if (blk < a.blocks) scan_side<EK, SIGMA>(a, blk);
+    else scan_side<EK, SIGMA>(b, blk - a.blocks);
+}
 __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *maxbits,
                                                              const uint64_t *sigma, int64_t rows,
                                                              int64_t rows_pad, const NTable *tab,
@@ -726,6 +755,43 @@ hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbit
     if ((tau == nullptr) != (zeros == nullptr)) return hipErrorInvalidValue;
     if (tau) return row_sigma_stats<true>(v, ek, maxbits, sigma, tau, zeros, s);
     return row_sigma_stats<false>(v, ek, maxbits, sigma, nullptr, nullptr, s);
+}
+
+static ScanSide scan_side_of(const OperandView &v, uint64_t *maxbits, uint64_t *sigma) {
+    ScanSide sd{v, maxbits, sigma, 0, 0, 0};
+    if (v.rows <= 0 || v.k <= 0) return sd;  // no blocks
+    if (v.contig_h) {
+        sd.gx = (v.rows + 3) / 4;
+        sd.blocks = sd.gx * ((v.k + kHChunk - 1) / kHChunk);
+    } else {
+        sd.hc = strided_chunk(v);
+        sd.gx = (v.rows + 255) / 256;
+        sd.blocks = sd.gx * ((v.k + sd.hc - 1) / sd.hc);
+    }
+    return sd;
+}
+
+template <int EK>
+hipError_t pair_scans_ek(const ScanSide &a, const ScanSide &b, bool sigma, hipStream_t s) {
+    const int64_t blocks = a.blocks + b.blocks;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    if (sigma) hipLaunchKernelGGL((pair_scan_kernel<EK, true>), dim3((unsigned)blocks), dim3(256), 0, s, a, b);
+    else hipLaunchKernelGGL((pair_scan_kernel<EK, false>), dim3((unsigned)blocks), dim3(256), 0, s, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_scans(const OperandView &va, const OperandView &vb, int ek, uint64_t *maxA,
+                             uint64_t *maxB, uint64_t *sigA, uint64_t *sigB, bool sigma,
+                             hipStream_t s) {
+    const ScanSide a = scan_side_of(va, maxA, sigA), b = scan_side_of(vb, maxB, sigB);
+    switch (ek) {
+        case kElemZ: return pair_scans_ek<kElemZ>(a, b, sigma, s);
+        case kElemC: return pair_scans_ek<kElemC>(a, b, sigma, s);
+        case kElemD: return pair_scans_ek<kElemD>(a, b, sigma, s);
+        case kElemS: return pair_scans_ek<kElemS>(a, b, sigma, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
