@@ -169,10 +169,9 @@ ozc_status_t compute_features(ozc_context *h, bool single, ozc_op_t ta, ozc_op_t
     uint64_t *zeros = (uint64_t *)(st->stat + 24 * (size_t)(m + n));
     OZC_TRY(launch_fill_u64(mb, 3 * (m + n) + 1, 0, str));  // maxbits, sigma, tau, zeros
     const OperandView vA = view_A(A, ta, m, kf, lda), vB = view_B(B, tb, n, kf, ldb);
-    OZC_TRY(launch_row_maxabs(vA, single, mb, str));
-    OZC_TRY(launch_row_maxabs(vB, single, mb + m, str));
-    OZC_TRY(launch_row_sigma(vA, single, mb, sig, str, tau, zeros));
-    OZC_TRY(launch_row_sigma(vB, single, mb + m, sig + m, str, tau + m, zeros));
+    OZC_TRY(launch_pair_scans(vA, vB, single, mb, mb + m, sig, sig + m, false, str));
+    OZC_TRY(launch_pair_scans(vA, vB, single, mb, mb + m, sig, sig + m, true, str, tau, tau + m,
+                              zeros));
     OZC_TRY(launch_feat_reduce((const unsigned long long *)tau, (const unsigned long long *)sig, m,
                                (const unsigned long long *)(tau + m),
                                (const unsigned long long *)(sig + m), n,

@@ -85,11 +85,13 @@ __host__ __device__ constexpr bool elem_real(int ek) { return ek >= kElemD; }
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_row_maxabs(const OperandView &v, int ek, uint64_t *maxbits, hipStream_t s);
 // Both operands of one call in one launch: row maxima (sigma = false) or sums of
-// squares (sigma = true, maxima final, sigA and sigB zeroed); the same results as
-// launch_row_maxabs / launch_row_sigma on each operand.
+// squares (sigma = true, maxima final, sigA and sigB zeroed), with tauA, tauB and
+// zeros (all or none, zeroed; zeros shared) also the predictor's statistics; the same
+// results as launch_row_maxabs / launch_row_sigma on each operand.
 hipError_t launch_pair_scans(const OperandView &va, const OperandView &vb, int ek, uint64_t *maxA,
                              uint64_t *maxB, uint64_t *sigA, uint64_t *sigB, bool sigma,
-                             hipStream_t s);
+                             hipStream_t s, uint64_t *tauA = nullptr, uint64_t *tauB = nullptr,
+                             uint64_t *zeros = nullptr);
 // sigma must be zeroed.  With tau and zeros (both or neither, zeroed): also the
 // predictor's statistics tau_r = sum ceil(|x| 2^(20 - e_r)) and the zero-real count.
 hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbits,

@@ -507,26 +507,28 @@ __global__ __launch_bounds__(256) void row_sigma_strided(OperandView v, const ui
 struct ScanSide {
     OperandView v;
     uint64_t *maxbits, *sigma;
-    int64_t gx, blocks;  // grid columns and blocks of this operand
-    int hc;              // strided layout: k-elements per thread
+    uint64_t *tau, *zeros;  // pass 2: the predictor's statistics
+    int64_t gx, blocks;     // grid columns and blocks of this operand
+    int hc;                 // strided layout: k-elements per thread
 };
-template <int EK, bool SIGMA>
+// PASS 0: row maxima; 1: sums of squares; 2: sums of squares and the statistics
+template <int EK, int PASS>
 __device__ __forceinline__ void scan_side(const ScanSide &sd, int64_t lb) {
     const int64_t bx = lb % sd.gx, by = lb / sd.gx;
     if (sd.v.contig_h) {
-        if constexpr (SIGMA) sigma_contig_body<EK, false>(sd.v, sd.maxbits, sd.sigma, nullptr, nullptr, bx, by);
+        if constexpr (PASS > 0) sigma_contig_body<EK, PASS == 2>(sd.v, sd.maxbits, sd.sigma, sd.tau, sd.zeros, bx, by);
         else maxabs_contig_body<EK>(sd.v, sd.maxbits, bx, by);
     } else {
-        if constexpr (SIGMA)
-            sigma_strided_body<EK, false>(sd.v, sd.maxbits, sd.sigma, nullptr, nullptr, bx, by, sd.hc);
+        if constexpr (PASS > 0)
+            sigma_strided_body<EK, PASS == 2>(sd.v, sd.maxbits, sd.sigma, sd.tau, sd.zeros, bx, by, sd.hc);
         else maxabs_strided_body<EK>(sd.v, sd.maxbits, bx, by, sd.hc);
     }
 }
-template <int EK, bool SIGMA>
+template <int EK, int PASS>
 __global__ __launch_bounds__(256) void pair_scan_kernel(ScanSide a, ScanSide b) {
     const int64_t blk = blockIdx.x;
-    if (blk < a.blocks) scan_side<EK, SIGMA>(a, blk);
-    else scan_side<EK, SIGMA>(b, blk - a.blocks);
+    if (blk < a.blocks) scan_side<EK, PASS>(a, blk);
+    else scan_side<EK, PASS>(b, blk - a.blocks);
 }
 __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *maxbits,
                                                              const uint64_t *sigma, int64_t rows,
@@ -757,8 +759,9 @@ hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbit
     return row_sigma_stats<false>(v, ek, maxbits, sigma, nullptr, nullptr, s);
 }
 
-static ScanSide scan_side_of(const OperandView &v, uint64_t *maxbits, uint64_t *sigma) {
-    ScanSide sd{v, maxbits, sigma, 0, 0, 0};
+static ScanSide scan_side_of(const OperandView &v, uint64_t *maxbits, uint64_t *sigma,
+                             uint64_t *tau, uint64_t *zeros) {
+    ScanSide sd{v, maxbits, sigma, tau, zeros, 0, 0, 0};
     if (v.rows <= 0 || v.k <= 0) return sd;  // no blocks
     if (v.contig_h) {
         sd.gx = (v.rows + 3) / 4;
@@ -772,24 +775,31 @@ static ScanSide scan_side_of(const OperandView &v, uint64_t *maxbits, uint64_t *
 }
 
 template <int EK>
-hipError_t pair_scans_ek(const ScanSide &a, const ScanSide &b, bool sigma, hipStream_t s) {
+hipError_t pair_scans_ek(const ScanSide &a, const ScanSide &b, int pass, hipStream_t s) {
     const int64_t blocks = a.blocks + b.blocks;
     if (blocks == 0) return hipSuccess;
     if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
-    if (sigma) hipLaunchKernelGGL((pair_scan_kernel<EK, true>), dim3((unsigned)blocks), dim3(256), 0, s, a, b);
-    else hipLaunchKernelGGL((pair_scan_kernel<EK, false>), dim3((unsigned)blocks), dim3(256), 0, s, a, b);
+    const dim3 grid((unsigned)blocks);
+    if (pass == 2) hipLaunchKernelGGL((pair_scan_kernel<EK, 2>), grid, dim3(256), 0, s, a, b);
+    else if (pass == 1) hipLaunchKernelGGL((pair_scan_kernel<EK, 1>), grid, dim3(256), 0, s, a, b);
+    else hipLaunchKernelGGL((pair_scan_kernel<EK, 0>), grid, dim3(256), 0, s, a, b);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_scans(const OperandView &va, const OperandView &vb, int ek, uint64_t *maxA,
                              uint64_t *maxB, uint64_t *sigA, uint64_t *sigB, bool sigma,
-                             hipStream_t s) {
-    const ScanSide a = scan_side_of(va, maxA, sigA), b = scan_side_of(vb, maxB, sigB);
+                             hipStream_t s, uint64_t *tauA, uint64_t *tauB, uint64_t *zeros) {
+    const bool stats = tauA != nullptr;
+    if (stats != (tauB != nullptr) || stats != (zeros != nullptr) || (stats && !sigma))
+        return hipErrorInvalidValue;
+    const ScanSide a = scan_side_of(va, maxA, sigA, tauA, zeros);
+    const ScanSide b = scan_side_of(vb, maxB, sigB, tauB, zeros);
+    const int pass = stats ? 2 : (sigma ? 1 : 0);
     switch (ek) {
-        case kElemZ: return pair_scans_ek<kElemZ>(a, b, sigma, s);
-        case kElemC: return pair_scans_ek<kElemC>(a, b, sigma, s);
-        case kElemD: return pair_scans_ek<kElemD>(a, b, sigma, s);
-        case kElemS: return pair_scans_ek<kElemS>(a, b, sigma, s);
+        case kElemZ: return pair_scans_ek<kElemZ>(a, b, pass, s);
+        case kElemC: return pair_scans_ek<kElemC>(a, b, pass, s);
+        case kElemD: return pair_scans_ek<kElemD>(a, b, pass, s);
+        case kElemS: return pair_scans_ek<kElemS>(a, b, pass, s);
         default: return hipErrorInvalidValue;
     }
 }
