@@ -435,8 +435,8 @@ ozc_status_t run(ozc_context *h, int ek, ozc_op_t ta, ozc_op_t tb, int64_t m, in
         if (!pre) {
             OZC_TRY(launch_pair_scans(vA, vB, ek, maxA, maxB, sigA, sigB, true, s));
         }
-        OZC_TRY(launch_fast_exponents(cmaxA, csigA, m, L.m_pad, tab, muA, status, s));
-        OZC_TRY(launch_fast_exponents(cmaxB, csigB, n, L.n_pad, tab, nuB, status, s));
+        OZC_TRY(launch_pair_fast_exponents(cmaxA, csigA, m, L.m_pad, muA, cmaxB, csigB, n, L.n_pad,
+                                           nuB, tab, status, s));
         abits = th.max_abits_fast;
     } else {
         int8_t *barA = (int8_t *)(ws + L.barA), *barB = (int8_t *)(ws + L.barB);

@@ -100,6 +100,11 @@ hipError_t launch_row_sigma(const OperandView &v, int ek, const uint64_t *maxbit
 hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
                                  int64_t rows_pad, const NTable *tab, int16_t *mu,
                                  uint32_t *status, hipStream_t s);
+// launch_fast_exponents for op(A) (m rows) and op(B) (n columns) in one launch
+hipError_t launch_pair_fast_exponents(const uint64_t *maxA, const uint64_t *sigA, int64_t m,
+                                      int64_t m_pad, int16_t *mu, const uint64_t *maxB,
+                                      const uint64_t *sigB, int64_t n, int64_t n_pad, int16_t *nu,
+                                      const NTable *tab, uint32_t *status, hipStream_t s);
 // complex: planes Abar_R, Abar_I, Abar_R - Abar_I; real: the plane Abar
 hipError_t launch_ceil7(const OperandView &v, int ek, const uint64_t *maxbits,
                         int8_t *dst, int64_t rows_pad, int64_t k_pad, hipStream_t s);

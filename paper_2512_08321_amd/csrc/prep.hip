@@ -536,6 +536,18 @@ __global__ __launch_bounds__(256) void fast_exponents_kernel(const uint64_t *max
                                                              int16_t *mu, uint32_t *status) {
     fast_exponents_body(maxbits, sigma, rows, rows_pad, tab, mu, status, blockIdx.x);
 }
+// The exponents of both operands of one call in one launch (the blocks of A first).
+struct ExpSide {
+    const uint64_t *maxbits, *sigma;
+    int64_t rows, rows_pad, blocks;
+    int16_t *mu;
+};
+__global__ __launch_bounds__(256) void pair_fast_exponents_kernel(ExpSide a, ExpSide b,
+                                                                  const NTable *tab, uint32_t *status) {
+    const int64_t blk = blockIdx.x;
+    if (blk < a.blocks) fast_exponents_body(a.maxbits, a.sigma, a.rows, a.rows_pad, tab, a.mu, status, blk);
+    else fast_exponents_body(b.maxbits, b.sigma, b.rows, b.rows_pad, tab, b.mu, status, blk - a.blocks);
+}
 template <int EK, bool CONTIG_H, int NPLANES, int W>
 __global__ __launch_bounds__(256) void split_kernel(OperandView v, const int16_t *__restrict__ mu,
                                                     const NTable *__restrict__ tab, int nmod,
@@ -802,6 +814,20 @@ hipError_t launch_pair_scans(const OperandView &va, const OperandView &vb, int e
         case kElemS: return pair_scans_ek<kElemS>(a, b, pass, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pair_fast_exponents(const uint64_t *maxA, const uint64_t *sigA, int64_t m,
+                                      int64_t m_pad, int16_t *mu, const uint64_t *maxB,
+                                      const uint64_t *sigB, int64_t n, int64_t n_pad, int16_t *nu,
+                                      const NTable *tab, uint32_t *status, hipStream_t s) {
+    const ExpSide a{maxA, sigA, m, m_pad, m_pad > 0 ? (m_pad + 255) / 256 : 0, mu};
+    const ExpSide b{maxB, sigB, n, n_pad, n_pad > 0 ? (n_pad + 255) / 256 : 0, nu};
+    const int64_t blocks = a.blocks + b.blocks;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(pair_fast_exponents_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, tab,
+                       status);
+    return hipGetLastError();
 }
 
 hipError_t launch_fast_exponents(const uint64_t *maxbits, const uint64_t *sigma, int64_t rows,
