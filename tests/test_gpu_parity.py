@@ -4,6 +4,8 @@ Bar: exponents, residues, INT32 products and E' bit-exact; outputs bit-exact
 (the reconstruction is exact on both sides, and alpha/beta follow the same
 fused multiply-add order).  NaN outputs compare as NaN.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -240,10 +242,11 @@ def _random_case(i):
     return m, n, k, single, N, mode, algo, ta, tb, phi, pads
 
 
-@pytest.mark.parametrize("i", range(40))
+@pytest.mark.parametrize("i", range(int(os.environ.get("OZC_RANDOM_CASES", "200"))))
 def test_randomized_configurations(handle, orc, i):
     """Seeded random shapes (1..400, tile edges +-1), moduli counts, modes, product forms,
-    op() forms, value spreads, precisions and leading-dimension padding."""
+    op() forms, value spreads, precisions and leading-dimension padding (200 cases; the
+    environment variable OZC_RANDOM_CASES runs more)."""
     m, n, k, single, N, mode, algo, ta, tb, phi, (pa, pb) = _random_case(i)
     dt = np.complex64 if single else np.complex128
     A = workloads.complex_matrix(m, k, phi, 8000 + 2 * i, dtype=dt)
