@@ -6,6 +6,7 @@ schedule (tile threshold, moduli group, graph or not); graph replays equal to
 the eager result with other GPU work in between.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -136,6 +137,37 @@ def test_schedule_invariance(handle):
         results.append(_download(dev))
     for r in results[1:]:
         assert all(_same(a, b) for a, b in zip(results[0], r))
+
+
+@pytest.mark.parametrize("i", range(int(os.environ.get("OZC_RANDOM_BATCHES", "24"))))
+def test_randomized_batches(handle, orc, i):
+    """Seeded random batches (1..20 problems of 1..320, both precisions and modes, both
+    product forms, tile thresholds that put problems on either tile size, moduli groups,
+    graph or not) bit-exact with the oracle problem by problem (24 batches; the
+    environment variable OZC_RANDOM_BATCHES runs more)."""
+    rng = np.random.default_rng(9100 + i)
+    single = bool(rng.random() < 0.4)
+    mode = str(rng.choice(["fast", "accurate"]))
+    algo = str(rng.choice(["karatsuba", "4m"]))
+    N = int(rng.integers(6, 13)) if single else int(rng.integers(10, 21))
+    thr = int(rng.choice([64, 128, 160, 256, 1024]))
+    grp = int(rng.choice([1, 2, 3, N]))
+    graph = bool(rng.random() < 0.5)
+    count = int(rng.integers(1, 21))
+    print(f"random batch {i}: single={single} mode={mode} algo={algo} N={N} thr={thr} "
+          f"group={grp} graph={graph} count={count}", flush=True)
+    handle.set_config(N, mode, algo)
+    handle.set_batch_policy(tile_threshold=thr, moduli_group=grp, use_graph=graph)
+    probs = _make_batch(9200 + i, count, 1, 320, single=single)
+    dev = _upload(probs)
+    handle.gemm_vbatched(dev, single=single)
+    got = _download(dev)
+    for p, q in enumerate(probs):
+        ref = orc.emulate(q["A"], q["B"], N, mode, algo=algo, alpha=q["alpha"], beta=q["beta"],
+                          C=q["C"], single=single)["out"]
+        assert _same(got[p], ref), p
+    handle.set_batch_policy(tile_threshold=1024, moduli_group=1, use_graph=True)
+    handle.set_config(14, "fast", "karatsuba")
 
 
 def test_expanded_algorithm_batch(handle, orc):
